@@ -1,0 +1,416 @@
+"""Pins of the CPU oracle against values fixed by the paper and by mathematics.
+
+Each test targets a plausible mistake in the oracle: a wrong Philox round, a
+dropped Klein-Nishina term, a wrong sign in the free-flight or score, a
+transposed index in the geometry, a parity slip in localization.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from workloads import configs as C
+from workloads import meshgen as mg
+from workloads import xsgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MEC2 = 510.99895
+
+
+def _sigma_ok(x, expect, sigma, k=3.0):
+    return abs(x - expect) <= k * sigma
+
+
+# --------------------------------------------------------------------------
+# Philox
+
+def test_philox_known_answers(orc):
+    rows = 0
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(x, 16) for x in line.split()]
+            assert orc.philox(w[0:4], w[4:6]) == w[6:10]
+            rows += 1
+    assert rows == 3
+
+
+def test_philox_bytes_uniform(orc):
+    # chi^2 of byte frequencies over 40k outputs (160 kB)
+    counts = np.zeros(256)
+    for i in range(10000):
+        for x in orc.philox([i, 7, 0, 3], [0x1234, 0x5678]):
+            for s in (0, 8, 16, 24):
+                counts[(x >> s) & 0xFF] += 1
+    e = counts.sum() / 256
+    chi2 = ((counts - e) ** 2 / e).sum()
+    # 255 dof: mean 255, sd ~22.6; p < 1e-4 beyond ~350
+    assert 170 < chi2 < 350
+
+
+# --------------------------------------------------------------------------
+# Klein-Nishina / Thomson
+
+@pytest.mark.parametrize("E", [1.0, 40.0, 100.0, 661.7, 1332.49, 3000.0])
+def test_kn_total_matches_textbook(orc, E):
+    k = E / MEC2
+    assert orc.kn_sigma(k) == pytest.approx(float(xsgen.sigma_kn(E)), rel=1e-9)
+
+
+def test_kn_value_at_cs137(orc):
+    # sigma_KN(661.7 keV) = 0.25619 b per electron
+    assert orc.kn_sigma(661.7 / MEC2) / 1e-24 == pytest.approx(0.25619, abs=5e-6)
+
+
+def _kn_density(eps, k):
+    # d sigma/d eps up to a constant: (1/eps + eps)(1 - eps sin^2/(1 + eps^2))
+    ct = 1.0 - (1.0 / eps - 1.0) / k
+    s2 = 1.0 - ct * ct
+    return (1.0 / eps + eps) * (1.0 - eps * s2 / (1.0 + eps * eps))
+
+
+@pytest.mark.parametrize("E", [40.0, 661.7, 2000.0])
+def test_kn_sampler_histogram(orc, E):
+    from scipy import integrate
+    k = E / MEC2
+    e0 = 1.0 / (1.0 + 2.0 * k)
+    n = 40000
+    rng = np.random.default_rng(5)
+    eps = np.array([orc.kn_sample(k, u) for u in rng.random(n)])
+    assert eps.min() >= e0 - 1e-12 and eps.max() <= 1.0 + 1e-12
+    edges = np.linspace(e0, 1.0, 31)
+    obs, _ = np.histogram(eps, edges)
+    w = np.array([integrate.quad(_kn_density, a, b, args=(k,))[0] for a, b in zip(edges[:-1], edges[1:])])
+    exp = n * w / w.sum()
+    chi2 = ((obs - exp) ** 2 / exp).sum()
+    assert chi2 < 70  # 29 dof, p ~ 5e-5
+
+
+def test_compton_edge(orc):
+    # T_max = E 2k/(1+2k) = 477.374 keV at 661.7 keV
+    E = 661.7
+    k = E / MEC2
+    eps_min = orc.kn_sample(k, 1e-15)
+    assert E * (1 - eps_min) == pytest.approx(477.374, abs=2e-3)
+    assert E * 2 * k / (1 + 2 * k) == pytest.approx(477.374, abs=1e-3)
+
+
+def test_thomson_sampler(orc):
+    n = 40000
+    rng = np.random.default_rng(6)
+    mu = np.array([orc.thomson_sample(u) for u in rng.random(n)])
+    edges = np.linspace(-1, 1, 21)
+    obs, _ = np.histogram(mu, edges)
+    cdf = lambda x: (x ** 3 + 3 * x + 4) / 8
+    exp = n * (cdf(edges[1:]) - cdf(edges[:-1]))
+    assert ((obs - exp) ** 2 / exp).sum() < 55  # 19 dof
+    assert orc.thomson_sample(0.5) == pytest.approx(0.0, abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# synthetic cross-section recipe
+
+def test_xs_table_magnitudes():
+    pe, c, coh = xsgen.mass_attenuation({"Ge": 1.0}, np.array([100.0, 661.7]))
+    assert pe[0] == pytest.approx(0.3999, abs=2e-4)
+    assert c[0] == pytest.approx(0.1307, abs=2e-4)
+    assert c[1] == pytest.approx(0.06798, abs=2e-5)
+    # K edge of Ge: photo drops by 7.5 just below 11.103 keV
+    lo, hi = xsgen.mass_attenuation({"Ge": 1.0}, np.array([11.102, 11.103]))[0]
+    assert hi / lo == pytest.approx(7.5 * (11.102 / 11.103) ** 3, rel=1e-9)
+
+
+def test_oracle_interpolation_at_grid_points(orc):
+    w = C.c1_bare()
+    s = orc.scene_from_workload(w)
+    lnE0, dlnE, n = w.grid
+    pe, c, _ = w.tables[1]
+    rho = float(np.float32(5.32))  # region densities travel as float32
+    for k in (0, 100, 511, 1022):
+        E = math.exp(lnE0 + k * dlnE)
+        mu = s.mu(1, E)
+        assert mu[0] == pytest.approx(0.1 * rho * pe[k], rel=1e-12)
+        assert mu[1] == pytest.approx(0.1 * rho * c[k], rel=1e-12)
+    # between grid points: log-log (geometric) interpolation
+    E = math.exp(lnE0 + 100.5 * dlnE)
+    assert s.mu(1, E)[1] == pytest.approx(0.1 * rho * math.sqrt(c[100] * c[101]), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# geometry
+
+def test_bvh_matches_brute_force(orc):
+    w = C.c2_hpge(n_seg=32, n_phi=4)
+    sc = w.scene
+    a = orc.Scene(sc.xyz, sc.tri, sc.tri_region, sc.n_regions, use_bvh=True)
+    b = orc.Scene(sc.xyz, sc.tri, sc.tri_region, sc.n_regions, use_bvh=False)
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        o = rng.uniform([-45, -45, -110], [45, 45, 20])
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        ta, fa = a.closest_hit(o, d)
+        tb, fb = b.closest_hit(o, d)
+        assert fa == fb and ta == tb
+        assert a.locate(o) == b.locate(o)
+
+
+def test_closest_hit_plane_distance(orc):
+    scene, mats, tabs, grid = C.slab(5.0, 1.0)
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    o = np.array([0.1234, 0.4321, 10.0])
+    d = np.array([0.3, -0.2, -1.0])
+    d /= np.linalg.norm(d)
+    t, f = s.closest_hit(o, d)
+    assert t == pytest.approx(10.0 / abs(d[2]), rel=1e-14)
+    t2, f2 = s.closest_hit(o + t * d, d, exclude=f)
+    assert t2 == pytest.approx(5.0 / abs(d[2]), rel=1e-12)
+
+
+def test_locate_nested_spheres(orc):
+    radii = (10.0, 20.0, 30.0)
+    sc = C.nested_spheres(radii)
+    s = orc.Scene(sc.xyz, sc.tri, sc.tri_region, sc.n_regions)
+    rng = np.random.default_rng(12)
+    checked = 0
+    for _ in range(400):
+        p = rng.uniform(-35, 35, size=3)
+        r = np.linalg.norm(p)
+        if min(abs(r - R) for R in radii) < 0.05 * 30:
+            continue
+        expect = 0
+        # region ids: outermost sphere added first => region 1 = radius 30
+        for rid, R in enumerate(sorted(radii, reverse=True), start=1):
+            if r < R:
+                expect = rid
+        assert s.locate(p) == expect
+        checked += 1
+    assert checked > 200
+
+
+def test_locate_hpge_regions(orc):
+    w = C.c2_hpge(n_seg=64, n_phi=8)
+    s = orc.scene_from_workload(w)
+    sc = w.scene
+    probes = {
+        "world": (0, 0, 600), "air": (0, 0, 100), "endcap": (37.5, 0, -50),
+        "window": (0, 0, 5.25), "interior": (0, 0, 2.0), "cup": (33.0, 0, -30),
+        "dead": (0, 0, -0.3), "active": (20, 0, -30), "bore": (3.0, 0, -40),
+        "pin": (0, 0, -40), "coldfinger": (0, 0, -80),
+    }
+    for name, p in probes.items():
+        assert s.locate(np.array(p, float)) == sc.region_id(name), name
+
+
+# --------------------------------------------------------------------------
+# mesh generator (Eq. 1-6)
+
+def test_generator_vertices_follow_eq1_to_eq4():
+    N, R = 64, 30.0
+    shell = mg.cylinder(R, -60, 0, N)
+    th = np.arctan2(shell.V[:, 1], shell.V[:, 0])
+    ring = shell.V[np.abs(np.hypot(shell.V[:, 0], shell.V[:, 1]) - R) < 1e-9]
+    assert len(ring) == 2 * N
+    i = np.round(np.mod(np.arctan2(ring[:, 1], ring[:, 0]), 2 * np.pi) / (2 * np.pi / N)).astype(int) % N
+    assert np.allclose(ring[:, 0], R * np.cos(2 * np.pi * i / N), atol=1e-12)
+    assert np.allclose(ring[:, 1], R * np.sin(2 * np.pi * i / N), atol=1e-12)
+    # rounded edge: every arc vertex sits on the torus (rho - (R-Rc))^2 + (z - (z1-Rc))^2 = Rc^2
+    Rr, Rc, z1 = 32.0, 3.0, 0.0
+    sh = mg.rounded_cylinder(Rr, -60, z1, Rc, 128, 20)
+    rho = np.hypot(sh.V[:, 0], sh.V[:, 1])
+    arc = (sh.V[:, 2] >= z1 - Rc - 1e-12) & (rho > Rr - Rc - 1e-9)
+    d = np.hypot(rho[arc] - (Rr - Rc), sh.V[arc, 2] - (z1 - Rc))
+    assert np.allclose(d, Rc, atol=1e-12)
+    zs = np.unique(np.round(sh.V[arc, 2], 12))
+    phis = np.sort(np.arcsin(np.clip((zs - (z1 - Rc)) / Rc, -1, 1)))
+    assert np.allclose(phis, 0.5 * np.pi * np.arange(21) / 20, atol=1e-9)
+
+
+def test_generator_signed_volume_and_euler():
+    N, r, h = 64, 30.0, 60.0
+    sh = mg.cylinder(r, -60, 0, N)
+    exact = 0.5 * N * r * r * math.sin(2 * math.pi / N) * h
+    assert mg.signed_volume(sh.V, sh.F) == pytest.approx(exact, rel=1e-12)
+    assert exact == pytest.approx(169373.6185, abs=1e-4)
+    for s in (mg.rounded_cylinder(32, -60, 0, 3, 128, 20), mg.capsule_top(5, -60, -15, 64, 10),
+              mg.cup(33.5, 32.5, -62, -1, 1, 64), mg.inverted_cup(70, 40, -60, 27.5, 20, 64),
+              mg.box((-1, -1, -1), (1, 1, 1)), mg.uv_sphere(10, 24, 12)):
+        assert mg.euler_characteristic(s.F) == 2
+        assert mg.signed_volume(s.V, s.F) > 0
+    # cup volume = outer prism - cavity prism (both inscribed N-gons)
+    a = lambda rr: 0.5 * 64 * rr * rr * math.sin(2 * math.pi / 64)
+    cupv = mg.signed_volume(*astuple(mg.cup(33.5, 32.5, -62, -1, 1, 64)))
+    assert cupv == pytest.approx(a(33.5) * 61 - a(32.5) * 60, rel=1e-12)
+
+
+def astuple(s):
+    return s.V, s.F
+
+
+def test_c1_has_256_facets_and_c2_about_20k():
+    assert len(C.c1_bare().scene.tri) == 256
+    n = len(C.c2_hpge(n_histories=1).scene.tri)
+    assert 19000 < n < 21500
+
+
+# --------------------------------------------------------------------------
+# transport closed forms
+
+def _slab_scene(orc, T, photo, compton=0.0, coherent=0.0, active=True):
+    scene, mats, tabs, grid = C.slab(T, photo, compton, coherent, active=active)
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    s.set_region(0, 0, 0.0)
+    s.set_region(1, 1, 1.0, 0, active)
+    for m, (a, b, c) in tabs.items():
+        s.set_xs(m, grid, a, b, c)
+    return s
+
+
+BEAM = C.Source(C.KIND_BEAM, pos=(0.1234, 0.4321, 10.0), direction=(0.0, 0.0, -1.0))
+
+
+def test_slab_photo_only_fepe(orc):
+    # pencil beam on a photo-only ACTIVE slab: FEPE = 1 - exp(-mu t)
+    s = _slab_scene(orc, 5.0, 2.0)  # mu = 0.2 /mm, mu t = 1
+    r = s.run(BEAM, 661.7, 400_000, 2101, scales=[1.0])
+    assert _sigma_ok(r.fepe(), 1 - math.exp(-1.0), r.fepe_sigma())
+    assert r.tally.n_fep + r.tally.n_escape == r.tally.n_histories
+    assert r.tally.n_balance_fail == 0 and r.tally.n_lost == 0
+
+
+def test_slab_uncollided_transmission(orc):
+    # full physics: uncollided escape fraction = exp(-mu_tot t)
+    s = _slab_scene(orc, 5.0, 0.5, 1.0, 0.3)  # mu_tot = 0.18 /mm
+    n = 300_000
+    r = s.run(BEAM, 300.0, n, 2102)
+    p = r.tally.n_uncollided / n
+    ex = math.exp(-0.18 * 5.0)
+    assert _sigma_ok(p, ex, math.sqrt(ex * (1 - ex) / n))
+    assert r.tally.n_balance_fail == 0
+
+
+def test_slab_density_scale_enters_attenuation(orc):
+    s = _slab_scene(orc, 5.0, 2.0)
+    r = s.run(BEAM, 661.7, 300_000, 2103, scales=[1.7])
+    assert _sigma_ok(r.fepe(), 1 - math.exp(-1.7), r.fepe_sigma())
+
+
+@pytest.mark.parametrize("scale", [1.0, 1.3])
+def test_slab_gradient_closed_form(orc, scale):
+    # dFEPE/ds = mu t exp(-s mu t) for the photo-only slab
+    s = _slab_scene(orc, 5.0, 2.0)
+    r = s.run(BEAM, 661.7, 400_000, 2104, scales=[scale])
+    g, gs = r.grad(1)[0], r.grad_sigma(1)[0]
+    assert _sigma_ok(g, 1.0 * math.exp(-scale * 1.0), gs)
+    # score has zero mean over all histories; |score| <= s mu t here
+    assert abs(r.tally.sum_score[0] / r.n) < 3 * 1.3 / math.sqrt(r.n)
+
+
+def test_slab_gradient_matches_crn_finite_difference(orc):
+    s = _slab_scene(orc, 5.0, 1.0, 1.0)  # photo + Compton
+    n, h = 300_000, 0.01
+    up = s.run(BEAM, 200.0, n, 2105, scales=[1 + h])
+    dn = s.run(BEAM, 200.0, n, 2105, scales=[1 - h])
+    fd = (up.fepe() - dn.fepe()) / (2 * h)
+    r = s.run(BEAM, 200.0, n, 2105, scales=[1.0])
+    g, gs = r.grad(1)[0], r.grad_sigma(1)[0]
+    assert abs(g - fd) <= max(0.02 * abs(fd), 3 * gs)
+
+
+def test_black_absorber_solid_angle(orc):
+    # photo-only, mu = 5320/mm cylinder; isotropic point on axis at d = 100:
+    # FEPE = Omega/4pi of the faceted front face (Van Oosterom-Strackee).
+    b = C.bare_crystal(64)
+    scene = b.build()
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    s.set_region(0, 0, 0.0)
+    s.set_region(1, 1, 5.32, 0, True)
+    n = xsgen.GRID_N
+    lnE0, dlnE, _ = xsgen.grid()
+    s.set_xs(0, (lnE0, dlnE, n), *xsgen.constant_table(n=n))
+    s.set_xs(1, (lnE0, dlnE, n), *xsgen.constant_table(1e4, 0, 0, n=n))
+    src = C.Source(C.KIND_POINT, pos=(0.0, 0.0, 100.0))
+    # exact faceted solid angle from the top-cap fan
+    V = scene.xyz.astype(np.float64)
+    F = scene.tri
+    top = [f for f in F if np.all(np.abs(V[f][:, 2]) < 1e-9)]
+    P = np.array([0, 0, 100.0])
+    om = 0.0
+    for f in top:
+        R1, R2, R3 = V[f[0]] - P, V[f[2]] - P, V[f[1]] - P  # as seen from the source
+        num = np.dot(R1, np.cross(R2, R3))
+        l1, l2, l3 = map(np.linalg.norm, (R1, R2, R3))
+        den = l1 * l2 * l3 + np.dot(R1, R2) * l3 + np.dot(R1, R3) * l2 + np.dot(R2, R3) * l1
+        om += 2 * math.atan2(num, den)
+    frac = abs(om) / (4 * math.pi)
+    assert frac == pytest.approx(0.0210551, abs=2e-7)
+    disk = 0.5 * (1 - 100 / math.hypot(100, 30))
+    assert disk == pytest.approx(0.021087, abs=1e-6)
+    r = s.run(src, 661.7, 4_000_000, 2106)
+    assert _sigma_ok(r.fepe(), frac, r.fepe_sigma())
+
+
+def test_infinite_medium_absorbs_everything(orc):
+    sh = mg.uv_sphere(1000.0, 48, 24)
+    b = mg.SceneBuilder("vacuum", 0.0)
+    b.add("ge", "Ge", 5.32, sh, group=0, active=True)
+    scene = b.build()
+    w = C.Workload("sphere", scene, ["vacuum", "Ge"], C._tables_for(["vacuum", "Ge"])[0],
+                   xsgen.grid(), C.Source(C.KIND_POINT, pos=(0.0, 0.0, 0.0)), [661.7], 20000, 1)
+    s = orc.scene_from_workload(w)
+    r = s.run(w.source, 661.7, 20000, 2107)
+    assert r.tally.n_fep == r.tally.n_histories
+    assert r.tally.edep_total == pytest.approx(20000 * 661.7, rel=1e-12)
+    assert r.tally.n_compton > 20000  # most histories scatter before absorption
+
+
+def test_energy_conservation_full_detector(orc):
+    w = C.c2_hpge(n_seg=64, n_phi=8, distance=20.0)
+    s = orc.scene_from_workload(w)
+    for E in (40.0, 661.7, 2000.0):
+        r = s.run(w.source, E, 100_000, 2108, n_channels=8192, channel_keV=0.25)
+        t = r.tally
+        assert t.n_balance_fail == 0 and t.n_lost == 0 and t.n_killed == 0
+        assert t.edep_total + t.e_escape == pytest.approx(t.n_histories * E, rel=1e-12)
+        assert t.n_absorbed + t.n_escape == t.n_histories
+        # FEP histories land in the channel holding E
+        assert r.spectrum[int(E / 0.25)] >= t.n_fep
+        assert t.n_fep <= t.n_absorbed
+
+
+def test_thin_photo_slab_spectrum_is_single_line(orc):
+    s = _slab_scene(orc, 0.5, 2.0)
+    r = s.run(BEAM, 100.0, 50_000, 2109, n_channels=1024, channel_keV=0.25)
+    assert r.spectrum.sum() == r.tally.n_fep > 0
+    assert r.spectrum[400] == r.tally.n_fep
+
+
+def test_determinism_and_thread_invariance(orc):
+    w = C.c1_bare()
+    s = orc.scene_from_workload(w)
+    a = s.run(w.source, 661.7, 50_000, 2110, n_channels=256, channel_keV=4.0, threads=1)
+    b = s.run(w.source, 661.7, 50_000, 2110, n_channels=256, channel_keV=4.0, threads=7)
+    for f in ("n_fep", "n_absorbed", "n_segments", "n_compton"):
+        assert getattr(a.tally, f) == getattr(b.tally, f)
+    assert np.array_equal(a.spectrum, b.spectrum)
+    # disjoint history ranges add up
+    c = s.run(w.source, 661.7, 20_000, 2110, first=0, threads=3)
+    d = s.run(w.source, 661.7, 30_000, 2110, first=20_000, threads=2)
+    assert c.tally.n_fep + d.tally.n_fep == a.tally.n_fep
+
+
+def test_broadening_moments(orc):
+    n, w = 8192, 0.25
+    spec = np.zeros(n)
+    spec[4000] = 1000.0
+    out = orc.broaden(spec, w, 0.64, 0.0018)
+    Ec = 4000.5 * w
+    sigma = math.sqrt(0.64 + 0.0018 * Ec) / (2 * math.sqrt(2 * math.log(2)))
+    centres = (np.arange(n) + 0.5) * w
+    assert out.sum() == pytest.approx(1000.0, rel=1e-5)
+    assert (out * centres).sum() / out.sum() == pytest.approx(Ec, abs=1e-9)
+    var = (out * (centres - Ec) ** 2).sum() / out.sum()
+    # channel-integrated Gaussian: variance sigma^2 + w^2/12 (Sheppard)
+    assert var == pytest.approx(sigma * sigma + w * w / 12, rel=2e-3)
