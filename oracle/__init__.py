@@ -66,7 +66,7 @@ def lib():
         L.orc_locate.argtypes = [C.c_void_p, dp]
         L.orc_closest_hit.restype = C.c_int32
         L.orc_closest_hit.argtypes = [C.c_void_p, dp, dp, C.c_int64, dp, C.POINTER(C.c_int64)]
-        L.orc_mu.argtypes = [C.c_void_p, C.c_int32, C.c_double, dp, dp]
+        L.orc_mu.argtypes = [C.c_void_p, C.c_int32, C.c_double, dp, C.c_int32, dp]
         for f in ("orc_kn_integral", "orc_kn_sigma", "orc_kn_sample", "orc_thomson_sample"):
             getattr(L, f).restype = C.c_double
         L.orc_kn_integral.argtypes = [C.c_double, C.c_double]
@@ -192,7 +192,8 @@ class Scene:
     def mu(self, region, E, scales=None):
         out = np.zeros(3)
         sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float64)
-        lib().orc_mu(self.h, region, E, None if sc is None else _dp(sc), _dp(out))
+        lib().orc_mu(self.h, region, E, None if sc is None else _dp(sc),
+                     0 if sc is None else len(sc), _dp(out))
         return out
 
     def run(self, source, E0, n, seed, unit=0, first=0, scales=None, n_channels=0,

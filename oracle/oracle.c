@@ -283,11 +283,12 @@ static void mass_atten(const orc_scene* s, int32_t m, double E, double out[3]) {
   }
 }
 
-void orc_mu(const orc_scene* s, int32_t r, double E, const double* scales, double out[3]) {
+void orc_mu(const orc_scene* s, int32_t r, double E, const double* scales, int32_t n_scales,
+            double out[3]) {
   double mr[3];
   mass_atten(s, s->mat[r], E, mr);
   double f = 0.1 * s->rho[r];
-  if (scales && s->grp[r] >= 0) f *= scales[s->grp[r]];
+  if (scales && s->grp[r] >= 0 && s->grp[r] < n_scales) f *= scales[s->grp[r]];
   for (int i = 0; i < 3; ++i) out[i] = f * mr[i];
 }
 
@@ -664,13 +665,13 @@ static void one_history(worker* w, int64_t h) {
     }
     T->n_segments++;
     double mu3[3];
-    orc_mu(s, region, E, w->scales, mu3);
+    orc_mu(s, region, E, w->scales, w->ngroups, mu3);
     double mu = mu3[0] + mu3[1] + mu3[2];
     int32_t gidx = s->grp[region];
     double mu0 = 0.0; /* unscaled total attenuation of the region */
     if (gidx >= 0 && gidx < w->ngroups) {
       double m0[3];
-      orc_mu(s, region, E, NULL, m0);
+      orc_mu(s, region, E, NULL, 0, m0);
       mu0 = m0[0] + m0[1] + m0[2];
     }
     double th;

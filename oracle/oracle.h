@@ -58,8 +58,10 @@ int32_t orc_locate(const orc_scene* s, const double p[3]);
  * Returns 1 and fills t, tri on a hit, else 0. */
 int32_t orc_closest_hit(const orc_scene* s, const double o[3], const double d[3],
                         int64_t exclude, double* t, int64_t* tri);
-/* Linear attenuation coefficients [1/mm] (photo, compton, coherent) of region r at E. */
-void orc_mu(const orc_scene* s, int32_t region, double E, const double* scales, double out[3]);
+/* Linear attenuation coefficients [1/mm] (photo, compton, coherent) of region r at E;
+ * scales[n_scales] multiply regions whose group is below n_scales. */
+void orc_mu(const orc_scene* s, int32_t region, double E, const double* scales, int32_t n_scales,
+            double out[3]);
 
 /* Klein-Nishina pieces: k = E / m_e c^2, eps = E'/E. */
 double orc_kn_integral(double k, double eps);    /* antiderivative of the bracket */

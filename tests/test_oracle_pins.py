@@ -375,8 +375,10 @@ def test_energy_conservation_full_detector(orc):
         assert t.n_balance_fail == 0 and t.n_lost == 0 and t.n_killed == 0
         assert t.edep_total + t.e_escape == pytest.approx(t.n_histories * E, rel=1e-12)
         assert t.n_absorbed + t.n_escape == t.n_histories
-        # FEP histories land in the channel holding E
-        assert r.spectrum[int(E / 0.25)] >= t.n_fep
+        # FEP histories land in the channel holding E (or the one below when E
+        # sits on a channel edge and the deposits sum to E minus rounding)
+        c = int(E / 0.25)
+        assert r.spectrum[c - 1:c + 1].sum() >= t.n_fep
         assert t.n_fep <= t.n_absorbed
 
 
@@ -414,3 +416,17 @@ def test_broadening_moments(orc):
     var = (out * (centres - Ec) ** 2).sum() / out.sum()
     # channel-integrated Gaussian: variance sigma^2 + w^2/12 (Sheppard)
     assert var == pytest.approx(sigma * sigma + w * w / 12, rel=2e-3)
+
+
+def test_scales_apply_only_to_listed_groups(orc):
+    # a region whose group has no scale passed is transported at density 1
+    w = C.c2_hpge(n_seg=32, n_phi=4)
+    s = orc.scene_from_workload(w)
+    cup = w.scene.region_id("cup")  # group 4
+    base = s.mu(cup, 100.0)
+    assert np.isfinite(base).all() and base.sum() > 0
+    assert np.array_equal(s.mu(cup, 100.0, scales=[2.0]), base)
+    scaled = s.mu(cup, 100.0, scales=[1.0, 1.0, 1.0, 1.0, 2.0])
+    assert np.allclose(scaled, 2.0 * base, rtol=1e-15)
+    dead = w.scene.region_id("dead")  # group 0
+    assert np.allclose(s.mu(dead, 100.0, scales=[3.0]), 3.0 * s.mu(dead, 100.0), rtol=1e-15)
