@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark: histories/s on the ~20k-facet synthetic HPGe detector.
+
+Workload: p-type coaxial HPGe detector (crystal r 32 mm, h 60 mm, 5 mm bore,
+0.7 mm dead layer, Al cup / end-cap / window), 20236 facets, in an air box;
+isotropic point source 250 mm above the end-cap; 12 log-spaced energies
+40-2000 keV; per energy N_e = max(1e8, histories for a 0.5 % FEPE relative
+standard error, from a 1e7-history pilot).  One step = one persistent
+launch transporting all 12 x N_e histories (inputs already resident on the
+GPU).  Also reported: the same step with score-function gradients for the
+five detector density groups (fwd+grad / fwd cost), the ALU roofline of the
+transport kernel and the CPU oracle on a bounded sample.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU lane-operations per event of the method, counted from its
+# arithmetic (one FP32/INT32 operation = 1; a transcendental, which issues at
+# quarter rate on the vector ALU, = 4).  The derivation of each figure is given
+# with the roofline discussion of the design notes.
+OPS_PER_EVENT = {
+    "rng_calls": 116,    # Philox4x32-10: 10 x (2 mul_lo + 2 mul_hi + 4 xor + 2 add), + 4 uniforms
+    "emissions": 35,     # isotropic direction, -ln u, energy-grid index
+    "segments": 76,      # 3 log-log partials (3 exp), 1/mu, ray set-up (3 rcp, shear), move
+    "node_visits": 36,   # two slab tests (12 FMA, 12 min/max) + near/far order + stack
+    "tri_tests": 40,     # watertight test: 9 sub, 6 shear FMA, 3 edge fns, signs, det, T
+    "photo": 8,
+    "compton": 100,      # Butcher-Messel sampling (~1.3 trials), deposit, rotation, re-index
+    "coherent": 70,      # Cardano inverse of the Thomson CDF, rotation
+    "crossings": 10,     # region update, tau update, bookkeeping
+    "locates": 40,       # probe-ray set-up (its traversal is in node_visits/tri_tests)
+}
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz one-lane-op slots per second
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--min-histories", type=float, default=1e8, help="per energy")
+    ap.add_argument("--pilot", type=float, default=1e7)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, target_s):
+    """The oracle on the host cores, on a bounded sample of the same workload."""
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    s = oracle.scene_from_workload(w)
+    # calibrate, then run about target_s seconds spread over all energies
+    t0 = time.perf_counter()
+    for k, E in enumerate(w.energies):
+        s.run(w.source, E, 20_000, 2002, unit=k, threads=threads)
+    t_cal = time.perf_counter() - t0
+    per_e = max(20_000, int(20_000 * target_s / max(t_cal, 1e-3)))
+    t0 = time.perf_counter()
+    n = 0
+    for k, E in enumerate(w.energies):
+        r = s.run(w.source, E, per_e, 2002, unit=k, threads=threads)
+        n += r.tally.n_histories
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"{per_e} histories at each of the {len(w.energies)} energies "
+                      f"({n} total, {dt:.1f} s), same detector and source"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
+              "the path shards over independent histories, see the design notes", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2605_25963_amd import gadep
+    from workloads import configs as C
+
+    w = C.c2_hpge(n_histories=0)
+    stream = torch.cuda.current_stream()
+    ctx = gadep.Context(0, stream if stream.cuda_stream else None)
+    gadep.load_workload(ctx, w)
+    n_groups = len(w.groups)
+
+    def jobs(n_per_e, grad=False):
+        return [dict(source=w.source, energies=[E], n_histories=int(n_per_e[k]), stream=k,
+                     scales=[1.0] * n_groups if grad else None) for k, E in enumerate(w.energies)]
+
+    # pilot: FEPE estimate per energy to size N_e for 0.5 % RSE
+    pilot = ctx.run_batch(jobs([a.pilot] * len(w.energies)), 999)
+    p = np.maximum(pilot.fepe(), 1e-12)
+    need = np.ceil((1 - p) / (p * 0.005 ** 2))
+    n_e = np.maximum(a.min_histories, need).astype(np.int64)
+    total = int(n_e.sum())
+    J = jobs(n_e)
+
+    def step(grad=False, seed=1002):
+        if grad:
+            return ctx.run_batch(jobs(n_e, True), seed, grad=True)
+        return ctx.run_batch(J, seed)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = []
+    res = None
+    for _ in range(a.steps):
+        res = step()
+        kernel_ms.append(ctx.get_last_launch_ms())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    fepe = res.fepe()
+    rse = np.sqrt((1 - fepe) / (n_e * np.maximum(fepe, 1e-300)))
+
+    fwd_grad_ratio = None
+    if not a.no_grad:
+        step(grad=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(a.steps):
+            step(grad=True)
+        torch.cuda.synchronize()
+        fwd_grad_ratio = (time.perf_counter() - t1) / a.steps / dt
+
+    # event counts of the same histories (deterministic) for the op model
+    ctx.set_option(gadep.OPT_COUNTERS, 1)
+    step()
+    ev = ctx.get_counters()
+    ctx.set_option(gadep.OPT_COUNTERS, 0)
+    ops = sum(OPS_PER_EVENT[k] * ev[k] for k in OPS_PER_EVENT)
+    k_ms = float(np.mean(kernel_ms))
+    achieved = ops / (k_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+            "kernel_ms": k_ms, "ops_per_history": ops / total,
+            "events_per_history": {k: ev[k] / total for k in ev}}
+
+    base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
+    line = {
+        "metric": "histories/s on 20k-tri HPGe mesh at <=0.5% FEPE RSE; fwd+grad/fwd cost",
+        "value": total / dt,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "hpge_coaxial_20236_facets_point_250mm_12_energies",
+                   "n_facets": int(len(w.scene.tri)), "energies_keV": [round(e, 3) for e in w.energies],
+                   "histories_per_energy": [int(x) for x in n_e], "histories_per_step": total,
+                   "max_fepe_rse": float(rse.max())},
+        "fwd_grad_over_fwd": fwd_grad_ratio,
+        "fepe": [float(x) for x in fepe],
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,276 @@
+/*
+ * gadep.h -- C interface of the MI355X photon-transport library.
+ *
+ * Analog photon transport through a closed, region-tagged triangle mesh for
+ * HPGe full-energy-peak efficiency (FEPE) calibration, after DetMesh-Gadep
+ * (arXiv 2605.25963), Sec. 2.2-2.4:
+ *   - the CPU prepares the geometry and initialises the engine, the GPU
+ *     transports the histories, the CPU scores the tallies (Sec. 2.4, Fig. 4);
+ *   - facets arrive as in-memory arrays, no file I/O (Sec. 2.2.3);
+ *   - each facet carries its enclosed ("inner") region; the region on its
+ *     other side is derived here with the ray-parity rule of Sec. 2.4.2, so
+ *     callers never declare nesting (Sec. 2.4.2, Fig. 5);
+ *   - facets are wound counter-clockwise seen from outside, i.e. the Eq. (5)
+ *     normal (v1-v0)x(v2-v0) points out of the enclosed volume.
+ *
+ * Conventions
+ *   Units: mm, keV, g/cm^3, cm^2/g.  Linear attenuation of region r in scale
+ *   group g: mu = 0.1 * rho_r * s_g * (mu/rho)(E)  [1/mm].
+ *   Region 0 is the world: everything outside every shell.
+ *   Every call returns gadep_status (0 = OK, < 0 = error); no exception or
+ *   signal crosses the interface.  On error, gadep_last_error(ctx) returns a
+ *   message that stays valid until the next call on that context.
+ *   Pointers are host pointers unless the name ends in _dev.  Inputs are
+ *   borrowed for the duration of the call only (copied, validated, uploaded);
+ *   outputs are caller-allocated.  The context owns every device buffer it
+ *   allocates and frees them in gadep_destroy.
+ *   Calls on one context are serialised by the caller (one context per host
+ *   thread); all device work of a context is ordered on its stream.
+ */
+#ifndef GADEP_H
+#define GADEP_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gadep_ctx gadep_ctx;
+
+typedef enum {
+  GADEP_OK = 0,
+  GADEP_E_ARG = -1,             /* bad argument (null, size, range, NaN)                */
+  GADEP_E_MESH_OPEN = -2,       /* a shell is not a closed 2-manifold                   */
+  GADEP_E_MESH_ORIENT = -3,     /* inconsistent winding, or a shell wound inward        */
+  GADEP_E_MESH_OVERLAP = -4,    /* shells intersect, coincide, or lie closer than min gap */
+  GADEP_E_XS = -5,              /* bad cross-section table, or energy outside the grid  */
+  GADEP_E_STATE = -6,           /* call out of order, e.g. run before load_mesh/set_xs  */
+  GADEP_E_HIP = -7,             /* HIP runtime failure                                  */
+  GADEP_E_OOM = -8,             /* device allocation failed                             */
+  GADEP_E_TOPOLOGY = -9,        /* shell nesting could not be derived (parity rule)     */
+  GADEP_E_MESH_DEGENERATE = -10 /* zero-area facet or non-finite vertex                 */
+} gadep_status;
+
+#define GADEP_MAX_REGIONS 64     /* per scene, world included */
+#define GADEP_MAX_GROUPS 8       /* density-scale groups */
+#define GADEP_MAX_SCENES 4096
+#define GADEP_ACTIVE 1u          /* gadep_region.flags: tallied detector volume */
+
+/* ----------------------------------------------------------------------------
+ * context */
+
+/* Creates a context on HIP device `device`.  hip_stream may be NULL (the
+ * context creates its own stream) or a caller's hipStream_t (for example
+ * torch.cuda.current_stream().cuda_stream), which the context then uses and
+ * never destroys. */
+gadep_status gadep_create(int device, void* hip_stream, gadep_ctx** out);
+void gadep_destroy(gadep_ctx* ctx);
+const char* gadep_last_error(const gadep_ctx* ctx);
+
+/* Tunables and switches (gadep_set_option / gadep_get_option). */
+typedef enum {
+  GADEP_OPT_MAX_STEPS = 1,    /* per-history segment limit (watchdog), default 10000   */
+  GADEP_OPT_BLOCK = 2,        /* threads per block of the transport kernel, 64..1024   */
+  GADEP_OPT_PERIOD = 3,       /* segments between block-wide compactions, 0 = never    */
+  GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim            */
+  GADEP_OPT_VALIDATE = 5,     /* 1 = validate meshes at load (default); 0 skips the
+                                 closed/orientation/overlap checks (fault-injection
+                                 tests only: results are undefined on a bad mesh)      */
+  GADEP_OPT_MIN_GAP_NM = 6,   /* smallest allowed distance between shells, nm (100)    */
+  GADEP_OPT_GRAPHS = 7,       /* 1 = replay captured HIP graphs for repeated runs (1)  */
+  GADEP_OPT_COUNTERS = 8,     /* 1 = count events (segments, node visits, ...) (0)     */
+  GADEP_OPT_GRID = 9          /* blocks of the persistent grid, 0 = from occupancy     */
+} gadep_option;
+gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t value);
+gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* value);
+
+/* ----------------------------------------------------------------------------
+ * geometry (Sec. 2.2.3, Sec. 2.4.2) */
+
+typedef struct {
+  int32_t material;      /* material id given to gadep_set_xs                   */
+  float density_g_cm3;   /* >= 0                                                 */
+  int32_t scale_group;   /* density-scale group 0..GADEP_MAX_GROUPS-1, -1 = none */
+  uint32_t flags;        /* GADEP_ACTIVE: energy deposited here is tallied       */
+} gadep_region;
+
+/* Loads scene 0: vertices xyz_mm[n_vertices][3]; facets tri_vertices[n_tri][3]
+ * (counter-clockwise seen from outside); tri_region[n_tri] = region whose
+ * closed boundary the facet belongs to (1..n_regions-1); regions[n_regions]
+ * with regions[0] the world.  Validates (closed consistently-oriented shells,
+ * positive signed volume, no intersecting/coincident shells, gap >= min gap),
+ * derives each shell's outside region by the parity rule, builds a SAH BVH and
+ * uploads.  Errors: GADEP_E_ARG, _MESH_*, _TOPOLOGY, _HIP, _OOM. */
+gadep_status gadep_load_mesh(gadep_ctx* ctx, const float* xyz_mm, int64_t n_vertices,
+                             const int32_t* tri_vertices, const int32_t* tri_region,
+                             int64_t n_tri, const gadep_region* regions, int32_t n_regions);
+/* Same, into scene slot `scene` (0..GADEP_MAX_SCENES-1); a batch job picks its
+ * scene, e.g. the detector together with a per-job sample container. */
+gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz_mm,
+                              int64_t n_vertices, const int32_t* tri_vertices,
+                              const int32_t* tri_region, int64_t n_tri,
+                              const gadep_region* regions, int32_t n_regions);
+
+/* ----------------------------------------------------------------------------
+ * cross sections (Sec. 2.4.1) */
+
+/* Partial mass attenuation coefficients mu/rho [cm^2/g] of `material` on the
+ * grid ln E_k = lnE0_keV + k dlnE, k = 0..n_E-1 (the same grid for every
+ * material).  Interpolation is linear in ln E of ln(mu/rho), per partial.
+ * Any partial may be NULL (absent); a present partial must be all-positive or
+ * all-zero.  The lowest grid energy is the photon cut-off: below it the
+ * remaining energy is deposited locally.  Errors: GADEP_E_ARG, GADEP_E_XS. */
+gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0_keV, double dlnE,
+                          int32_t n_E, const float* mu_rho_photo, const float* mu_rho_compton,
+                          const float* mu_rho_coherent);
+
+/* Density scales s_g used by gadep_run (default 1).  scales[n_scales]. */
+gadep_status gadep_set_scales(gadep_ctx* ctx, const float* scales, int32_t n_scales);
+
+/* ----------------------------------------------------------------------------
+ * sources and tallies */
+
+typedef enum { GADEP_SRC_POINT = 0, GADEP_SRC_BEAM = 1, GADEP_SRC_CYL = 2 } gadep_source_kind;
+typedef struct {
+  int32_t kind;          /* gadep_source_kind                                      */
+  float pos_mm[3];       /* POINT/BEAM: origin.  CYL: centre of the base face      */
+  float dir[3];          /* BEAM: direction (normalised here)                      */
+  float r_in_mm, r_out_mm, h_mm; /* CYL: uniform in r_in <= r <= r_out, 0 <= z <= h
+                                    (axis +z); points outside `region` rejected    */
+  int32_t region;        /* CYL: region every emission point must lie in           */
+  int32_t n_lines;       /* > 0: each history draws its energy from the lines     */
+  const float* line_keV; /* [n_lines]                                              */
+  const float* line_prob;/* [n_lines], relative weights                            */
+} gadep_source;
+
+/* Per (job, energy) unit.  A history is FEP when it ends by absorption with
+ * every deposit inside ACTIVE regions (its ACTIVE deposit equals its source
+ * energy).  n_escape = n_histories - n_absorbed - n_lost - n_killed
+ * - n_source_fail. */
+typedef struct {
+  uint64_t n_histories, n_absorbed, n_fep, n_escape, n_uncollided, n_lost, n_killed, n_glitch,
+      n_source_fail;
+  double edep_active_keV, edep_total_keV, e_escape_keV, e_source_keV;
+  uint64_t* spectrum;        /* in: nullable caller buffer [n_channels] of ACTIVE
+                                deposit counts, channel = floor(E_dep/channel_keV) */
+  int32_t n_channels;        /* in */
+  float channel_keV;         /* in */
+  uint64_t spectrum_overflow;/* out: histories with E_dep >= n_channels*channel_keV */
+} gadep_tally;
+
+/* ----------------------------------------------------------------------------
+ * transport */
+
+/* n_histories histories (numbers first_history..) at each of the energies,
+ * point/beam/volume source, seed for the counter-based generator
+ * (Philox4x32-10 keyed by seed, counter = (draw, history, unit)).  Results are
+ * a pure function of (inputs, seed, history numbers): disjoint history ranges
+ * add up exactly, and launch shape never changes a tally.
+ * out[n_energies]; for a line source pass energies_keV = NULL, n_energies = 1. */
+gadep_status gadep_run(gadep_ctx* ctx, const gadep_source* src, const double* energies_keV,
+                       int32_t n_energies, int64_t n_histories, uint64_t seed,
+                       int64_t first_history, gadep_tally* out);
+
+/* As gadep_run at density scales `scales[n_scales]`, also returning the
+ * score-function derivative of FEPE with respect to each scale,
+ * dfepe_ds[n_energies][n_scales] = mean over histories of
+ * 1_FEP * (n_g / s_g - sum over path segments in group g of mu0 * l),
+ * and the variance of that mean, dfepe_ds_var (same shape, nullable). */
+gadep_status gadep_run_grad(gadep_ctx* ctx, const gadep_source* src, const double* energies_keV,
+                            int32_t n_energies, int64_t n_histories, uint64_t seed,
+                            int64_t first_history, const float* scales, int32_t n_scales,
+                            gadep_tally* out, double* dfepe_ds, double* dfepe_ds_var);
+
+/* Many calibration jobs of uneven size in one persistent launch. */
+typedef struct {
+  gadep_source src;
+  const double* energies_keV;  /* [n_energies]; NULL for a line source (n_energies 1) */
+  int32_t n_energies;
+  int64_t n_histories;         /* per energy */
+  int64_t first_history;
+  const float* scales;         /* nullable [n_scales]: all 1 */
+  int32_t n_scales;
+  int32_t scene;               /* scene slot */
+  uint32_t stream;             /* random stream id: identical (stream, seed, histories)
+                                  give identical results, batched or not */
+  const int32_t* region_material_override; /* nullable [n_regions of the scene]     */
+  const float* region_density_override;    /* nullable [n_regions of the scene]     */
+} gadep_job;
+
+/* out[sum of n_energies] in job order.  grads (nullable) receives
+ * dFEPE/ds [unit][GADEP_MAX_GROUPS] and grads_var (nullable) its variance. */
+gadep_status gadep_run_batch(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
+                             uint64_t seed, gadep_tally* out, double* grads, double* grads_var);
+
+/* Times short pilot launches of `jobs` over block sizes, compaction periods
+ * and claim sizes, keeps the fastest in the context and returns it (any
+ * output pointer may be NULL).  Tallies never depend on these settings. */
+gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
+                            int64_t pilot_histories, int32_t* block, int32_t* period,
+                            int32_t* claim);
+
+/* Event counts of the last run with GADEP_OPT_COUNTERS = 1. */
+typedef struct {
+  uint64_t segments, crossings, node_visits, tri_tests, photo, compton, coherent, rng_calls,
+      locates, emissions;
+} gadep_counters;
+gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
+
+/* Duration of the last transport launch, from HIP events recorded on the
+ * context's stream right before and after it (the graph replay, when graphs
+ * are on, which adds two tiny set-up kernels to the transport kernel). */
+gadep_status gadep_get_last_launch_ms(const gadep_ctx* ctx, double* ms);
+
+/* Gaussian broadening of spectra on the device: FWHM(E)^2 = a + b E (keV^2,
+ * E = channel centre), counts spread over the channels within 5 sigma,
+ * each receiving channel taking the integral of the normal law over its
+ * width.  in_dev / out_dev: device arrays [n_spectra][n_channels], FP64. */
+gadep_status gadep_broaden_dev(gadep_ctx* ctx, const double* in_dev, double* out_dev,
+                               int32_t n_spectra, int32_t n_channels, double channel_keV,
+                               double a, double b);
+
+/* ----------------------------------------------------------------------------
+ * geometry queries on the device (checks of the boundary handling) */
+
+/* Closest facet hit for rays o[n][3] + t d[n][3], t > 0, from region
+ * region[n] (nullable: no region-consistency filter).  Returns t[n]
+ * (INFINITY on a miss), tri[n] (caller's facet index, -1 on a miss) and
+ * region_after[n] (region entered across the hit facet). */
+gadep_status gadep_raycast(gadep_ctx* ctx, int32_t scene, const float* o, const float* d,
+                           const int32_t* region, int64_t n, float* t, int32_t* tri,
+                           int32_t* region_after);
+/* Region of points p[n][3] by the ray-parity rule (Sec. 2.4.2); -1 when every
+ * probe ray was degenerate. */
+gadep_status gadep_locate(gadep_ctx* ctx, int32_t scene, const float* p, int64_t n,
+                          int32_t* region);
+
+/* ----------------------------------------------------------------------------
+ * host-only mesh preparation (no device needed) */
+
+typedef struct {
+  int32_t n_shells;       /* connected closed surfaces */
+  int32_t genus_max;      /* largest shell genus, from the Euler characteristic */
+  int64_t n_nodes;        /* BVH nodes (each holds two children) */
+  int32_t depth;          /* BVH depth = traversal stack needed */
+  double sah_cost;        /* SAH cost with unit traversal and intersection cost */
+  double min_gap_mm;      /* smallest distance found between different shells */
+} gadep_mesh_info;
+
+/* Validation + topology + BVH on the host, as gadep_load_mesh does, without
+ * a context.  tri_outside[n_tri] (nullable) receives the region outside each
+ * facet, tri_shell[n_tri] (nullable) its shell index.  bvh_method 0 = binned
+ * SAH (the one used for transport), 1 = object-median split.  nodes_out
+ * (nullable, [cap_nodes][16] 32-bit words, the device layout: two child boxes
+ * as 12 floats, then two child links as int32, then 2 words of padding) and
+ * tri_order (nullable, [n_tri]: caller facet index of each BVH facet slot). */
+gadep_status gadep_mesh_prepare(const float* xyz_mm, int64_t n_vertices,
+                                const int32_t* tri_vertices, const int32_t* tri_region,
+                                int64_t n_tri, int32_t n_regions, double min_gap_mm,
+                                int32_t validate, int32_t bvh_method, int32_t* tri_outside,
+                                int32_t* tri_shell, void* nodes_out, int64_t cap_nodes,
+                                int32_t* tri_order, gadep_mesh_info* info,
+                                char* err, int32_t err_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GADEP_H */

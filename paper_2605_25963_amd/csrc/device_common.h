@@ -1,0 +1,263 @@
+// Device building blocks for gfx950: counter-based RNG, ray set-up, the
+// watertight facet test and BVH traversal.  Wavefronts are 64 lanes wide.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gadep_internal.h"
+
+namespace gadep {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// whose halves are mixed with the other counter words and the round key; the
+// key advances by the Weyl constants between rounds.
+
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
+    const uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Per-history stream: counter = (draw, history lo, history hi, stream id).
+// Four 32-bit outputs per call are consumed through a shift register.
+struct Rng {
+  uint32_t b0, b1, b2, b3;
+  uint32_t left;
+  uint32_t draw;
+  uint32_t h_lo, h_hi, stream;
+};
+
+__device__ __forceinline__ void rng_start(Rng& g, uint64_t history, uint32_t stream) {
+  g.left = 0;
+  g.draw = 0;
+  g.h_lo = static_cast<uint32_t>(history);
+  g.h_hi = static_cast<uint32_t>(history >> 32);
+  g.stream = stream;
+}
+
+// Uniform in (0, 1): 23 random bits, (k + 1/2) 2^-23, exact in FP32 so that
+// neither 0 nor 1 can occur.
+template <bool COUNT>
+__device__ __forceinline__ float rng_u(Rng& g, uint32_t k0, uint32_t k1, uint32_t& nrng) {
+  if (g.left == 0) {
+    uint32_t c0 = g.draw, c1 = g.h_lo, c2 = g.h_hi, c3 = g.stream;
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    g.b0 = c0;
+    g.b1 = c1;
+    g.b2 = c2;
+    g.b3 = c3;
+    g.draw += 1;
+    g.left = 4;
+    if (COUNT) nrng++;
+  }
+  const uint32_t x = g.b0;
+  g.b0 = g.b1;
+  g.b1 = g.b2;
+  g.b2 = g.b3;
+  g.left -= 1;
+  return (static_cast<float>(x >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+// ---------------------------------------------------------------------------
+// rays
+
+struct Ray {
+  float ox, oy, oz;
+  float dx, dy, dz;
+  float ix, iy, iz;     // 1/d, zero components replaced by +-2^100 reciprocals
+  float oix, oiy, oiz;  // o * (1/d), for one FMA per slab plane
+  int kx, ky, kz;       // watertight permutation: kz = dominant axis
+  float sx, sy, sz;     // shear constants
+};
+
+__device__ __forceinline__ float pick3(float x, float y, float z, int k) {
+  return k == 0 ? x : (k == 1 ? y : z);
+}
+
+__device__ __forceinline__ float safe_rcp(float d) {
+  const float tiny = 7.8886091e-31f;  // 2^-100
+  return 1.0f / (fabsf(d) > tiny ? d : copysignf(tiny, d));
+}
+
+__device__ __forceinline__ Ray make_ray(float ox, float oy, float oz, float dx, float dy,
+                                        float dz) {
+  Ray r;
+  r.ox = ox;
+  r.oy = oy;
+  r.oz = oz;
+  r.dx = dx;
+  r.dy = dy;
+  r.dz = dz;
+  r.ix = safe_rcp(dx);
+  r.iy = safe_rcp(dy);
+  r.iz = safe_rcp(dz);
+  r.oix = ox * r.ix;
+  r.oiy = oy * r.iy;
+  r.oiz = oz * r.iz;
+  const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+  int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  const float dkz = pick3(dx, dy, dz, kz);
+  if (dkz < 0.0f) {
+    const int t = kx;
+    kx = ky;
+    ky = t;
+  }
+  r.kx = kx;
+  r.ky = ky;
+  r.kz = kz;
+  r.sx = pick3(dx, dy, dz, kx) / dkz;
+  r.sy = pick3(dx, dy, dz, ky) / dkz;
+  r.sz = 1.0f / dkz;
+  return r;
+}
+
+// slab test of one child box; returns entry distance or +inf on a miss
+__device__ __forceinline__ float slab(const Ray& r, float lx, float ly, float lz, float hx, float hy,
+                                      float hz, float tmax) {
+  const float t0x = fmaf(lx, r.ix, -r.oix), t1x = fmaf(hx, r.ix, -r.oix);
+  const float t0y = fmaf(ly, r.iy, -r.oiy), t1y = fmaf(hy, r.iy, -r.oiy);
+  const float t0z = fmaf(lz, r.iz, -r.oiz), t1z = fmaf(hz, r.iz, -r.oiz);
+  const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+  const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+  // widen the exit distance by a few ulps so rounding never drops a box
+  return tn <= tf * 1.0000005f ? tn : INFINITY;
+}
+
+__device__ __forceinline__ float edge_fn(float a, float b, float c, float d) {
+#pragma clang fp contract(off)
+  return a * b - c * d;
+}
+
+enum { kWtMiss = 0, kWtHit = 1, kWtDegenerate = 2 };
+
+// Watertight ray-facet test (Woop, Benthin, Wald, JCGT 2013): the facet is
+// sheared into a frame where the ray runs along +z from the origin; the 2-D
+// edge functions are evaluated without contraction (recomputed in FP64 when
+// one is exactly zero), so a ray never slips between facets that share an
+// edge.  That decides hit or miss and the side: `entering` is true when the
+// ray meets the outward (Eq. 5) side.  The distance itself is taken from the
+// facet plane, t = ((v0 - o) . n) / (d . n): on long, thin facets the
+// sheared-frame distance T/det loses several digits, the plane form does not.
+// Hits must satisfy 0 < t <= tmax.  kWtDegenerate marks a crossing exactly on
+// an edge or vertex, or a ray lying in the facet plane.
+__device__ __forceinline__ int wt_test(const Ray& r, const float4 a, const float4 b,
+                                       const float4 c, float tmax, float& t, bool& entering) {
+  const float Ax = a.x - r.ox, Ay = a.y - r.oy, Az = a.z - r.oz;
+  const float Bx = a.w - r.ox, By = b.x - r.oy, Bz = b.y - r.oz;
+  const float Cx = b.z - r.ox, Cy = b.w - r.oy, Cz = c.x - r.oz;
+  const float akz = pick3(Ax, Ay, Az, r.kz), bkz = pick3(Bx, By, Bz, r.kz),
+              ckz = pick3(Cx, Cy, Cz, r.kz);
+  const float ax = fmaf(-r.sx, akz, pick3(Ax, Ay, Az, r.kx));
+  const float ay = fmaf(-r.sy, akz, pick3(Ax, Ay, Az, r.ky));
+  const float bx = fmaf(-r.sx, bkz, pick3(Bx, By, Bz, r.kx));
+  const float by = fmaf(-r.sy, bkz, pick3(Bx, By, Bz, r.ky));
+  const float cx = fmaf(-r.sx, ckz, pick3(Cx, Cy, Cz, r.kx));
+  const float cy = fmaf(-r.sy, ckz, pick3(Cx, Cy, Cz, r.ky));
+  float U = edge_fn(cx, by, cy, bx);
+  float V = edge_fn(ax, cy, ay, cx);
+  float W = edge_fn(bx, ay, by, ax);
+  bool degenerate = false;
+  if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    U = static_cast<float>((double)cx * (double)by - (double)cy * (double)bx);
+    V = static_cast<float>((double)ax * (double)cy - (double)ay * (double)cx);
+    W = static_cast<float>((double)bx * (double)ay - (double)by * (double)ax);
+    degenerate = (U == 0.0f || V == 0.0f || W == 0.0f);
+  }
+  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return kWtMiss;
+  const float det = U + V + W;
+  if (det == 0.0f) return (U == 0.0f && V == 0.0f && W == 0.0f) ? kWtDegenerate : kWtMiss;
+  // plane distance with the Eq. 5 normal of the facet
+  const float e1x = a.w - a.x, e1y = b.x - a.y, e1z = b.y - a.z;  // v1 - v0
+  const float e2x = b.z - a.x, e2y = b.w - a.y, e2z = c.x - a.z;  // v2 - v0
+  const float nx = e1y * e2z - e1z * e2y;
+  const float ny = e1z * e2x - e1x * e2z;
+  const float nz = e1x * e2y - e1y * e2x;
+  const float num = Ax * nx + Ay * ny + Az * nz;
+  const float den = r.dx * nx + r.dy * ny + r.dz * nz;
+  const float th = num * __builtin_amdgcn_rcpf(den);
+  if (!(th > 0.0f) || !(th <= tmax)) return kWtMiss;
+  t = th;
+  entering = det > 0.0f;
+  return degenerate ? kWtDegenerate : kWtHit;
+}
+
+__device__ __forceinline__ void load_node(const BvhNode* nodes, int i, float4& n0, float4& n1,
+                                          float4& n2, int4& n3) {
+  const float4* p = reinterpret_cast<const float4*>(nodes + i);
+  n0 = p[0];
+  n1 = p[1];
+  n2 = p[2];
+  n3 = reinterpret_cast<const int4*>(p)[3];
+}
+
+__device__ __forceinline__ void load_tri(const TriRec* tris, int i, float4& a, float4& b,
+                                         float4& c) {
+  const float4* p = reinterpret_cast<const float4*>(tris + i);
+  a = p[0];
+  b = p[1];
+  c = p[2];
+}
+
+constexpr int kDone = INT32_MIN;
+
+// Depth-first traversal of the two-child BVH.  The pending-node stack lives in
+// LDS, one column per thread (stack[i * stride]), so consecutive lanes touch
+// consecutive banks.  visit_leaf(first, count, tmax) tests facets and returns
+// the (possibly shrunk) tmax.  Returns the number of nodes visited.
+template <class LeafFn>
+__device__ __forceinline__ uint32_t traverse(const BvhNode* __restrict__ nodes, const Ray& r,
+                                             float& tmax, int* stack, int stride, int cap,
+                                             LeafFn&& visit_leaf) {
+  uint32_t visits = 0;
+  int sp = 0;
+  int node = 0;
+  for (;;) {
+    while (node >= 0) {
+      ++visits;
+      float4 n0, n1, n2;
+      int4 n3;
+      load_node(nodes, node, n0, n1, n2, n3);
+      const float tl = slab(r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tmax);
+      const float tr = slab(r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tmax);
+      const bool hl = tl != INFINITY, hr = tr != INFINITY;
+      if (hl && hr) {
+        const bool lfirst = tl <= tr;
+        const int near = lfirst ? n3.x : n3.y;
+        const int far = lfirst ? n3.y : n3.x;
+        if (sp < cap) {
+          stack[sp * stride] = far;
+          ++sp;
+        }
+        node = near;
+      } else if (hl) {
+        node = n3.x;
+      } else if (hr) {
+        node = n3.y;
+      } else {
+        node = sp > 0 ? stack[(--sp) * stride] : kDone;
+      }
+    }
+    if (node == kDone) break;
+    const int code = ~node;
+    tmax = visit_leaf(code >> 3, code & 7, tmax);
+    if (sp == 0) break;
+    node = stack[(--sp) * stride];
+  }
+  return visits;
+}
+
+}  // namespace gadep

@@ -1,0 +1,146 @@
+// Internal data layouts shared by the host runtime and the gfx950 kernels.
+//
+// Everything the kernels read lives in device memory in these layouts; the
+// host fills them once per mesh / per table / per run.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace gadep {
+
+constexpr int kLeafMax = 4;          // facets per BVH leaf
+constexpr int kMaxDepth = 64;        // hard cap on BVH depth (traversal stack)
+constexpr int kMaxRegions = 64;      // regions per scene (parity mask is 64-bit)
+constexpr int kMaxGroups = 8;        // density-scale groups
+constexpr float kMec2 = 510.99895f;  // electron rest energy [keV]
+
+// Fixed-point scales of the 64-bit tally accumulators (exact, order-free sums).
+constexpr double kEnergyFix = 65536.0;      // keV
+constexpr double kScoreFix = 16777216.0;    // score
+constexpr double kScore2Fix = 65536.0;      // score^2
+
+// Two children per node, each with its box; 64 bytes, read as four 16-byte loads.
+struct alignas(16) BvhNode {
+  float lmin[3], lmax[3];
+  float rmin[3], rmax[3];
+  int32_t child[2];  // >= 0: node index; < 0: leaf ~(first_facet << 3 | count)
+  int32_t pad[2];
+};
+static_assert(sizeof(BvhNode) == 64, "node layout");
+
+// Facet record in BVH leaf order; 48 bytes, read as three 16-byte loads.
+struct alignas(16) TriRec {
+  float v0[3], v1[3], v2[3];
+  uint32_t regions;  // inside (low 16 bits) | outside (high 16 bits)
+  int32_t orig;      // caller's facet index
+  uint32_t pad;
+};
+static_assert(sizeof(TriRec) == 48, "facet layout");
+
+inline int32_t leaf_code(int64_t first, int32_t count) {
+  return ~static_cast<int32_t>((first << 3) | count);
+}
+
+// Region as seen by the kernel: mu = mult * (mu/rho)(E); mu0 = mu * inv_scale.
+struct alignas(16) RegionRec {
+  float mult;        // 0.1 * density * scale
+  float inv_scale;   // 1 / scale
+  int32_t material;  // xs table index
+  int32_t bits;      // group (low 8 bits, 0xFF none) | ACTIVE << 8
+};
+
+struct SceneRec {
+  const BvhNode* nodes;
+  const TriRec* tris;
+  int32_t n_regions;
+  int32_t depth;
+};
+
+enum SourceKind : int32_t { kPoint = 0, kBeam = 1, kCyl = 2 };
+
+struct SourceRec {
+  int32_t kind;
+  float pos[3];
+  float dir[3];
+  float r_in, r_out, h;
+  int32_t region;
+  int32_t n_lines;
+  int32_t line_off;  // into the line table (float2: keV, cumulative probability)
+  int32_t pad;
+};
+
+struct UnitRec {
+  int64_t n;            // histories
+  int64_t first;        // number of the first history
+  float energy;         // keV (ignored for a line source)
+  int32_t source;       // SourceRec index
+  int32_t scene;        // SceneRec index
+  int32_t region_off;   // first RegionRec of this unit's region table
+  uint32_t stream;      // random stream id: counter word 3
+  int32_t src_region;   // region of a point/beam origin (set on the device)
+  int32_t n_groups;
+  int32_t pad;
+};
+
+// Per-unit tally slots (uint64 each).
+enum TallySlot : int {
+  kT_Hist = 0, kT_Absorbed, kT_Fep, kT_CollEscape, kT_Lost, kT_Killed, kT_Glitch, kT_SrcFail,
+  kT_SpecOvf, kT_EdepAct, kT_EdepTot, kT_EEsc, kT_ESrc,
+  kT_Score = 16, kT_FepScore = 24, kT_FepScore2 = 32,
+  kT_Ev = 40,  // event counters, 10 slots
+  kT_Slots = 64
+};
+enum EventSlot : int {
+  kEv_Segments = 0, kEv_Crossings, kEv_NodeVisits, kEv_TriTests, kEv_Photo, kEv_Compton,
+  kEv_Coherent, kEv_Rng, kEv_Locates, kEv_Emissions, kEv_N
+};
+
+struct TransportParams {
+  const UnitRec* units;
+  const int64_t* chunk_begin;  // [n_units + 1], prefix sums of chunks per unit
+  int32_t n_units;
+  int32_t chunk;               // histories per chunk
+  const SceneRec* scenes;
+  const SourceRec* sources;
+  const float* lines;          // float2 pairs
+  const RegionRec* regions;
+  const float* xs;             // float4 per (material, grid point): ln photo, compton, coherent
+  int32_t n_e;
+  float ln_e0;
+  float inv_dlne;
+  float e_cut;
+  unsigned long long* tally;   // [n_units][kT_Slots]
+  unsigned long long* spectra; // [n_units][n_channels] or null
+  int32_t n_channels;
+  float inv_channel_kev;
+  unsigned long long* cursor;  // chunk cursor
+  uint32_t seed_lo, seed_hi;
+  int32_t max_steps;
+  int32_t stack_depth;
+  int32_t period;
+};
+
+// ---------------------------------------------------------------------------
+// host preparation (mesh_prep.cpp)
+
+struct PreparedMesh {
+  std::vector<TriRec> tris;        // BVH order
+  std::vector<BvhNode> nodes;
+  std::vector<int32_t> outside;    // per caller facet
+  std::vector<int32_t> shell;      // per caller facet
+  std::vector<int32_t> order;      // caller facet of each BVH slot
+  int32_t depth = 0;
+  double sah = 0.0;
+  int32_t n_shells = 0;
+  int32_t genus_max = 0;
+  double min_gap = 0.0;
+};
+
+// Returns a gadep_status value; fills err on failure.
+int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t* tri_region,
+                 int64_t nt, int32_t n_regions, double min_gap, bool validate, int bvh_method,
+                 PreparedMesh& out, std::string& err);
+
+}  // namespace gadep

@@ -1,0 +1,708 @@
+// Host-side mesh preparation: validation, shell topology, SAH BVH.
+//
+//  * validation -- every facet edge is shared with exactly one other facet of
+//    the same region traversed in the opposite direction (closed, consistently
+//    wound 2-manifold shells), every shell has positive signed volume (outward
+//    Eq. 5 normals), and no two shells intersect or come closer than the
+//    minimum gap (coincident surfaces must be separated inside-out,
+//    Sec. 2.4.2, Fig. 6);
+//  * topology -- the region outside each shell is found with the ray-parity
+//    rule of Sec. 2.4.2 from a point on the shell, in FP64, so the per-facet
+//    inner/outer pair of the Triangle structure (Sec. 2.2.3) is derived rather
+//    than declared;
+//  * BVH -- binned surface-area-heuristic build, flattened depth-first into
+//    64-byte two-child nodes, facets reordered into 48-byte leaf records.
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <unordered_map>
+
+#include "gadep.h"
+#include "gadep_internal.h"
+
+namespace gadep {
+namespace {
+
+struct D3 {
+  double x, y, z;
+};
+inline D3 operator-(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline D3 operator*(double s, D3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline D3 cross(D3 a, D3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double len(D3 a) { return sqrt(dot(a, a)); }
+inline double clamp01(double x) { return x < 0 ? 0 : (x > 1 ? 1 : x); }
+
+struct Box {
+  float lo[3], hi[3];
+  void reset() {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = INFINITY;
+      hi[a] = -INFINITY;
+    }
+  }
+  void grow(const Box& b) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], b.lo[a]);
+      hi[a] = std::max(hi[a], b.hi[a]);
+    }
+  }
+  void grow(const float* p) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], p[a]);
+      hi[a] = std::max(hi[a], p[a]);
+    }
+  }
+  double area() const {
+    double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    if (dx < 0 || dy < 0 || dz < 0) return 0.0;
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+  }
+};
+
+struct Ref {
+  Box box;
+  float c[3];
+  int32_t id;
+};
+
+// ---------------------------------------------------------------------------
+// BVH build
+
+class Builder {
+ public:
+  Builder(std::vector<Ref>& refs, int method) : refs_(refs), method_(method) {}
+
+  void run(std::vector<BvhNode>& nodes, int32_t& depth, double& sah) {
+    nodes_.clear();
+    max_depth_ = 0;
+    const int64_t n = static_cast<int64_t>(refs_.size());
+    Box all;
+    nodes_.emplace_back();  // root
+    if (n <= kLeafMax) {
+      all.reset();
+      for (auto& r : refs_) all.grow(r.box);
+      Box empty;
+      empty.reset();
+      set_node(0, all, leaf_code(0, static_cast<int32_t>(n)), empty, leaf_code(0, 0));
+      max_depth_ = 1;
+    } else {
+      build_into(0, 0, n, 1, all);
+    }
+    nodes.swap(nodes_);
+    depth = max_depth_;
+    sah = sah_cost(nodes, all);
+  }
+
+ private:
+  std::vector<Ref>& refs_;
+  int method_;
+  std::vector<BvhNode> nodes_;
+  int32_t max_depth_ = 0;
+  static constexpr int kBins = 32;
+
+  void set_node(int32_t idx, const Box& l, int32_t lc, const Box& r, int32_t rc) {
+    BvhNode& nd = nodes_[idx];
+    for (int a = 0; a < 3; ++a) {
+      nd.lmin[a] = l.lo[a];
+      nd.lmax[a] = l.hi[a];
+      nd.rmin[a] = r.lo[a];
+      nd.rmax[a] = r.hi[a];
+    }
+    nd.child[0] = lc;
+    nd.child[1] = rc;
+    nd.pad[0] = nd.pad[1] = 0;
+  }
+
+  // Splits refs[b, e) (more than kLeafMax of them) under node `idx`.
+  void build_into(int32_t idx, int64_t b, int64_t e, int depth, Box& box_out) {
+    max_depth_ = std::max(max_depth_, depth);
+    int64_t mid = split(b, e, depth);
+    Box lb, rb;
+    int32_t lc = subtree(b, mid, depth, lb);
+    int32_t rc = subtree(mid, e, depth, rb);
+    set_node(idx, lb, lc, rb, rc);
+    box_out = lb;
+    box_out.grow(rb);
+  }
+
+  int32_t subtree(int64_t b, int64_t e, int depth, Box& box) {
+    if (e - b <= kLeafMax) {
+      box.reset();
+      for (int64_t i = b; i < e; ++i) box.grow(refs_[i].box);
+      return leaf_code(b, static_cast<int32_t>(e - b));
+    }
+    int32_t idx = static_cast<int32_t>(nodes_.size());
+    nodes_.emplace_back();
+    build_into(idx, b, e, depth + 1, box);
+    return idx;
+  }
+
+  int64_t split(int64_t b, int64_t e, int depth) {
+    Box cb;
+    cb.reset();
+    for (int64_t i = b; i < e; ++i) cb.grow(refs_[i].c);
+    if (method_ == 0 && depth < kMaxDepth - 16) {
+      double best = INFINITY;
+      int best_axis = -1, best_bin = -1;
+      for (int a = 0; a < 3; ++a) {
+        float ext = cb.hi[a] - cb.lo[a];
+        if (!(ext > 0)) continue;
+        Box bins[kBins];
+        int64_t cnt[kBins] = {0};
+        for (auto& bx : bins) bx.reset();
+        const float scale = kBins * (1.0f - 1e-6f) / ext;
+        for (int64_t i = b; i < e; ++i) {
+          int k = std::min(kBins - 1, static_cast<int>((refs_[i].c[a] - cb.lo[a]) * scale));
+          cnt[k]++;
+          bins[k].grow(refs_[i].box);
+        }
+        double right_area[kBins];
+        int64_t right_cnt[kBins];
+        Box acc;
+        acc.reset();
+        int64_t c = 0;
+        for (int k = kBins - 1; k > 0; --k) {
+          acc.grow(bins[k]);
+          c += cnt[k];
+          right_area[k] = acc.area();
+          right_cnt[k] = c;
+        }
+        acc.reset();
+        c = 0;
+        for (int k = 0; k < kBins - 1; ++k) {
+          acc.grow(bins[k]);
+          c += cnt[k];
+          if (c == 0 || right_cnt[k + 1] == 0) continue;
+          double cost = acc.area() * c + right_area[k + 1] * right_cnt[k + 1];
+          if (cost < best) {
+            best = cost;
+            best_axis = a;
+            best_bin = k;
+          }
+        }
+      }
+      if (best_axis >= 0) {
+        const int a = best_axis;
+        const float ext = cb.hi[a] - cb.lo[a];
+        const float scale = kBins * (1.0f - 1e-6f) / ext;
+        auto it = std::partition(refs_.begin() + b, refs_.begin() + e, [&](const Ref& r) {
+          return std::min(kBins - 1, static_cast<int>((r.c[a] - cb.lo[a]) * scale)) <= best_bin;
+        });
+        int64_t mid = it - refs_.begin();
+        if (mid > b && mid < e) return mid;
+      }
+    }
+    // object median along the widest centroid extent
+    int a = 0;
+    for (int k = 1; k < 3; ++k)
+      if (cb.hi[k] - cb.lo[k] > cb.hi[a] - cb.lo[a]) a = k;
+    int64_t mid = b + (e - b) / 2;
+    std::nth_element(refs_.begin() + b, refs_.begin() + mid, refs_.begin() + e,
+                     [a](const Ref& x, const Ref& y) {
+                       return x.c[a] < y.c[a] || (x.c[a] == y.c[a] && x.id < y.id);
+                     });
+    return mid;
+  }
+
+  static double box_area(const float* lo, const float* hi) {
+    Box b;
+    for (int a = 0; a < 3; ++a) {
+      b.lo[a] = lo[a];
+      b.hi[a] = hi[a];
+    }
+    return b.area();
+  }
+
+  // SAH cost, unit cost per node visit and per facet test, relative to the root
+  static double sah_cost(const std::vector<BvhNode>& nodes, const Box& root) {
+    double ra = root.area();
+    if (!(ra > 0)) return 0.0;
+    double cost = 1.0;  // root visit
+    for (const BvhNode& nd : nodes) {
+      const float* lo[2] = {nd.lmin, nd.rmin};
+      const float* hi[2] = {nd.lmax, nd.rmax};
+      for (int c = 0; c < 2; ++c) {
+        double a = box_area(lo[c], hi[c]) / ra;
+        if (nd.child[c] >= 0)
+          cost += a;
+        else
+          cost += a * ((~nd.child[c]) & 7);
+      }
+    }
+    return cost;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// FP64 queries over the flattened BVH (host preparation only)
+
+class HostQuery {
+ public:
+  HostQuery(const std::vector<BvhNode>& nodes, const std::vector<int32_t>& order,
+            const std::vector<D3>& v, const std::vector<int32_t>& tri, double margin)
+      : nodes_(nodes), order_(order), v_(v), tri_(tri), m_(margin) {}
+
+  template <class F>
+  void ray_all(D3 o, D3 d, F&& visit) const {
+    int32_t stack[kMaxDepth + 4];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+      const BvhNode& nd = nodes_[stack[--sp]];
+      const float* lo[2] = {nd.lmin, nd.rmin};
+      const float* hi[2] = {nd.lmax, nd.rmax};
+      for (int c = 0; c < 2; ++c) {
+        if (!ray_box(o, d, lo[c], hi[c])) continue;
+        int32_t ch = nd.child[c];
+        if (ch >= 0) {
+          stack[sp++] = ch;
+        } else {
+          int32_t x = ~ch;
+          for (int32_t i = x >> 3, n = x & 7, k = 0; k < n; ++k) visit(order_[i + k]);
+        }
+      }
+    }
+  }
+
+  template <class F>
+  void box_all(const double* lo, const double* hi, F&& visit) const {
+    int32_t stack[kMaxDepth + 4];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+      const BvhNode& nd = nodes_[stack[--sp]];
+      const float* blo[2] = {nd.lmin, nd.rmin};
+      const float* bhi[2] = {nd.lmax, nd.rmax};
+      for (int c = 0; c < 2; ++c) {
+        bool ov = true;
+        for (int a = 0; a < 3 && ov; ++a)
+          ov = !(hi[a] < blo[c][a] - m_ || lo[a] > bhi[c][a] + m_);
+        if (!ov) continue;
+        int32_t ch = nd.child[c];
+        if (ch >= 0) {
+          stack[sp++] = ch;
+        } else {
+          int32_t x = ~ch;
+          for (int32_t i = x >> 3, n = x & 7, k = 0; k < n; ++k) visit(order_[i + k]);
+        }
+      }
+    }
+  }
+
+ private:
+  const std::vector<BvhNode>& nodes_;
+  const std::vector<int32_t>& order_;
+  const std::vector<D3>& v_;
+  const std::vector<int32_t>& tri_;
+  double m_;
+
+  bool ray_box(D3 o, D3 d, const float* lo, const float* hi) const {
+    double t0 = 0.0, t1 = INFINITY;
+    const double oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+    for (int a = 0; a < 3; ++a) {
+      double l = lo[a] - m_, h = hi[a] + m_;
+      if (dd[a] == 0.0) {
+        if (oo[a] < l || oo[a] > h) return false;
+        continue;
+      }
+      double ta = (l - oo[a]) / dd[a], tb = (h - oo[a]) / dd[a];
+      if (ta > tb) std::swap(ta, tb);
+      t0 = std::max(t0, ta);
+      t1 = std::min(t1, tb);
+      if (t0 > t1) return false;
+    }
+    return true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// exact-ish FP64 facet geometry for validation
+
+struct Tri3 {
+  D3 a, b, c;
+};
+
+// crossing of segment p + s (q - p), s in [0, 1], with the facet (inclusive)
+bool segment_hits(D3 p, D3 q, const Tri3& t) {
+  D3 d = q - p;
+  D3 e1 = t.b - t.a, e2 = t.c - t.a;
+  D3 h = cross(d, e2);
+  double det = dot(e1, h);
+  double scale = len(e1) * len(e2) * len(d);
+  if (fabs(det) <= 1e-15 * scale) return false;  // parallel: covered by distances
+  double inv = 1.0 / det;
+  D3 s = p - t.a;
+  double u = dot(s, h) * inv;
+  if (u < 0 || u > 1) return false;
+  D3 qv = cross(s, e1);
+  double v = dot(d, qv) * inv;
+  if (v < 0 || u + v > 1) return false;
+  double w = dot(e2, qv) * inv;
+  return w >= 0 && w <= 1;
+}
+
+// distance from p to the closest point of the facet (Voronoi-region walk)
+double point_tri_dist(D3 p, const Tri3& t) {
+  D3 ab = t.b - t.a, ac = t.c - t.a, ap = p - t.a;
+  double d1 = dot(ab, ap), d2 = dot(ac, ap);
+  if (d1 <= 0 && d2 <= 0) return len(p - t.a);
+  D3 bp = p - t.b;
+  double d3 = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3 >= 0 && d4 <= d3) return len(p - t.b);
+  double vc = d1 * d4 - d3 * d2;
+  if (vc <= 0 && d1 >= 0 && d3 <= 0) {
+    double s = d1 / (d1 - d3);
+    return len(p - (t.a + s * ab));
+  }
+  D3 cp = p - t.c;
+  double d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= 0 && d5 <= d6) return len(p - t.c);
+  double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+    double s = d2 / (d2 - d6);
+    return len(p - (t.a + s * ac));
+  }
+  double va = d3 * d6 - d5 * d4;
+  if (va <= 0 && (d4 - d3) >= 0 && (d5 - d6) >= 0) {
+    double s = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    return len(p - (t.b + s * (t.c - t.b)));
+  }
+  double den = 1.0 / (va + vb + vc);
+  double v = vb * den, w = vc * den;
+  return len(p - (t.a + v * ab + w * ac));
+}
+
+// distance between segments p1q1 and p2q2 (clamped closest parameters)
+double seg_seg_dist(D3 p1, D3 q1, D3 p2, D3 q2) {
+  D3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
+  double a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
+  double s, t;
+  if (a <= 1e-30 && e <= 1e-30) return len(r);
+  if (a <= 1e-30) {
+    s = 0;
+    t = clamp01(f / e);
+  } else {
+    double c = dot(d1, r);
+    if (e <= 1e-30) {
+      t = 0;
+      s = clamp01(-c / a);
+    } else {
+      double b = dot(d1, d2);
+      double den = a * e - b * b;
+      s = den > 1e-30 * a * e ? clamp01((b * f - c * e) / den) : 0.0;
+      t = (b * s + f) / e;
+      if (t < 0) {
+        t = 0;
+        s = clamp01(-c / a);
+      } else if (t > 1) {
+        t = 1;
+        s = clamp01((b - c) / a);
+      }
+    }
+  }
+  return len((p1 + s * d1) - (p2 + t * d2));
+}
+
+double tri_tri_dist(const Tri3& A, const Tri3& B) {
+  const D3 av[3] = {A.a, A.b, A.c}, bv[3] = {B.a, B.b, B.c};
+  for (int i = 0; i < 3; ++i) {
+    if (segment_hits(av[i], av[(i + 1) % 3], B)) return 0.0;
+    if (segment_hits(bv[i], bv[(i + 1) % 3], A)) return 0.0;
+  }
+  double d = INFINITY;
+  for (int i = 0; i < 3; ++i) {
+    d = std::min(d, point_tri_dist(av[i], B));
+    d = std::min(d, point_tri_dist(bv[i], A));
+    for (int j = 0; j < 3; ++j)
+      d = std::min(d, seg_seg_dist(av[i], av[(i + 1) % 3], bv[j], bv[(j + 1) % 3]));
+  }
+  return d;
+}
+
+// parity probe directions (unit vectors, generic)
+const double kProbe[8][3] = {
+    {0.3420201433256687, 0.4698463103929542, 0.8137976813493738},
+    {-0.6123724356957945, 0.6123724356957945, 0.5000000000000001},
+    {0.5265407233266235, -0.2807702340418462, -0.8024434918893496},
+    {-0.2588190451025208, -0.9153482049516813, 0.3085601688130047},
+    {0.8717797887081347, 0.1889822365046136, -0.4520064213127209},
+    {-0.7745966692414834, -0.3162277660168379, -0.5477225575051661},
+    {0.1543033499620919, 0.7715167498104596, -0.6172133998483676},
+    {0.6928203230275509, -0.6, 0.4},
+};
+
+enum { kMiss = 0, kHit = 1, kDegenerate = 2 };
+
+// ray o + t d, t > 0, against a facet; edge/vertex/in-plane grazing => degenerate
+int probe_facet(D3 o, D3 d, const Tri3& t, double ext, double& th) {
+  D3 e1 = t.b - t.a, e2 = t.c - t.a;
+  D3 n = cross(e1, e2);
+  D3 p = cross(d, e2);
+  double det = dot(e1, p);
+  D3 s = o - t.a;
+  if (fabs(det) <= 1e-13 * len(e1) * len(e2)) {
+    return fabs(dot(s, n)) <= 1e-11 * len(n) * ext ? kDegenerate : kMiss;
+  }
+  double inv = 1.0 / det;
+  double u = dot(s, p) * inv;
+  D3 q = cross(s, e1);
+  double v = dot(d, q) * inv;
+  double w = 1.0 - u - v;
+  const double tol = 1e-10;
+  if (u < -tol || v < -tol || w < -tol) return kMiss;
+  th = dot(e2, q) * inv;
+  if (th < -1e-11 * ext) return kMiss;
+  if (u < tol || v < tol || w < tol || th <= 1e-11 * ext) return kDegenerate;
+  return kHit;
+}
+
+int fail(std::string& err, int code, const std::string& msg) {
+  err = msg;
+  return code;
+}
+
+}  // namespace
+
+int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t* tri_region,
+                 int64_t nt, int32_t n_regions, double min_gap, bool validate, int bvh_method,
+                 PreparedMesh& out, std::string& err) {
+  if (!xyz || !tri || !tri_region || nv < 3 || nt < 1)
+    return fail(err, GADEP_E_ARG, "mesh: null array or empty mesh");
+  if (n_regions < 2 || n_regions > kMaxRegions)
+    return fail(err, GADEP_E_ARG, "mesh: n_regions must be in [2, 64]");
+  if (nt > (int64_t(1) << 27)) return fail(err, GADEP_E_ARG, "mesh: too many facets");
+  if (bvh_method != 0 && bvh_method != 1) return fail(err, GADEP_E_ARG, "mesh: bvh_method");
+
+  // ---- basic checks
+  std::vector<D3> v(static_cast<size_t>(nv));
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < nv; ++i) {
+    double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+      return fail(err, GADEP_E_MESH_DEGENERATE, "mesh: non-finite vertex " + std::to_string(i));
+    v[i] = {x, y, z};
+    lo[0] = std::min(lo[0], x), lo[1] = std::min(lo[1], y), lo[2] = std::min(lo[2], z);
+    hi[0] = std::max(hi[0], x), hi[1] = std::max(hi[1], y), hi[2] = std::max(hi[2], z);
+  }
+  const double ext = sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                          (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  std::vector<int32_t> tv(tri, tri + 3 * nt);
+  for (int64_t f = 0; f < nt; ++f) {
+    for (int k = 0; k < 3; ++k)
+      if (tv[3 * f + k] < 0 || tv[3 * f + k] >= nv)
+        return fail(err, GADEP_E_ARG, "mesh: vertex index out of range in facet " + std::to_string(f));
+    if (tri_region[f] < 1 || tri_region[f] >= n_regions)
+      return fail(err, GADEP_E_ARG, "mesh: facet region out of range in facet " + std::to_string(f));
+    D3 a = v[tv[3 * f]], b = v[tv[3 * f + 1]], c = v[tv[3 * f + 2]];
+    if (len(cross(b - a, c - a)) <= 0.0)
+      return fail(err, GADEP_E_MESH_DEGENERATE, "mesh: zero-area facet " + std::to_string(f));
+  }
+
+  // ---- edges: each directed edge once, its reverse once, same region
+  std::vector<int32_t> parent(static_cast<size_t>(nt));
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int32_t x) {
+    while (parent[x] != x) x = parent[x] = parent[parent[x]];
+    return x;
+  };
+  {
+    std::unordered_map<uint64_t, int32_t> edge;
+    edge.reserve(static_cast<size_t>(3 * nt));
+    for (int64_t f = 0; f < nt; ++f)
+      for (int k = 0; k < 3; ++k) {
+        uint32_t a = tv[3 * f + k], b = tv[3 * f + (k + 1) % 3];
+        uint64_t key = (uint64_t(a) << 32) | b;
+        if (!edge.emplace(key, static_cast<int32_t>(f)).second) {
+          if (validate)
+            return fail(err, GADEP_E_MESH_ORIENT,
+                        "mesh: directed edge used twice (inconsistent winding) at facet " +
+                            std::to_string(f));
+        }
+      }
+    for (int64_t f = 0; f < nt; ++f)
+      for (int k = 0; k < 3; ++k) {
+        uint32_t a = tv[3 * f + k], b = tv[3 * f + (k + 1) % 3];
+        auto it = edge.find((uint64_t(b) << 32) | a);
+        if (it == edge.end()) {
+          if (validate)
+            return fail(err, GADEP_E_MESH_OPEN,
+                        "mesh: open edge at facet " + std::to_string(f) + " (region " +
+                            std::to_string(tri_region[f]) + ")");
+          continue;
+        }
+        if (tri_region[it->second] != tri_region[f] && validate)
+          return fail(err, GADEP_E_MESH_OVERLAP,
+                      "mesh: facets of regions " + std::to_string(tri_region[f]) + " and " +
+                          std::to_string(tri_region[it->second]) + " share an edge");
+        int32_t ra = find(static_cast<int32_t>(f)), rb = find(it->second);
+        if (ra != rb) parent[ra] = rb;
+      }
+  }
+
+  // ---- shells
+  std::vector<int32_t> shell(static_cast<size_t>(nt), -1);
+  std::vector<int32_t> shell_first;  // first facet of each shell
+  {
+    std::unordered_map<int32_t, int32_t> id;
+    for (int64_t f = 0; f < nt; ++f) {
+      int32_t r = find(static_cast<int32_t>(f));
+      auto it = id.find(r);
+      if (it == id.end()) {
+        it = id.emplace(r, static_cast<int32_t>(shell_first.size())).first;
+        shell_first.push_back(static_cast<int32_t>(f));
+      }
+      shell[f] = it->second;
+    }
+  }
+  const int32_t ns = static_cast<int32_t>(shell_first.size());
+  std::vector<double> vol(ns, 0.0);
+  std::vector<int64_t> nf(ns, 0);
+  for (int64_t f = 0; f < nt; ++f) {
+    D3 a = v[tv[3 * f]], b = v[tv[3 * f + 1]], c = v[tv[3 * f + 2]];
+    vol[shell[f]] += dot(a, cross(b, c)) / 6.0;
+    nf[shell[f]]++;
+  }
+  int32_t genus_max = 0;
+  {
+    // Euler characteristic per shell: V - E + F, E = 3F/2 for a closed shell
+    std::vector<std::vector<int32_t>> sv(ns);
+    for (int64_t f = 0; f < nt; ++f)
+      for (int k = 0; k < 3; ++k) sv[shell[f]].push_back(tv[3 * f + k]);
+    for (int32_t s = 0; s < ns; ++s) {
+      auto& x = sv[s];
+      std::sort(x.begin(), x.end());
+      int64_t nvs = std::unique(x.begin(), x.end()) - x.begin();
+      int64_t chi = nvs - 3 * nf[s] / 2 + nf[s];
+      genus_max = std::max<int32_t>(genus_max, static_cast<int32_t>((2 - chi) / 2));
+    }
+  }
+  if (validate)
+    for (int32_t s = 0; s < ns; ++s)
+      if (!(vol[s] > 0))
+        return fail(err, GADEP_E_MESH_ORIENT,
+                    "mesh: shell of region " + std::to_string(tri_region[shell_first[s]]) +
+                        " has non-positive signed volume (wound inward)");
+
+  // ---- BVH
+  std::vector<Ref> refs(static_cast<size_t>(nt));
+  for (int64_t f = 0; f < nt; ++f) {
+    Ref& r = refs[f];
+    r.box.reset();
+    for (int k = 0; k < 3; ++k) r.box.grow(xyz + 3 * tv[3 * f + k]);
+    for (int a = 0; a < 3; ++a) r.c[a] = 0.5f * (r.box.lo[a] + r.box.hi[a]);
+    r.id = static_cast<int32_t>(f);
+  }
+  Builder builder(refs, bvh_method);
+  builder.run(out.nodes, out.depth, out.sah);
+  out.order.resize(static_cast<size_t>(nt));
+  for (int64_t i = 0; i < nt; ++i) out.order[i] = refs[i].id;
+
+  auto facet = [&](int32_t f) {
+    return Tri3{v[tv[3 * f]], v[tv[3 * f + 1]], v[tv[3 * f + 2]]};
+  };
+  HostQuery q(out.nodes, out.order, v, tv, 1e-9 * ext + 1e-12);
+
+  // ---- shells must not intersect or come closer than min_gap
+  double gap_seen = INFINITY;
+  if (validate && ns > 1) {
+    for (int64_t f = 0; f < nt; ++f) {
+      Tri3 A = facet(static_cast<int32_t>(f));
+      double blo[3], bhi[3];
+      const D3 p[3] = {A.a, A.b, A.c};
+      for (int a = 0; a < 3; ++a) {
+        double mn = INFINITY, mx = -INFINITY;
+        for (int k = 0; k < 3; ++k) {
+          double c = a == 0 ? p[k].x : (a == 1 ? p[k].y : p[k].z);
+          mn = std::min(mn, c);
+          mx = std::max(mx, c);
+        }
+        blo[a] = mn - min_gap;
+        bhi[a] = mx + min_gap;
+      }
+      int bad = -1;
+      q.box_all(blo, bhi, [&](int32_t g) {
+        if (bad >= 0 || g <= f || shell[g] == shell[f]) return;
+        double d = tri_tri_dist(A, facet(g));
+        gap_seen = std::min(gap_seen, d);
+        if (d < min_gap) bad = g;
+      });
+      if (bad >= 0)
+        return fail(err, GADEP_E_MESH_OVERLAP,
+                    "mesh: shells of regions " + std::to_string(tri_region[f]) + " and " +
+                        std::to_string(tri_region[bad]) + " intersect or are closer than the "
+                        "minimum gap (facets " + std::to_string(f) + ", " + std::to_string(bad) + ")");
+    }
+  }
+
+  // ---- topology: region outside each shell by the parity rule
+  std::vector<int32_t> container(ns, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    Tri3 t0 = facet(shell_first[s]);
+    D3 o = (1.0 / 3.0) * (t0.a + t0.b + t0.c);
+    bool done = false;
+    for (int k = 0; k < 8 && !done; ++k) {
+      D3 d{kProbe[k][0], kProbe[k][1], kProbe[k][2]};
+      d = (1.0 / len(d)) * d;
+      uint64_t parity = 0;
+      double first[kMaxRegions];
+      for (double& x : first) x = INFINITY;
+      bool degenerate = false;
+      q.ray_all(o, d, [&](int32_t g) {
+        if (degenerate || shell[g] == s) return;
+        double th;
+        int r = probe_facet(o, d, facet(g), ext, th);
+        if (r == kDegenerate) degenerate = true;
+        if (r != kHit) return;
+        int32_t rg = tri_region[g];
+        parity ^= uint64_t(1) << rg;
+        first[rg] = std::min(first[rg], th);
+      });
+      if (degenerate) continue;
+      int32_t best = 0;
+      double tb = INFINITY;
+      for (int32_t r = 1; r < n_regions; ++r)
+        if (((parity >> r) & 1) && first[r] < tb) {
+          tb = first[r];
+          best = r;
+        }
+      container[s] = best;
+      done = true;
+    }
+    if (!done) return fail(err, GADEP_E_TOPOLOGY, "mesh: every parity probe was degenerate");
+    const int32_t own = tri_region[shell_first[s]];
+    if (validate && container[s] == own)
+      return fail(err, GADEP_E_TOPOLOGY,
+                  "mesh: a shell of region " + std::to_string(own) +
+                      " lies inside another shell of the same region");
+  }
+
+  // ---- outputs
+  out.outside.resize(static_cast<size_t>(nt));
+  out.shell = shell;
+  for (int64_t f = 0; f < nt; ++f) out.outside[f] = container[shell[f]];
+  out.tris.resize(static_cast<size_t>(nt));
+  for (int64_t i = 0; i < nt; ++i) {
+    int32_t f = out.order[i];
+    TriRec& r = out.tris[i];
+    for (int k = 0; k < 3; ++k) {
+      const float* p = xyz + 3 * tv[3 * f + k];
+      float* dst = k == 0 ? r.v0 : (k == 1 ? r.v1 : r.v2);
+      dst[0] = p[0], dst[1] = p[1], dst[2] = p[2];
+    }
+    r.regions = uint32_t(tri_region[f]) | (uint32_t(out.outside[f]) << 16);
+    r.orig = f;
+    r.pad = 0;
+  }
+  out.n_shells = ns;
+  out.genus_max = genus_max;
+  out.min_gap = gap_seen;
+  return GADEP_OK;
+}
+
+}  // namespace gadep

@@ -1,0 +1,991 @@
+// Runtime behind the C interface: contexts, scenes, tables, unit tables,
+// persistent launches, graph replay, tally conversion and the autotuner.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "gadep.h"
+#include "gadep_internal.h"
+
+namespace gadep {
+// kernels.hip
+size_t transport_smem(int block, int depth);
+hipError_t transport_launch(const TransportParams& P, int variant, int grid, int block,
+                            hipStream_t s);
+hipError_t transport_occupancy(int variant, int block, int depth, int* blocks_per_cu);
+hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t locate_units(UnitRec* units, int n_units, const SceneRec* scenes,
+                        const SourceRec* sources, int depth, hipStream_t s);
+hipError_t raycast(const SceneRec& sc, const float* o, const float* d, const int32_t* region,
+                   int64_t n, float* t, int32_t* tri, int32_t* region_after, hipStream_t s);
+hipError_t locate(const SceneRec& sc, const float* p, int64_t n, int32_t* region, hipStream_t s);
+hipError_t broaden(const double* in, double* out, int n_spectra, int n, double w, double a,
+                   double b, hipStream_t s);
+}  // namespace gadep
+
+using namespace gadep;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Scene {
+  bool loaded = false;
+  int32_t n_regions = 0;
+  std::vector<gadep_region> regions;
+  int32_t depth = 0;
+  int64_t n_tri = 0;
+  int64_t n_nodes = 0;
+  void* d_nodes = nullptr;
+  void* d_tris = nullptr;
+};
+
+struct Material {
+  bool set = false;
+  std::vector<float> ln[3];  // ln(mu/rho) per grid point; -200 for an absent partial
+};
+
+}  // namespace
+
+struct gadep_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n_cu = 0;
+  std::string err;
+
+  std::vector<std::unique_ptr<Scene>> scenes;
+
+  bool grid_set = false;
+  double lnE0 = 0, dlnE = 0;
+  int32_t nE = 0;
+  std::vector<Material> mats;
+  bool xs_dirty = false;
+  DevBuf xs;
+
+  std::vector<float> scales = std::vector<float>(GADEP_MAX_GROUPS, 1.0f);
+
+  int64_t max_steps = 10000;
+  int64_t block = 256;
+  int64_t period = 0;
+  int64_t claim = 32;
+  int64_t validate = 1;
+  int64_t min_gap_nm = 100;
+  int64_t graphs = 1;
+  int64_t counters = 0;
+  int64_t grid = 0;
+
+  DevBuf units, chunk_begin, scene_tab, sources, lines, regions, tally, spectra, cursor;
+  void* h_tally = nullptr;  // pinned
+  size_t h_tally_cap = 0;
+  gadep_counters last_counters{};
+  bool have_counters = false;
+  double last_ms = -1.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  // graph cache
+  hipGraphExec_t graph = nullptr;
+  std::vector<uint8_t> graph_key;
+};
+
+namespace {
+
+gadep_status set_err(gadep_ctx* c, gadep_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+gadep_status hip_err(gadep_ctx* c, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return set_err(c, GADEP_E_OOM, std::string(what) + ": " + hipGetErrorString(e));
+  return set_err(c, GADEP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_err(ctx, e_, what); \
+  } while (0)
+
+gadep_status ensure(gadep_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 16;
+  if (b.cap >= bytes) return GADEP_OK;
+  if (b.p) {
+    hipStreamSynchronize(ctx->stream);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t cap = bytes + bytes / 4;
+  HIP_TRY(hipMalloc(&b.p, cap), what);
+  b.cap = cap;
+  // cached graphs refer to the old buffer
+  if (ctx->graph) {
+    hipGraphExecDestroy(ctx->graph);
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+  }
+  return GADEP_OK;
+}
+
+void free_buf(DevBuf& b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+gadep_status upload(gadep_ctx* ctx, DevBuf& b, const void* src, size_t bytes, const char* what) {
+  gadep_status s = ensure(ctx, b, bytes, what);
+  if (s) return s;
+  if (bytes) HIP_TRY(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, ctx->stream), what);
+  return GADEP_OK;
+}
+
+gadep_status sync_xs(gadep_ctx* ctx) {
+  if (!ctx->xs_dirty) return GADEP_OK;
+  const size_t nm = ctx->mats.size();
+  std::vector<float> host(nm * ctx->nE * 4, -200.0f);
+  for (size_t m = 0; m < nm; ++m) {
+    if (!ctx->mats[m].set) continue;
+    for (int32_t k = 0; k < ctx->nE; ++k)
+      for (int i = 0; i < 3; ++i) host[(m * ctx->nE + k) * 4 + i] = ctx->mats[m].ln[i][k];
+  }
+  gadep_status s = upload(ctx, ctx->xs, host.data(), host.size() * sizeof(float), "upload xs");
+  if (s) return s;
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "upload xs");
+  ctx->xs_dirty = false;
+  return GADEP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// run planning
+
+struct Plan {
+  std::vector<UnitRec> units;
+  std::vector<int64_t> chunk_begin;
+  std::vector<SourceRec> sources;
+  std::vector<float> lines;
+  std::vector<RegionRec> regions;
+  std::vector<double> unit_energy;  // for reporting
+  bool spectrum = false;
+  int32_t n_channels = 0;
+  float channel_keV = 0;
+  bool grad = false;
+  int32_t depth = 1;
+};
+
+gadep_status check_source(gadep_ctx* ctx, const gadep_source& s, const Scene& sc) {
+  if (s.kind < GADEP_SRC_POINT || s.kind > GADEP_SRC_CYL)
+    return set_err(ctx, GADEP_E_ARG, "source: unknown kind");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(s.pos_mm[a])) return set_err(ctx, GADEP_E_ARG, "source: non-finite position");
+  if (s.kind == GADEP_SRC_BEAM) {
+    double n = 0;
+    for (int a = 0; a < 3; ++a) n += double(s.dir[a]) * s.dir[a];
+    if (!(n > 0) || !std::isfinite(n)) return set_err(ctx, GADEP_E_ARG, "source: bad beam direction");
+  }
+  if (s.kind == GADEP_SRC_CYL) {
+    if (!(s.r_in_mm >= 0) || !(s.r_out_mm > s.r_in_mm) || !(s.h_mm > 0))
+      return set_err(ctx, GADEP_E_ARG, "source: bad cylinder dimensions");
+    if (s.region < 0 || s.region >= sc.n_regions)
+      return set_err(ctx, GADEP_E_ARG, "source: region out of range");
+  }
+  if (s.n_lines < 0) return set_err(ctx, GADEP_E_ARG, "source: n_lines < 0");
+  if (s.n_lines > 0) {
+    if (!s.line_keV || !s.line_prob) return set_err(ctx, GADEP_E_ARG, "source: null line arrays");
+    double tot = 0;
+    for (int i = 0; i < s.n_lines; ++i) {
+      if (!(s.line_prob[i] >= 0)) return set_err(ctx, GADEP_E_ARG, "source: negative line weight");
+      tot += s.line_prob[i];
+    }
+    if (!(tot > 0)) return set_err(ctx, GADEP_E_ARG, "source: line weights sum to zero");
+  }
+  return GADEP_OK;
+}
+
+gadep_status check_energy(gadep_ctx* ctx, double E) {
+  const double lo = exp(ctx->lnE0), hi = exp(ctx->lnE0 + ctx->dlnE * (ctx->nE - 1));
+  if (!(E >= lo * (1 - 1e-12) && E <= hi * (1 + 1e-12)))
+    return set_err(ctx, GADEP_E_XS, "energy " + std::to_string(E) + " keV outside the table grid");
+  return GADEP_OK;
+}
+
+gadep_status plan_jobs(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
+                       const gadep_tally* out, bool grad, Plan& P) {
+  if (!jobs || n_jobs <= 0) return set_err(ctx, GADEP_E_ARG, "no jobs");
+  if (!ctx->grid_set) return set_err(ctx, GADEP_E_STATE, "run before gadep_set_xs");
+  P = Plan();
+  P.grad = grad;
+  const int64_t chunk = 64 * ctx->claim;
+  int64_t chunks = 0;
+  int32_t unit_index = 0;
+  for (int32_t j = 0; j < n_jobs; ++j) {
+    const gadep_job& J = jobs[j];
+    if (J.scene < 0 || J.scene >= static_cast<int32_t>(ctx->scenes.size()) || !ctx->scenes[J.scene] ||
+        !ctx->scenes[J.scene]->loaded)
+      return set_err(ctx, GADEP_E_STATE, "job " + std::to_string(j) + ": scene not loaded");
+    const Scene& sc = *ctx->scenes[J.scene];
+    gadep_status s = check_source(ctx, J.src, sc);
+    if (s) return s;
+    if (J.n_histories < 0 || J.first_history < 0)
+      return set_err(ctx, GADEP_E_ARG, "job: negative history count or first history");
+    if (J.n_energies < 1 || J.n_energies > 65536)
+      return set_err(ctx, GADEP_E_ARG, "job: n_energies must be in [1, 65536]");
+    if (J.src.n_lines == 0 && !J.energies_keV)
+      return set_err(ctx, GADEP_E_ARG, "job: energies_keV is NULL for a mono-energetic source");
+    if (J.src.n_lines > 0 && J.n_energies != 1)
+      return set_err(ctx, GADEP_E_ARG, "job: a line source takes n_energies = 1");
+    if (J.stream > 0xFFFFu) return set_err(ctx, GADEP_E_ARG, "job: stream id above 65535");
+    if (J.n_scales < 0 || J.n_scales > GADEP_MAX_GROUPS || (J.n_scales > 0 && !J.scales))
+      return set_err(ctx, GADEP_E_ARG, "job: bad scales");
+    float sc8[GADEP_MAX_GROUPS];
+    for (int g = 0; g < GADEP_MAX_GROUPS; ++g) sc8[g] = 1.0f;
+    for (int g = 0; g < J.n_scales; ++g) {
+      if (!(J.scales[g] > 0) || !std::isfinite(J.scales[g]))
+        return set_err(ctx, GADEP_E_ARG, "job: scales must be positive");
+      sc8[g] = J.scales[g];
+    }
+    // region table of this job
+    const int32_t roff = static_cast<int32_t>(P.regions.size());
+    for (int32_t r = 0; r < sc.n_regions; ++r) {
+      gadep_region R = sc.regions[r];
+      if (J.region_material_override) R.material = J.region_material_override[r];
+      if (J.region_density_override) R.density_g_cm3 = J.region_density_override[r];
+      if (R.material < 0 || R.material >= static_cast<int32_t>(ctx->mats.size()) ||
+          !ctx->mats[R.material].set)
+        return set_err(ctx, GADEP_E_STATE,
+                       "region " + std::to_string(r) + ": material has no cross sections");
+      if (!(R.density_g_cm3 >= 0) || !std::isfinite(R.density_g_cm3))
+        return set_err(ctx, GADEP_E_ARG, "region density must be finite and >= 0");
+      if (R.scale_group < -1 || R.scale_group >= GADEP_MAX_GROUPS)
+        return set_err(ctx, GADEP_E_ARG, "region scale group out of range");
+      const float s = R.scale_group >= 0 ? sc8[R.scale_group] : 1.0f;
+      RegionRec rr;
+      rr.mult = static_cast<float>(0.1 * R.density_g_cm3 * s);
+      rr.inv_scale = 1.0f / s;
+      rr.material = R.material;
+      rr.bits = (R.scale_group >= 0 ? R.scale_group : 0xFF) | ((R.flags & GADEP_ACTIVE) ? 0x100 : 0);
+      P.regions.push_back(rr);
+    }
+    // source
+    SourceRec sr{};
+    sr.kind = J.src.kind;
+    for (int a = 0; a < 3; ++a) sr.pos[a] = J.src.pos_mm[a];
+    if (J.src.kind == GADEP_SRC_BEAM) {
+      double n = sqrt(double(J.src.dir[0]) * J.src.dir[0] + double(J.src.dir[1]) * J.src.dir[1] +
+                      double(J.src.dir[2]) * J.src.dir[2]);
+      for (int a = 0; a < 3; ++a) sr.dir[a] = static_cast<float>(J.src.dir[a] / n);
+    }
+    sr.r_in = J.src.r_in_mm;
+    sr.r_out = J.src.r_out_mm;
+    sr.h = J.src.h_mm;
+    sr.region = J.src.region;
+    sr.n_lines = J.src.n_lines;
+    sr.line_off = static_cast<int32_t>(P.lines.size() / 2);
+    if (J.src.n_lines > 0) {
+      double tot = 0;
+      for (int i = 0; i < J.src.n_lines; ++i) tot += J.src.line_prob[i];
+      double cum = 0;
+      for (int i = 0; i < J.src.n_lines; ++i) {
+        gadep_status es = check_energy(ctx, J.src.line_keV[i]);
+        if (es) return es;
+        cum += J.src.line_prob[i];
+        P.lines.push_back(J.src.line_keV[i]);
+        P.lines.push_back(static_cast<float>(i == J.src.n_lines - 1 ? 2.0 : cum / tot));
+      }
+    }
+    const int32_t src_idx = static_cast<int32_t>(P.sources.size());
+    P.sources.push_back(sr);
+    P.depth = std::max(P.depth, sc.depth);
+    for (int32_t e = 0; e < J.n_energies; ++e) {
+      UnitRec u{};
+      u.n = J.n_histories;
+      u.first = J.first_history;
+      double E = J.src.n_lines > 0 ? 0.0 : J.energies_keV[e];
+      if (J.src.n_lines == 0) {
+        gadep_status es = check_energy(ctx, E);
+        if (es) return es;
+      }
+      u.energy = static_cast<float>(E);
+      u.source = src_idx;
+      u.scene = J.scene;
+      u.region_off = roff;
+      u.stream = (J.stream << 16) | static_cast<uint32_t>(e);
+      u.src_region = 0;
+      u.n_groups = grad ? GADEP_MAX_GROUPS : 0;
+      P.units.push_back(u);
+      P.unit_energy.push_back(E);
+      P.chunk_begin.push_back(chunks);
+      chunks += (u.n + chunk - 1) / chunk;
+      if (out) {
+        const gadep_tally& t = out[unit_index];
+        if (t.spectrum) {
+          if (t.n_channels <= 0 || !(t.channel_keV > 0))
+            return set_err(ctx, GADEP_E_ARG, "tally: spectrum needs n_channels > 0 and channel_keV > 0");
+          if (P.spectrum && (t.n_channels != P.n_channels || t.channel_keV != P.channel_keV))
+            return set_err(ctx, GADEP_E_ARG, "tally: all spectra of one run share their binning");
+          P.spectrum = true;
+          P.n_channels = t.n_channels;
+          P.channel_keV = t.channel_keV;
+        }
+      }
+      ++unit_index;
+    }
+  }
+  P.chunk_begin.push_back(chunks);
+  return GADEP_OK;
+}
+
+void to_tally(const unsigned long long* T, gadep_tally& t) {
+  t.n_histories = T[kT_Hist];
+  t.n_absorbed = T[kT_Absorbed];
+  t.n_fep = T[kT_Fep];
+  t.n_lost = T[kT_Lost];
+  t.n_killed = T[kT_Killed];
+  t.n_glitch = T[kT_Glitch];
+  t.n_source_fail = T[kT_SrcFail];
+  t.n_escape = T[kT_Hist] - T[kT_Absorbed] - T[kT_Lost] - T[kT_Killed] - T[kT_SrcFail];
+  t.n_uncollided = t.n_escape - T[kT_CollEscape];
+  t.edep_active_keV = static_cast<double>(static_cast<int64_t>(T[kT_EdepAct])) / kEnergyFix;
+  t.edep_total_keV = static_cast<double>(static_cast<int64_t>(T[kT_EdepTot])) / kEnergyFix;
+  t.e_escape_keV = static_cast<double>(static_cast<int64_t>(T[kT_EEsc])) / kEnergyFix;
+  t.e_source_keV = static_cast<double>(static_cast<int64_t>(T[kT_ESrc])) / kEnergyFix;
+  t.spectrum_overflow = T[kT_SpecOvf];
+}
+
+gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, double* grads,
+                     double* grads_var, int32_t n_grad_cols, float* elapsed_ms = nullptr) {
+  gadep_status s = sync_xs(ctx);
+  if (s) return s;
+  const int32_t nu = static_cast<int32_t>(P.units.size());
+  // scene table
+  std::vector<SceneRec> st(ctx->scenes.size());
+  for (size_t i = 0; i < ctx->scenes.size(); ++i) {
+    if (!ctx->scenes[i] || !ctx->scenes[i]->loaded) continue;
+    st[i].nodes = static_cast<const BvhNode*>(ctx->scenes[i]->d_nodes);
+    st[i].tris = static_cast<const TriRec*>(ctx->scenes[i]->d_tris);
+    st[i].n_regions = ctx->scenes[i]->n_regions;
+    st[i].depth = ctx->scenes[i]->depth;
+  }
+  if ((s = upload(ctx, ctx->scene_tab, st.data(), st.size() * sizeof(SceneRec), "scene table"))) return s;
+  if ((s = upload(ctx, ctx->units, P.units.data(), P.units.size() * sizeof(UnitRec), "unit table"))) return s;
+  if ((s = upload(ctx, ctx->chunk_begin, P.chunk_begin.data(), P.chunk_begin.size() * sizeof(int64_t),
+                  "chunk table")))
+    return s;
+  if ((s = upload(ctx, ctx->sources, P.sources.data(), P.sources.size() * sizeof(SourceRec), "sources"))) return s;
+  if ((s = upload(ctx, ctx->lines, P.lines.data(), P.lines.size() * sizeof(float), "lines"))) return s;
+  if ((s = upload(ctx, ctx->regions, P.regions.data(), P.regions.size() * sizeof(RegionRec), "regions"))) return s;
+  const int64_t tally_words = static_cast<int64_t>(nu) * kT_Slots;
+  const int64_t spec_words = P.spectrum ? static_cast<int64_t>(nu) * P.n_channels : 0;
+  if ((s = ensure(ctx, ctx->tally, tally_words * 8, "tally"))) return s;
+  if ((s = ensure(ctx, ctx->spectra, std::max<int64_t>(spec_words, 1) * 8, "spectra"))) return s;
+  if ((s = ensure(ctx, ctx->cursor, 64, "cursor"))) return s;
+
+  TransportParams K{};
+  K.units = static_cast<const UnitRec*>(ctx->units.p);
+  K.chunk_begin = static_cast<const int64_t*>(ctx->chunk_begin.p);
+  K.n_units = nu;
+  K.chunk = static_cast<int32_t>(64 * ctx->claim);
+  K.scenes = static_cast<const SceneRec*>(ctx->scene_tab.p);
+  K.sources = static_cast<const SourceRec*>(ctx->sources.p);
+  K.lines = static_cast<const float*>(ctx->lines.p);
+  K.regions = static_cast<const RegionRec*>(ctx->regions.p);
+  K.xs = static_cast<const float*>(ctx->xs.p);
+  K.n_e = ctx->nE;
+  K.ln_e0 = static_cast<float>(ctx->lnE0);
+  K.inv_dlne = static_cast<float>(1.0 / ctx->dlnE);
+  K.e_cut = static_cast<float>(exp(ctx->lnE0));
+  K.tally = static_cast<unsigned long long*>(ctx->tally.p);
+  K.spectra = P.spectrum ? static_cast<unsigned long long*>(ctx->spectra.p) : nullptr;
+  K.n_channels = P.n_channels;
+  K.inv_channel_kev = P.spectrum ? 1.0f / P.channel_keV : 0.0f;
+  K.cursor = static_cast<unsigned long long*>(ctx->cursor.p);
+  K.seed_lo = static_cast<uint32_t>(seed);
+  K.seed_hi = static_cast<uint32_t>(seed >> 32);
+  K.max_steps = static_cast<int32_t>(ctx->max_steps);
+  K.stack_depth = P.depth;
+  K.period = static_cast<int32_t>(ctx->period);
+
+  const int variant = (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0);
+  const int block = static_cast<int>(ctx->block);
+  int grid = static_cast<int>(ctx->grid);
+  if (grid <= 0) {
+    int per_cu = 0;
+    HIP_TRY(transport_occupancy(variant, block, P.depth, &per_cu), "occupancy");
+    if (per_cu < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");
+    grid = per_cu * ctx->n_cu;
+  }
+
+  // graph key: everything baked into the captured launches
+  std::vector<uint8_t> key(sizeof(TransportParams) + 4 * sizeof(int64_t));
+  memcpy(key.data(), &K, sizeof K);
+  int64_t extra[4] = {variant, grid, block, static_cast<int64_t>(tally_words + spec_words)};
+  memcpy(key.data() + sizeof K, extra, sizeof extra);
+
+  if (!ctx->ev0) HIP_TRY(hipEventCreate(&ctx->ev0), "event");
+  if (!ctx->ev1) HIP_TRY(hipEventCreate(&ctx->ev1), "event");
+  auto enqueue = [&]() -> hipError_t {
+    hipError_t e = fill_u64(K.tally, tally_words, 0, ctx->stream);
+    if (e == hipSuccess && spec_words) e = fill_u64(K.spectra, spec_words, 0, ctx->stream);
+    if (e == hipSuccess) e = fill_u64(K.cursor, 1, 0, ctx->stream);
+    if (e == hipSuccess)
+      e = locate_units(static_cast<UnitRec*>(ctx->units.p), nu,
+                       static_cast<const SceneRec*>(ctx->scene_tab.p),
+                       static_cast<const SourceRec*>(ctx->sources.p), P.depth, ctx->stream);
+    if (e == hipSuccess) e = transport_launch(K, variant, grid, block, ctx->stream);
+    return e;
+  };
+  // the enqueue below is wrapped by two events: the launch duration
+  if (!ctx->graphs) {
+    hipError_t e = fill_u64(K.tally, tally_words, 0, ctx->stream);
+    if (e == hipSuccess && spec_words) e = fill_u64(K.spectra, spec_words, 0, ctx->stream);
+    if (e == hipSuccess) e = fill_u64(K.cursor, 1, 0, ctx->stream);
+    if (e == hipSuccess)
+      e = locate_units(static_cast<UnitRec*>(ctx->units.p), nu,
+                       static_cast<const SceneRec*>(ctx->scene_tab.p),
+                       static_cast<const SourceRec*>(ctx->sources.p), P.depth, ctx->stream);
+    HIP_TRY(e, "set-up kernels");
+  }
+  HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream), "event");
+  if (ctx->graphs) {
+    if (!ctx->graph || ctx->graph_key != key) {
+      if (ctx->graph) {
+        hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "capture");
+      hipError_t ce = enqueue();
+      hipError_t ee = hipStreamEndCapture(ctx->stream, &g);
+      if (ce != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return hip_err(ctx, ce, "capture transport");
+      }
+      HIP_TRY(ee, "end capture");
+      hipError_t ie = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIP_TRY(ie, "graph instantiate");
+      ctx->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->graph, ctx->stream), "graph launch");
+  } else {
+    HIP_TRY(transport_launch(K, variant, grid, block, ctx->stream), "transport launch");
+  }
+  HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream), "event");
+
+  // read back
+  const size_t need = static_cast<size_t>(tally_words) * 8;
+  if (ctx->h_tally_cap < need) {
+    if (ctx->h_tally) hipHostFree(ctx->h_tally);
+    ctx->h_tally = nullptr;
+    HIP_TRY(hipHostMalloc(&ctx->h_tally, need), "pinned tally");
+    ctx->h_tally_cap = need;
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->h_tally, K.tally, need, hipMemcpyDeviceToHost, ctx->stream), "tally D2H");
+  std::vector<unsigned long long> spec;
+  if (spec_words) {
+    spec.resize(static_cast<size_t>(spec_words));
+    HIP_TRY(hipMemcpyAsync(spec.data(), K.spectra, spec_words * 8, hipMemcpyDeviceToHost, ctx->stream),
+            "spectra D2H");
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "transport");
+  {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1), "event time");
+    ctx->last_ms = ms;
+    if (elapsed_ms) *elapsed_ms = ms;
+  }
+
+  const unsigned long long* T = static_cast<const unsigned long long*>(ctx->h_tally);
+  gadep_counters cnt{};
+  for (int32_t u = 0; u < nu; ++u) {
+    const unsigned long long* Tu = T + static_cast<int64_t>(u) * kT_Slots;
+    if (out) {
+      gadep_tally& t = out[u];
+      to_tally(Tu, t);
+      if (t.spectrum && spec_words)
+        memcpy(t.spectrum, spec.data() + static_cast<int64_t>(u) * P.n_channels, P.n_channels * 8);
+    }
+    if (P.grad && (grads || grads_var)) {
+      const double n = static_cast<double>(Tu[kT_Hist]);
+      for (int32_t g = 0; g < n_grad_cols; ++g) {
+        const double m1 = n > 0 ? static_cast<double>(static_cast<int64_t>(Tu[kT_FepScore + g])) / kScoreFix / n : 0.0;
+        const double m2 = n > 0 ? static_cast<double>(Tu[kT_FepScore2 + g]) / kScore2Fix / n : 0.0;
+        if (grads) grads[static_cast<int64_t>(u) * n_grad_cols + g] = m1;
+        if (grads_var) grads_var[static_cast<int64_t>(u) * n_grad_cols + g] = n > 1 ? std::max(0.0, m2 - m1 * m1) / n : 0.0;
+      }
+    }
+    const unsigned long long* ev = Tu + kT_Ev;
+    cnt.segments += ev[kEv_Segments];
+    cnt.crossings += ev[kEv_Crossings];
+    cnt.node_visits += ev[kEv_NodeVisits];
+    cnt.tri_tests += ev[kEv_TriTests];
+    cnt.photo += ev[kEv_Photo];
+    cnt.compton += ev[kEv_Compton];
+    cnt.coherent += ev[kEv_Coherent];
+    cnt.rng_calls += ev[kEv_Rng];
+    cnt.locates += ev[kEv_Locates];
+    cnt.emissions += ev[kEv_Emissions];
+  }
+  if (ctx->counters) {
+    ctx->last_counters = cnt;
+    ctx->have_counters = true;
+  }
+  return GADEP_OK;
+}
+
+gadep_job single_job(const gadep_source* src, const double* energies, int32_t n_energies,
+                     int64_t n, int64_t first, const float* scales, int32_t n_scales) {
+  gadep_job j{};
+  j.src = *src;
+  j.energies_keV = energies;
+  j.n_energies = n_energies;
+  j.n_histories = n;
+  j.first_history = first;
+  j.scales = scales;
+  j.n_scales = n_scales;
+  j.scene = 0;
+  j.stream = 0;
+  return j;
+}
+
+}  // namespace
+
+// ============================================================================
+// C interface
+
+extern "C" {
+
+gadep_status gadep_create(int device, void* hip_stream, gadep_ctx** out) {
+  if (!out) return GADEP_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return GADEP_E_HIP;
+  if (device < 0 || device >= n) return GADEP_E_ARG;
+  auto* ctx = new gadep_ctx();
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return GADEP_E_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete ctx;
+    return GADEP_E_HIP;
+  }
+  ctx->n_cu = prop.multiProcessorCount;
+  if (hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+      delete ctx;
+      return GADEP_E_HIP;
+    }
+    ctx->own_stream = true;
+  }
+  *out = ctx;
+  return GADEP_OK;
+}
+
+void gadep_destroy(gadep_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->graph) hipGraphExecDestroy(ctx->graph);
+  for (auto& sc : ctx->scenes)
+    if (sc) {
+      if (sc->d_nodes) hipFree(sc->d_nodes);
+      if (sc->d_tris) hipFree(sc->d_tris);
+    }
+  for (DevBuf* b : {&ctx->xs, &ctx->units, &ctx->chunk_begin, &ctx->scene_tab, &ctx->sources,
+                    &ctx->lines, &ctx->regions, &ctx->tally, &ctx->spectra, &ctx->cursor})
+    free_buf(*b);
+  if (ctx->h_tally) hipHostFree(ctx->h_tally);
+  if (ctx->ev0) hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) hipEventDestroy(ctx->ev1);
+  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* gadep_last_error(const gadep_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t v) {
+  if (!ctx) return GADEP_E_ARG;
+  switch (option) {
+    case GADEP_OPT_MAX_STEPS:
+      if (v < 1 || v > (1 << 30)) return set_err(ctx, GADEP_E_ARG, "max_steps out of range");
+      ctx->max_steps = v;
+      return GADEP_OK;
+    case GADEP_OPT_BLOCK:
+      if (v < 64 || v > 256 || v % 64) return set_err(ctx, GADEP_E_ARG, "block must be 64, 128, 192 or 256");
+      ctx->block = v;
+      return GADEP_OK;
+    case GADEP_OPT_PERIOD:
+      if (v < 0 || v > 1024) return set_err(ctx, GADEP_E_ARG, "period out of range");
+      ctx->period = v;
+      return GADEP_OK;
+    case GADEP_OPT_CLAIM:
+      if (v < 1 || v > (1 << 20)) return set_err(ctx, GADEP_E_ARG, "claim out of range");
+      ctx->claim = v;
+      return GADEP_OK;
+    case GADEP_OPT_VALIDATE:
+      ctx->validate = v ? 1 : 0;
+      return GADEP_OK;
+    case GADEP_OPT_MIN_GAP_NM:
+      if (v < 0) return set_err(ctx, GADEP_E_ARG, "min gap must be >= 0");
+      ctx->min_gap_nm = v;
+      return GADEP_OK;
+    case GADEP_OPT_GRAPHS:
+      ctx->graphs = v ? 1 : 0;
+      return GADEP_OK;
+    case GADEP_OPT_COUNTERS:
+      ctx->counters = v ? 1 : 0;
+      return GADEP_OK;
+    case GADEP_OPT_GRID:
+      if (v < 0 || v > (1 << 20)) return set_err(ctx, GADEP_E_ARG, "grid out of range");
+      ctx->grid = v;
+      return GADEP_OK;
+    default:
+      return set_err(ctx, GADEP_E_ARG, "unknown option");
+  }
+}
+
+gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* v) {
+  if (!ctx || !v) return GADEP_E_ARG;
+  switch (option) {
+    case GADEP_OPT_MAX_STEPS: *v = ctx->max_steps; return GADEP_OK;
+    case GADEP_OPT_BLOCK: *v = ctx->block; return GADEP_OK;
+    case GADEP_OPT_PERIOD: *v = ctx->period; return GADEP_OK;
+    case GADEP_OPT_CLAIM: *v = ctx->claim; return GADEP_OK;
+    case GADEP_OPT_VALIDATE: *v = ctx->validate; return GADEP_OK;
+    case GADEP_OPT_MIN_GAP_NM: *v = ctx->min_gap_nm; return GADEP_OK;
+    case GADEP_OPT_GRAPHS: *v = ctx->graphs; return GADEP_OK;
+    case GADEP_OPT_COUNTERS: *v = ctx->counters; return GADEP_OK;
+    case GADEP_OPT_GRID: *v = ctx->grid; return GADEP_OK;
+    default: return GADEP_E_ARG;
+  }
+}
+
+gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, int64_t nv,
+                              const int32_t* tri, const int32_t* tri_region, int64_t nt,
+                              const gadep_region* regions, int32_t n_regions) {
+  if (!ctx) return GADEP_E_ARG;
+  if (scene < 0 || scene >= GADEP_MAX_SCENES) return set_err(ctx, GADEP_E_ARG, "scene slot out of range");
+  if (!regions) return set_err(ctx, GADEP_E_ARG, "regions is NULL");
+  for (int32_t r = 0; r < n_regions; ++r) {
+    const gadep_region& R = regions[r];
+    if (R.material < 0 || !(R.density_g_cm3 >= 0) || !std::isfinite(R.density_g_cm3) ||
+        R.scale_group < -1 || R.scale_group >= GADEP_MAX_GROUPS)
+      return set_err(ctx, GADEP_E_ARG, "region " + std::to_string(r) + ": bad material, density or group");
+  }
+  PreparedMesh pm;
+  std::string err;
+  int rc = prepare_mesh(xyz, nv, tri, tri_region, nt, n_regions, ctx->min_gap_nm * 1e-6,
+                        ctx->validate != 0, 0, pm, err);
+  if (rc != GADEP_OK) return set_err(ctx, static_cast<gadep_status>(rc), err);
+  if (static_cast<int32_t>(ctx->scenes.size()) <= scene) ctx->scenes.resize(scene + 1);
+  if (!ctx->scenes[scene]) ctx->scenes[scene].reset(new Scene());
+  Scene& sc = *ctx->scenes[scene];
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "sync");
+  if (sc.d_nodes) hipFree(sc.d_nodes);
+  if (sc.d_tris) hipFree(sc.d_tris);
+  sc.d_nodes = sc.d_tris = nullptr;
+  sc.loaded = false;
+  HIP_TRY(hipMalloc(&sc.d_nodes, pm.nodes.size() * sizeof(BvhNode)), "alloc nodes");
+  HIP_TRY(hipMalloc(&sc.d_tris, pm.tris.size() * sizeof(TriRec)), "alloc facets");
+  HIP_TRY(hipMemcpy(sc.d_nodes, pm.nodes.data(), pm.nodes.size() * sizeof(BvhNode), hipMemcpyHostToDevice),
+          "upload nodes");
+  HIP_TRY(hipMemcpy(sc.d_tris, pm.tris.data(), pm.tris.size() * sizeof(TriRec), hipMemcpyHostToDevice),
+          "upload facets");
+  sc.regions.assign(regions, regions + n_regions);
+  sc.n_regions = n_regions;
+  sc.depth = pm.depth;
+  sc.n_tri = nt;
+  sc.n_nodes = static_cast<int64_t>(pm.nodes.size());
+  sc.loaded = true;
+  if (ctx->graph) {
+    hipGraphExecDestroy(ctx->graph);
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+  }
+  return GADEP_OK;
+}
+
+gadep_status gadep_load_mesh(gadep_ctx* ctx, const float* xyz, int64_t nv, const int32_t* tri,
+                             const int32_t* tri_region, int64_t nt, const gadep_region* regions,
+                             int32_t n_regions) {
+  return gadep_load_scene(ctx, 0, xyz, nv, tri, tri_region, nt, regions, n_regions);
+}
+
+gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0, double dlnE, int32_t nE,
+                          const float* photo, const float* compton, const float* coherent) {
+  if (!ctx) return GADEP_E_ARG;
+  if (material < 0 || material >= 1024) return set_err(ctx, GADEP_E_ARG, "material id out of range");
+  if (nE < 2 || !(dlnE > 0) || !std::isfinite(lnE0) || !std::isfinite(dlnE))
+    return set_err(ctx, GADEP_E_XS, "bad energy grid");
+  if (ctx->grid_set && (lnE0 != ctx->lnE0 || dlnE != ctx->dlnE || nE != ctx->nE))
+    return set_err(ctx, GADEP_E_XS, "every material must use the same energy grid");
+  Material m;
+  const float* src[3] = {photo, compton, coherent};
+  for (int i = 0; i < 3; ++i) {
+    m.ln[i].assign(nE, -200.0f);
+    if (!src[i]) continue;
+    int npos = 0;
+    for (int32_t k = 0; k < nE; ++k) {
+      if (!(src[i][k] >= 0) || !std::isfinite(src[i][k]))
+        return set_err(ctx, GADEP_E_XS, "cross sections must be finite and >= 0");
+      npos += src[i][k] > 0;
+    }
+    if (npos == 0) continue;
+    if (npos != nE) return set_err(ctx, GADEP_E_XS, "a partial must be all-positive or all-zero");
+    for (int32_t k = 0; k < nE; ++k) m.ln[i][k] = logf(src[i][k]);
+  }
+  m.set = true;
+  if (static_cast<int32_t>(ctx->mats.size()) <= material) ctx->mats.resize(material + 1);
+  ctx->mats[material] = std::move(m);
+  ctx->grid_set = true;
+  ctx->lnE0 = lnE0;
+  ctx->dlnE = dlnE;
+  ctx->nE = nE;
+  ctx->xs_dirty = true;
+  return GADEP_OK;
+}
+
+gadep_status gadep_set_scales(gadep_ctx* ctx, const float* scales, int32_t n) {
+  if (!ctx) return GADEP_E_ARG;
+  if (n < 0 || n > GADEP_MAX_GROUPS || (n > 0 && !scales)) return set_err(ctx, GADEP_E_ARG, "bad scales");
+  for (int32_t g = 0; g < n; ++g)
+    if (!(scales[g] > 0) || !std::isfinite(scales[g])) return set_err(ctx, GADEP_E_ARG, "scales must be > 0");
+  for (int32_t g = 0; g < GADEP_MAX_GROUPS; ++g) ctx->scales[g] = g < n ? scales[g] : 1.0f;
+  return GADEP_OK;
+}
+
+gadep_status gadep_run(gadep_ctx* ctx, const gadep_source* src, const double* energies,
+                       int32_t n_energies, int64_t n, uint64_t seed, int64_t first, gadep_tally* out) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!src || !out) return set_err(ctx, GADEP_E_ARG, "null source or output");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  gadep_job j = single_job(src, energies, n_energies, n, first, ctx->scales.data(), GADEP_MAX_GROUPS);
+  Plan P;
+  gadep_status s = plan_jobs(ctx, &j, 1, out, false, P);
+  if (s) return s;
+  return execute(ctx, P, seed, out, nullptr, nullptr, 0);
+}
+
+gadep_status gadep_run_grad(gadep_ctx* ctx, const gadep_source* src, const double* energies,
+                            int32_t n_energies, int64_t n, uint64_t seed, int64_t first,
+                            const float* scales, int32_t n_scales, gadep_tally* out, double* dfepe_ds,
+                            double* dfepe_ds_var) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!src || !out) return set_err(ctx, GADEP_E_ARG, "null source or output");
+  if (n_scales < 1 || n_scales > GADEP_MAX_GROUPS || !scales)
+    return set_err(ctx, GADEP_E_ARG, "run_grad needs 1..8 scales");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  gadep_job j = single_job(src, energies, n_energies, n, first, scales, n_scales);
+  Plan P;
+  gadep_status s = plan_jobs(ctx, &j, 1, out, true, P);
+  if (s) return s;
+  return execute(ctx, P, seed, out, dfepe_ds, dfepe_ds_var, n_scales);
+}
+
+gadep_status gadep_run_batch(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs, uint64_t seed,
+                             gadep_tally* out, double* grads, double* grads_var) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!out) return set_err(ctx, GADEP_E_ARG, "null output");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  Plan P;
+  const bool grad = grads || grads_var;
+  gadep_status s = plan_jobs(ctx, jobs, n_jobs, out, grad, P);
+  if (s) return s;
+  return execute(ctx, P, seed, out, grads, grads_var, GADEP_MAX_GROUPS);
+}
+
+gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs, int64_t pilot,
+                            int32_t* block_out, int32_t* period_out, int32_t* claim_out) {
+  if (!ctx) return GADEP_E_ARG;
+  if (pilot < 1) return set_err(ctx, GADEP_E_ARG, "pilot_histories must be >= 1");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  std::vector<gadep_job> pj(jobs, jobs + std::max(0, n_jobs));
+  int64_t total = 0;
+  for (auto& j : pj) total += j.n_histories * std::max(1, j.n_energies);
+  // scale every job down to about `pilot` histories in total, keeping the mix
+  for (auto& j : pj)
+    if (total > pilot) j.n_histories = std::max<int64_t>(1, j.n_histories * pilot / total);
+  size_t units = 0;
+  for (auto& j : pj) units += std::max(1, j.n_energies);
+  std::vector<gadep_tally> out(units);
+  const int64_t saved_block = ctx->block, saved_claim = ctx->claim, saved_graphs = ctx->graphs;
+  ctx->graphs = 0;
+  float best = INFINITY;
+  int64_t best_block = saved_block, best_claim = saved_claim;
+  const int64_t blocks[] = {64, 128, 256};
+  const int64_t claims[] = {4, 16, 64};
+  for (int64_t b : blocks)
+    for (int64_t c : claims) {
+      ctx->block = b;
+      ctx->claim = c;
+      Plan P;
+      gadep_status s = plan_jobs(ctx, pj.data(), static_cast<int32_t>(pj.size()), out.data(), false, P);
+      if (s) {
+        ctx->block = saved_block, ctx->claim = saved_claim, ctx->graphs = saved_graphs;
+        return s;
+      }
+      float ms = 0, ms2 = 0;
+      s = execute(ctx, P, 12345, out.data(), nullptr, nullptr, 0, &ms);  // warm-up
+      if (!s) s = execute(ctx, P, 12345, out.data(), nullptr, nullptr, 0, &ms2);
+      if (s) {
+        ctx->block = saved_block, ctx->claim = saved_claim, ctx->graphs = saved_graphs;
+        return s;
+      }
+      if (ms2 < best) {
+        best = ms2;
+        best_block = b;
+        best_claim = c;
+      }
+    }
+  ctx->block = best_block;
+  ctx->claim = best_claim;
+  ctx->graphs = saved_graphs;
+  if (block_out) *block_out = static_cast<int32_t>(best_block);
+  if (period_out) *period_out = static_cast<int32_t>(ctx->period);
+  if (claim_out) *claim_out = static_cast<int32_t>(best_claim);
+  return GADEP_OK;
+}
+
+gadep_status gadep_get_last_launch_ms(const gadep_ctx* ctx, double* ms) {
+  if (!ctx || !ms) return GADEP_E_ARG;
+  if (ctx->last_ms < 0) return GADEP_E_STATE;
+  *ms = ctx->last_ms;
+  return GADEP_OK;
+}
+
+gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out) {
+  if (!ctx || !out) return GADEP_E_ARG;
+  if (!ctx->have_counters) return GADEP_E_STATE;
+  *out = ctx->last_counters;
+  return GADEP_OK;
+}
+
+gadep_status gadep_broaden_dev(gadep_ctx* ctx, const double* in_dev, double* out_dev,
+                               int32_t n_spectra, int32_t n_channels, double w, double a, double b) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!in_dev || !out_dev || n_spectra < 1 || n_channels < 1 || !(w > 0) || !(a >= 0) || !(b >= 0) ||
+      !(a + b > 0))
+    return set_err(ctx, GADEP_E_ARG, "broaden: bad arguments");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(broaden(in_dev, out_dev, n_spectra, n_channels, w, a, b, ctx->stream), "broaden");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "broaden");
+  return GADEP_OK;
+}
+
+static gadep_status scene_rec(gadep_ctx* ctx, int32_t scene, SceneRec& sr) {
+  if (scene < 0 || scene >= static_cast<int32_t>(ctx->scenes.size()) || !ctx->scenes[scene] ||
+      !ctx->scenes[scene]->loaded)
+    return set_err(ctx, GADEP_E_STATE, "scene not loaded");
+  const Scene& sc = *ctx->scenes[scene];
+  sr.nodes = static_cast<const BvhNode*>(sc.d_nodes);
+  sr.tris = static_cast<const TriRec*>(sc.d_tris);
+  sr.n_regions = sc.n_regions;
+  sr.depth = sc.depth;
+  return GADEP_OK;
+}
+
+gadep_status gadep_raycast(gadep_ctx* ctx, int32_t scene, const float* o, const float* d,
+                           const int32_t* region, int64_t n, float* t, int32_t* tri,
+                           int32_t* region_after) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!o || !d || !t || !tri || !region_after || n < 0) return set_err(ctx, GADEP_E_ARG, "raycast: bad arguments");
+  if (n == 0) return GADEP_OK;
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  SceneRec sr;
+  gadep_status s = scene_rec(ctx, scene, sr);
+  if (s) return s;
+  void* buf = nullptr;
+  const size_t nb = static_cast<size_t>(n);
+  const size_t bytes = nb * (3 + 3 + 1 + 1 + 1 + 1) * 4;
+  HIP_TRY(hipMalloc(&buf, bytes), "raycast buffers");
+  float* d_o = static_cast<float*>(buf);
+  float* d_d = d_o + 3 * nb;
+  int32_t* d_r = reinterpret_cast<int32_t*>(d_d + 3 * nb);
+  float* d_t = reinterpret_cast<float*>(d_r + nb);
+  int32_t* d_tri = reinterpret_cast<int32_t*>(d_t + nb);
+  int32_t* d_ra = d_tri + nb;
+  hipError_t e = hipMemcpyAsync(d_o, o, 12 * nb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_d, d, 12 * nb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && region) e = hipMemcpyAsync(d_r, region, 4 * nb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = raycast(sr, d_o, d_d, region ? d_r : nullptr, n, d_t, d_tri, d_ra, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(t, d_t, 4 * nb, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(tri, d_tri, 4 * nb, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(region_after, d_ra, 4 * nb, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  hipFree(buf);
+  if (e != hipSuccess) return hip_err(ctx, e, "raycast");
+  return GADEP_OK;
+}
+
+gadep_status gadep_locate(gadep_ctx* ctx, int32_t scene, const float* p, int64_t n, int32_t* region) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!p || !region || n < 0) return set_err(ctx, GADEP_E_ARG, "locate: bad arguments");
+  if (n == 0) return GADEP_OK;
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  SceneRec sr;
+  gadep_status s = scene_rec(ctx, scene, sr);
+  if (s) return s;
+  void* buf = nullptr;
+  const size_t nb = static_cast<size_t>(n);
+  HIP_TRY(hipMalloc(&buf, nb * 16), "locate buffers");
+  float* d_p = static_cast<float*>(buf);
+  int32_t* d_r = reinterpret_cast<int32_t*>(d_p + 3 * nb);
+  hipError_t e = hipMemcpyAsync(d_p, p, 12 * nb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = locate(sr, d_p, n, d_r, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(region, d_r, 4 * nb, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  hipFree(buf);
+  if (e != hipSuccess) return hip_err(ctx, e, "locate");
+  return GADEP_OK;
+}
+
+gadep_status gadep_mesh_prepare(const float* xyz, int64_t nv, const int32_t* tri,
+                                const int32_t* tri_region, int64_t nt, int32_t n_regions,
+                                double min_gap_mm, int32_t validate, int32_t bvh_method,
+                                int32_t* tri_outside, int32_t* tri_shell, void* nodes_out,
+                                int64_t cap_nodes, int32_t* tri_order, gadep_mesh_info* info,
+                                char* err, int32_t err_len) {
+  PreparedMesh pm;
+  std::string e;
+  int rc = prepare_mesh(xyz, nv, tri, tri_region, nt, n_regions, min_gap_mm, validate != 0,
+                        bvh_method, pm, e);
+  if (err && err_len > 0) {
+    strncpy(err, e.c_str(), static_cast<size_t>(err_len) - 1);
+    err[err_len - 1] = 0;
+  }
+  if (rc != GADEP_OK) return static_cast<gadep_status>(rc);
+  if (tri_outside) memcpy(tri_outside, pm.outside.data(), pm.outside.size() * 4);
+  if (tri_shell) memcpy(tri_shell, pm.shell.data(), pm.shell.size() * 4);
+  if (tri_order) memcpy(tri_order, pm.order.data(), pm.order.size() * 4);
+  if (nodes_out) {
+    if (cap_nodes < static_cast<int64_t>(pm.nodes.size())) return GADEP_E_ARG;
+    memcpy(nodes_out, pm.nodes.data(), pm.nodes.size() * sizeof(BvhNode));
+  }
+  if (info) {
+    info->n_shells = pm.n_shells;
+    info->genus_max = pm.genus_max;
+    info->n_nodes = static_cast<int64_t>(pm.nodes.size());
+    info->depth = pm.depth;
+    info->sah_cost = pm.sah;
+    info->min_gap_mm = pm.min_gap;
+  }
+  return GADEP_OK;
+}
+
+}  // extern "C"

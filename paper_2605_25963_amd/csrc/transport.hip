@@ -1,0 +1,759 @@
+// gfx950 kernels of the photon-transport path.
+//
+// One persistent grid transports every history of every (job, energy) unit.
+// Per lane, a history runs segment by segment (paper Sec. 2.4.1-2.4.3):
+//   emission -> free path in mean free paths -> closest boundary on the BVH
+//   (watertight FP32 test, region-consistency filter) -> either cross the
+//   boundary (region from the facet's inside/outside pair) or interact
+//   (photoelectric, Klein-Nishina Compton, Thomson coherent) -> score.
+// Work is claimed per wavefront in chunks of consecutive histories of one
+// unit; a lane whose history ends immediately starts the next history of the
+// chunk, and a wavefront only drains (waits for its live lanes) when its next
+// chunk belongs to another unit.  Tallies are integer (fixed point for sums),
+// accumulated per wavefront in LDS and flushed with one global atomic per
+// slot, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "gadep_internal.h"
+
+namespace gadep {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// closest hit with the region-consistency filter
+
+struct HitOut {
+  float t;
+  int slot;
+  int region_after;
+};
+
+// Closest facet with 0 < t <= tmax, skipping slot `exclude`.  A candidate is
+// accepted only if it is consistent with the current region: entering
+// requires outside == cur, leaving requires inside == cur (cur < 0: accept
+// all).  Returns true on a hit; `glitch` is set when a rejected candidate lay
+// nearer than the accepted one.
+template <bool COUNT>
+__device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, float tmax,
+                                            int exclude, int cur, int* stack, int stride,
+                                            HitOut& h, bool& glitch, uint32_t& nvis,
+                                            uint32_t& ntri) {
+  float best = tmax;
+  int best_slot = -1;
+  int best_reg = 0;
+  float rejected = INFINITY;
+  const TriRec* __restrict__ tris = sc.tris;
+  float tm = tmax;
+  const uint32_t v = traverse(sc.nodes, r, tm, stack, stride, sc.depth, [&](int first, int count,
+                                                                             float tcur) {
+    for (int k = 0; k < count; ++k) {
+      const int slot = first + k;
+      if (COUNT) ntri++;
+      if (slot == exclude) continue;
+      float4 a, b, c;
+      load_tri(tris, slot, a, b, c);
+      float t;
+      bool enter;
+      if (wt_test(r, a, b, c, tcur, t, enter) == kWtMiss) continue;
+      const uint32_t regs = __float_as_uint(c.y);
+      const int inside = static_cast<int>(regs & 0xFFFFu);
+      const int outside = static_cast<int>(regs >> 16);
+      if (cur >= 0 && (enter ? outside : inside) != cur) {
+        rejected = fminf(rejected, t);
+        continue;
+      }
+      tcur = t;
+      best = t;
+      best_slot = slot;
+      best_reg = enter ? inside : outside;
+    }
+    return tcur;
+  });
+  if (COUNT) nvis += v;
+  glitch = rejected < best;
+  if (best_slot < 0) return false;
+  h.t = best;
+  h.slot = best_slot;
+  h.region_after = best_reg;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// ray-parity localization (Sec. 2.4.2): count crossings per closed geometry
+// along a probe ray; odd => inside; the odd geometry crossed first contains
+// the point; none odd => world.  Two traversals: the parity mask, then the
+// nearest crossing among odd regions.  A probe touching an edge, vertex or
+// facet plane is discarded and the next probe direction is tried.
+
+__constant__ float kProbe[4][3] = {
+    {0.4830462f, 0.3714437f, 0.7929236f},
+    {-0.6651950f, 0.5306224f, -0.5252790f},
+    {0.2079117f, -0.8899187f, 0.4058776f},
+    {-0.3550744f, -0.4253337f, -0.8325470f},
+};
+
+template <bool COUNT>
+__device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, int* stack,
+                             int stride, uint32_t& nvis, uint32_t& ntri) {
+  const TriRec* __restrict__ tris = sc.tris;
+  for (int k = 0; k < 4; ++k) {
+    const Ray r = make_ray(px, py, pz, kProbe[k][0], kProbe[k][1], kProbe[k][2]);
+    uint64_t parity = 0;
+    bool degenerate = false;
+    float tm = INFINITY;
+    uint32_t v = traverse(sc.nodes, r, tm, stack, stride, sc.depth, [&](int first, int count,
+                                                                        float tcur) {
+      for (int j = 0; j < count; ++j) {
+        float4 a, b, c;
+        load_tri(tris, first + j, a, b, c);
+        float t;
+        bool enter;
+        const int w = wt_test(r, a, b, c, INFINITY, t, enter);
+        if (COUNT) ntri++;
+        if (w == kWtMiss) continue;
+        if (w == kWtDegenerate) degenerate = true;
+        parity ^= 1ull << (__float_as_uint(c.y) & 63u);
+      }
+      return tcur;
+    });
+    if (COUNT) nvis += v;
+    if (degenerate) continue;
+    if (parity == 0) return 0;
+    float best = INFINITY;
+    int best_reg = 0;
+    tm = INFINITY;
+    v = traverse(sc.nodes, r, tm, stack, stride, sc.depth, [&](int first, int count, float tcur) {
+      for (int j = 0; j < count; ++j) {
+        float4 a, b, c;
+        load_tri(tris, first + j, a, b, c);
+        const int reg = static_cast<int>(__float_as_uint(c.y) & 0xFFFFu);
+        if (!((parity >> reg) & 1ull)) continue;
+        float t;
+        bool enter;
+        if (COUNT) ntri++;
+        if (wt_test(r, a, b, c, tcur, t, enter) == kWtMiss) continue;
+        if (t < best || (t == best && reg < best_reg)) {
+          best = t;
+          best_reg = reg;
+        }
+        tcur = t;
+      }
+      return tcur;
+    });
+    if (COUNT) nvis += v;
+    return best_reg;
+  }
+  return -1;
+}
+
+// ---------------------------------------------------------------------------
+// physics helpers
+
+struct Xs {
+  int k;
+  float w;
+};
+
+__device__ __forceinline__ Xs xs_index(float E, float ln_e0, float inv_dlne, int n_e) {
+  const float x = (__logf(E) - ln_e0) * inv_dlne;
+  int k = static_cast<int>(floorf(x));
+  k = k < 0 ? 0 : (k > n_e - 2 ? n_e - 2 : k);
+  float w = x - static_cast<float>(k);
+  w = fminf(fmaxf(w, 0.0f), 1.0f);
+  return {k, w};
+}
+
+// partial linear attenuation [1/mm] of a region: log-log interpolation of
+// each partial, mu_i = mult * exp(lerp(ln(mu/rho)_i))
+__device__ __forceinline__ void xs_mu(const float4* __restrict__ xs, int n_e, const RegionRec& rr,
+                                      Xs ix, float& mp, float& mc, float& mh) {
+  if (rr.mult > 0.0f) {
+    const float4 lo = xs[rr.material * n_e + ix.k];
+    const float4 hi = xs[rr.material * n_e + ix.k + 1];
+    mp = rr.mult * __expf(fmaf(ix.w, hi.x - lo.x, lo.x));
+    mc = rr.mult * __expf(fmaf(ix.w, hi.y - lo.y, lo.y));
+    mh = rr.mult * __expf(fmaf(ix.w, hi.z - lo.z, lo.z));
+  } else {
+    mp = mc = mh = 0.0f;
+  }
+}
+
+// New direction at polar cosine ct and azimuth 2 pi u about (dx, dy, dz), in an
+// orthonormal basis built branch-free from the direction (Duff et al., JCGT
+// 2017).  sin/cos of 2 pi u come from the hardware sine, which takes
+// revolutions.
+__device__ __forceinline__ void turn(float& dx, float& dy, float& dz, float ct, float u) {
+  const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+  const float cp = __builtin_amdgcn_cosf(u), sp = __builtin_amdgcn_sinf(u);
+  const float s = copysignf(1.0f, dz);
+  const float a = -1.0f / (s + dz);
+  const float b = dx * dy * a;
+  const float b1x = 1.0f + s * dx * dx * a, b1y = s * b, b1z = -s * dx;
+  const float b2x = b, b2y = s + dy * dy * a, b2z = -dy;
+  const float ux = st * cp, uy = st * sp;
+  float nx = ct * dx + ux * b1x + uy * b2x;
+  float ny = ct * dy + ux * b1y + uy * b2y;
+  float nz = ct * dz + ux * b1z + uy * b2z;
+  const float inv = rsqrtf(nx * nx + ny * ny + nz * nz);
+  dx = nx * inv;
+  dy = ny * inv;
+  dz = nz * inv;
+}
+
+// ---------------------------------------------------------------------------
+// wavefront helpers
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) x += __shfl_xor(x, m, kWave);
+  return x;
+}
+
+__device__ __forceinline__ unsigned long long fx(double v, double scale) {
+  return static_cast<unsigned long long>(__double2ll_rn(v * scale));
+}
+
+// ---------------------------------------------------------------------------
+// transport kernel
+
+template <bool GRAD, bool SPEC, bool COUNT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) transport_kernel(TransportParams P) {
+  extern __shared__ unsigned long long smem[];
+  const int lane = static_cast<int>(__lane_id());
+  const int wave = static_cast<int>(threadIdx.x) / kWave;
+  const int nwaves = static_cast<int>(blockDim.x) / kWave;
+  unsigned long long* wt = smem + wave * kT_Slots;  // this wavefront's tally
+  int* stack = reinterpret_cast<int*>(smem + nwaves * kT_Slots) + threadIdx.x;
+  const int stride = static_cast<int>(blockDim.x);
+  for (int i = lane; i < kT_Slots; i += kWave) wt[i] = 0;
+
+  const uint32_t k0 = P.seed_lo, k1 = P.seed_hi;
+  const int64_t total_chunks = P.chunk_begin[P.n_units];
+
+  // wave-uniform claim state
+  int cur = -1;             // current unit
+  int64_t next_h = 0, end_h = 0;
+  int pend = -1;            // claimed chunk waiting for a drain
+  int64_t pend_h0 = 0, pend_h1 = 0;
+  bool exhausted = false;
+  UnitRec U{};
+  SceneRec S{};
+  SourceRec Src{};
+
+  // lane state
+  bool alive = false;
+  float px = 0, py = 0, pz = 0, dx = 0, dy = 0, dz = 1, E = 0, E0 = 0, tau = 0;
+  float edep_act = 0, edep_tot = 0;
+  int region = 0, last = -1, steps = 0;
+  bool clean = true, interacted = false, touched = false;
+  Xs ix{0, 0.0f};
+  Rng g{};
+  float sc[kMaxGroups];
+#pragma unroll
+  for (int i = 0; i < kMaxGroups; ++i) sc[i] = 0.0f;
+  // per-lane accumulators of the per-history (frequent) quantities
+  unsigned long long acc_hist = 0, acc_eunc = 0, acc_esrc = 0;
+  uint32_t ev[kEv_N];
+#pragma unroll
+  for (int i = 0; i < kEv_N; ++i) ev[i] = 0;
+  uint32_t nvis_dummy = 0, ntri_dummy = 0;
+
+  auto flush = [&]() {
+    if (cur < 0) return;
+    const unsigned long long h = wave_sum_u64(acc_hist);
+    const unsigned long long eu = wave_sum_u64(acc_eunc);
+    const unsigned long long es = wave_sum_u64(acc_esrc);
+    unsigned long long evs[kEv_N];
+    if (COUNT) {
+#pragma unroll
+      for (int i = 0; i < kEv_N; ++i) evs[i] = wave_sum_u64(ev[i]);
+    }
+    if (lane == 0) {
+      wt[kT_Hist] += h;
+      wt[kT_EEsc] += eu;
+      wt[kT_ESrc] += es;
+      if (COUNT) {
+#pragma unroll
+        for (int i = 0; i < kEv_N; ++i) wt[kT_Ev + i] += evs[i];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < kT_Slots; i += kWave) {
+      const unsigned long long x = wt[i];
+      if (x) atomicAdd(P.tally + static_cast<int64_t>(cur) * kT_Slots + i, x);
+      wt[i] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    acc_hist = acc_eunc = acc_esrc = 0;
+#pragma unroll
+    for (int i = 0; i < kEv_N; ++i) ev[i] = 0;
+  };
+
+  auto end_history = [&](bool absorbed, bool escaped, bool lost, bool killed) {
+    alive = false;
+    acc_hist += 1;
+    if (escaped) {
+      if (interacted) {
+        atomicAdd(&wt[kT_CollEscape], 1ull);
+        atomicAdd(&wt[kT_EEsc], fx(E, kEnergyFix));
+      } else {
+        acc_eunc += fx(E, kEnergyFix);
+      }
+    }
+    const bool fep = absorbed && clean;
+    if (absorbed) atomicAdd(&wt[kT_Absorbed], 1ull);
+    if (fep) atomicAdd(&wt[kT_Fep], 1ull);
+    if (lost) atomicAdd(&wt[kT_Lost], 1ull);
+    if (killed) atomicAdd(&wt[kT_Killed], 1ull);
+    if (edep_tot > 0.0f) atomicAdd(&wt[kT_EdepTot], fx(edep_tot, kEnergyFix));
+    if (edep_act > 0.0f) {
+      atomicAdd(&wt[kT_EdepAct], fx(edep_act, kEnergyFix));
+      if (SPEC) {
+        const float ch = floorf(edep_act * P.inv_channel_kev);
+        if (ch < static_cast<float>(P.n_channels))
+          atomicAdd(P.spectra + static_cast<int64_t>(cur) * P.n_channels + static_cast<int>(ch),
+                    1ull);
+        else
+          atomicAdd(&wt[kT_SpecOvf], 1ull);
+      }
+    }
+    if (GRAD && touched) {
+#pragma unroll
+      for (int i = 0; i < kMaxGroups; ++i) {
+        if (i >= U.n_groups || sc[i] == 0.0f) continue;
+        const double s = static_cast<double>(sc[i]);
+        atomicAdd(&wt[kT_Score + i], fx(s, kScoreFix));
+        if (fep) {
+          atomicAdd(&wt[kT_FepScore + i], fx(s, kScoreFix));
+          atomicAdd(&wt[kT_FepScore2 + i], fx(s * s, kScore2Fix));
+        }
+      }
+    }
+  };
+
+  for (;;) {
+    // ---- refill dead lanes from the wavefront's current chunk
+    const uint64_t need = __ballot(!alive);
+    if (need) {
+      if (next_h >= end_h && pend < 0 && !exhausted) {
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd(P.cursor, 1ull);
+        c = __shfl(c, 0, kWave);
+        if (static_cast<int64_t>(c) >= total_chunks) {
+          exhausted = true;
+        } else {
+          int lo = 0, hi = P.n_units - 1;  // unit u: chunk_begin[u] <= c < chunk_begin[u+1]
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.chunk_begin[mid] <= static_cast<int64_t>(c))
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+          pend = lo;
+          const int64_t local = static_cast<int64_t>(c) - P.chunk_begin[lo];
+          pend_h0 = local * P.chunk;
+          const int64_t nu = P.units[lo].n;
+          pend_h1 = pend_h0 + P.chunk < nu ? pend_h0 + P.chunk : nu;
+        }
+      }
+      if (next_h >= end_h && pend >= 0 && (pend == cur || __ballot(alive) == 0)) {
+        if (pend != cur) {
+          flush();
+          cur = pend;
+          U = P.units[cur];
+          S = P.scenes[U.scene];
+          Src = P.sources[U.source];
+        }
+        next_h = pend_h0;
+        end_h = pend_h1;
+        pend = -1;
+      }
+      if (next_h < end_h) {
+        const uint64_t below = need & ((1ull << lane) - 1ull);
+        const int64_t h = next_h + __popcll(below);
+        if (!alive && h < end_h) {
+          // ---- emission
+          rng_start(g, static_cast<uint64_t>(U.first + h), U.stream);
+          if (COUNT) ev[kEv_Emissions]++;
+          if (Src.n_lines > 0) {
+            const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+            const float2* L = reinterpret_cast<const float2*>(P.lines) + Src.line_off;
+            int pick = Src.n_lines - 1;
+            for (int i = 0; i < Src.n_lines; ++i)
+              if (x < L[i].y) {
+                pick = i;
+                break;
+              }
+            E = L[pick].x;
+          } else {
+            E = U.energy;
+          }
+          E0 = E;
+          bool ok = true;
+          if (Src.kind == kCyl) {
+            ok = false;
+            const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
+            for (int attempt = 0; attempt < 1000 && !ok; ++attempt) {
+              const float rr = sqrtf(fmaf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
+              const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+              px = Src.pos[0] + rr * __builtin_amdgcn_cosf(uphi);
+              py = Src.pos[1] + rr * __builtin_amdgcn_sinf(uphi);
+              pz = Src.pos[2] + rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * Src.h;
+              if (COUNT) ev[kEv_Locates]++;
+              ok = locate_parity<COUNT>(S, px, py, pz, stack, stride, ev[kEv_NodeVisits],
+                                        ev[kEv_TriTests]) == Src.region;
+            }
+            region = Src.region;
+          } else {
+            px = Src.pos[0];
+            py = Src.pos[1];
+            pz = Src.pos[2];
+            region = U.src_region;
+            ok = region >= 0;
+          }
+          if (!ok) {
+            atomicAdd(&wt[kT_SrcFail], 1ull);
+            acc_hist += 1;
+          } else {
+            acc_esrc += fx(E0, kEnergyFix);
+            if (Src.kind == kBeam) {
+              dx = Src.dir[0];
+              dy = Src.dir[1];
+              dz = Src.dir[2];
+            } else {
+              const float ct = fmaf(2.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -1.0f);
+              const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+              const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+              dx = st * __builtin_amdgcn_cosf(uphi);
+              dy = st * __builtin_amdgcn_sinf(uphi);
+              dz = ct;
+            }
+            tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+            ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+            edep_act = edep_tot = 0.0f;
+            clean = true;
+            interacted = touched = false;
+            last = -1;
+            steps = 0;
+#pragma unroll
+            for (int i = 0; i < kMaxGroups; ++i) sc[i] = 0.0f;
+            alive = true;
+          }
+        }
+        next_h += __popcll(need);
+        if (next_h > end_h) next_h = end_h;
+      }
+    }
+    if (__ballot(alive) == 0) {
+      if (exhausted && pend < 0 && next_h >= end_h) break;
+      continue;
+    }
+    if (!alive) continue;
+
+    // ---- one segment of the live history
+    if (COUNT) ev[kEv_Segments]++;
+    const RegionRec rr = P.regions[U.region_off + region];
+    float mp, mc, mh;
+    xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ix, mp, mc, mh);
+    const float mu = mp + mc + mh;
+    const float tmax = mu > 0.0f ? tau / mu : INFINITY;
+    const int grp = rr.bits & 0xFF;
+    const bool active = (rr.bits >> 8) & 1;
+    const Ray ray = make_ray(px, py, pz, dx, dy, dz);
+    HitOut hit;
+    bool glitch = false;
+    const bool has_hit = closest_hit<COUNT>(S, ray, tmax, last, region, stack, stride, hit, glitch,
+                                            COUNT ? ev[kEv_NodeVisits] : nvis_dummy,
+                                            COUNT ? ev[kEv_TriTests] : ntri_dummy);
+    if (glitch) atomicAdd(&wt[kT_Glitch], 1ull);
+    if (++steps > P.max_steps) {
+      clean = false;
+      end_history(false, false, false, true);
+      continue;
+    }
+    if (has_hit) {
+      // boundary crossing
+      if (COUNT) ev[kEv_Crossings]++;
+      if (GRAD && grp < kMaxGroups) {
+        const float d0 = mu * rr.inv_scale * hit.t;
+#pragma unroll
+        for (int i = 0; i < kMaxGroups; ++i)
+          if (grp == i) sc[i] -= d0;
+        touched = true;
+      }
+      px = fmaf(hit.t, dx, px);
+      py = fmaf(hit.t, dy, py);
+      pz = fmaf(hit.t, dz, pz);
+      tau = fmaxf(0.0f, fmaf(-mu, hit.t, tau));
+      region = hit.region_after;
+      last = hit.slot;
+      continue;
+    }
+    if (mu > 0.0f) {
+      // interaction at the end of the flight
+      const float s = tau / mu;
+      px = fmaf(s, dx, px);
+      py = fmaf(s, dy, py);
+      pz = fmaf(s, dz, pz);
+      if (GRAD && grp < kMaxGroups) {
+        const float d = rr.inv_scale - mu * rr.inv_scale * s;
+#pragma unroll
+        for (int i = 0; i < kMaxGroups; ++i)
+          if (grp == i) sc[i] += d;
+        touched = true;
+      }
+      last = -1;
+      interacted = true;
+      const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * mu;
+      if (x < mp) {
+        if (COUNT) ev[kEv_Photo]++;
+        edep_tot += E;
+        if (active)
+          edep_act += E;
+        else
+          clean = false;
+        end_history(true, false, false, false);
+        continue;
+      }
+      if (x < mp + mc) {
+        // Klein-Nishina by the composition-rejection of Butcher and Messel
+        // (1960): eps = E'/E on [e0, 1] is drawn from the 1/eps or the eps
+        // part of (1/eps + eps) with weights ln(1/e0) and (1 - e0^2)/2, and
+        // accepted with probability 1 - eps sin^2 / (1 + eps^2).
+        if (COUNT) ev[kEv_Compton]++;
+        const float k = E * (1.0f / kMec2);
+        const float e0 = 1.0f / fmaf(2.0f, k, 1.0f);
+        const float e02 = e0 * e0;
+        const float a1 = -__logf(e0);
+        const float a2 = 0.5f * (1.0f - e02);
+        float eps = 1.0f, t = 0.0f;
+        for (int it = 0; it < 64; ++it) {
+          const float u1 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+          const float u2 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+          const float u3 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+          float eps2;
+          if (u1 * (a1 + a2) < a1) {
+            eps = __expf(-a1 * u2);
+            eps2 = eps * eps;
+          } else {
+            eps2 = fmaf(1.0f - e02, u2, e02);
+            eps = sqrtf(eps2);
+          }
+          t = (1.0f - eps) / (k * eps);
+          const float sin2 = t * (2.0f - t);
+          if (u3 * (1.0f + eps2) <= 1.0f + eps2 - eps * sin2) break;
+        }
+        const float Ep = eps * E;
+        const float dep = E - Ep;
+        edep_tot += dep;
+        if (active)
+          edep_act += dep;
+        else
+          clean = false;
+        turn(dx, dy, dz, 1.0f - t, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+        E = Ep;
+        if (E < P.e_cut) {
+          edep_tot += E;
+          if (active)
+            edep_act += E;
+          else
+            clean = false;
+          end_history(true, false, false, false);
+          continue;
+        }
+        ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+      } else {
+        // coherent: Thomson law 3/8 (1 + mu^2); its CDF (mu^3 + 3 mu + 4)/8
+        // inverts in closed form (Cardano): with a = 4u - 2,
+        // mu = c - 1/c, c = cbrt(a + sqrt(a^2 + 1)), taken on |a| for accuracy
+        if (COUNT) ev[kEv_Coherent]++;
+        const float a = fmaf(4.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -2.0f);
+        const float c = cbrtf(fabsf(a) + sqrtf(fmaf(a, a, 1.0f)));
+        const float ct = copysignf(c - 1.0f / c, a);
+        turn(dx, dy, dz, fminf(1.0f, fmaxf(-1.0f, ct)), rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+      }
+      tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+      continue;
+    }
+    // vacuum and no facet ahead: escape from the world, otherwise lost
+    if (region == 0) {
+      clean = false;
+      end_history(false, true, false, false);
+    } else {
+      clean = false;
+      end_history(false, false, true, false);
+    }
+  }
+  flush();
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// region of each unit's point/beam origin
+__global__ void locate_units_kernel(UnitRec* units, int n_units, const SceneRec* scenes,
+                                    const SourceRec* sources, int stack_depth) {
+  extern __shared__ int lstack[];
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n_units) return;
+  UnitRec& U = units[u];
+  const SourceRec s = sources[U.source];
+  uint32_t a = 0, b = 0;
+  if (s.kind == kCyl) {
+    U.src_region = s.region;
+  } else {
+    U.src_region = locate_parity<false>(scenes[U.scene], s.pos[0], s.pos[1], s.pos[2],
+                                        lstack + threadIdx.x, blockDim.x, a, b);
+  }
+  (void)stack_depth;
+}
+
+__global__ void raycast_kernel(SceneRec sc, const float* o, const float* d, const int32_t* region,
+                               int64_t n, float* t, int32_t* tri, int32_t* region_after) {
+  extern __shared__ int lstack[];
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const Ray r = make_ray(o[3 * i], o[3 * i + 1], o[3 * i + 2], d[3 * i], d[3 * i + 1], d[3 * i + 2]);
+  HitOut h;
+  bool glitch;
+  uint32_t a = 0, b = 0;
+  const int cur = region ? region[i] : -1;
+  if (closest_hit<false>(sc, r, INFINITY, -1, cur, lstack + threadIdx.x, blockDim.x, h, glitch, a,
+                         b)) {
+    t[i] = h.t;
+    tri[i] = sc.tris[h.slot].orig;
+    region_after[i] = h.region_after;
+  } else {
+    t[i] = INFINITY;
+    tri[i] = -1;
+    region_after[i] = -1;
+  }
+}
+
+__global__ void locate_kernel(SceneRec sc, const float* p, int64_t n, int32_t* region) {
+  extern __shared__ int lstack[];
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  uint32_t a = 0, b = 0;
+  region[i] = locate_parity<false>(sc, p[3 * i], p[3 * i + 1], p[3 * i + 2], lstack + threadIdx.x,
+                                   blockDim.x, a, b);
+}
+
+// Gaussian broadening: one thread per output channel gathers from the input
+// channels whose 5-sigma window reaches it.
+__global__ void broaden_kernel(const double* in, double* out, int n_spectra, int n, double w,
+                               double a, double b, int reach) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= static_cast<int64_t>(n_spectra) * n) return;
+  const int s = static_cast<int>(i / n), c = static_cast<int>(i % n);
+  const double* src = in + static_cast<int64_t>(s) * n;
+  const double centre = (c + 0.5) * w;
+  const double k = 1.0 / (2.0 * sqrt(2.0 * log(2.0)));
+  double acc = 0.0;
+  const int lo = c - reach < 0 ? 0 : c - reach, hi = c + reach >= n ? n - 1 : c + reach;
+  for (int cp = lo; cp <= hi; ++cp) {
+    const double x = src[cp];
+    if (x == 0.0) continue;
+    const double Ec = (cp + 0.5) * w;
+    const double sigma = sqrt(a + b * Ec) * k;
+    if (fabs(centre - Ec) > 5.0 * sigma) continue;
+    const double r = 1.0 / (sigma * sqrt(2.0));
+    acc += x * 0.5 * (erfc(-((c + 1) * w - Ec) * r) - erfc(-(c * w - Ec) * r));
+  }
+  out[i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (called from the runtime)
+
+using TK = void (*)(TransportParams);
+
+static TK pick(int variant) {
+  switch (variant & 7) {
+    case 0: return transport_kernel<false, false, false>;
+    case 1: return transport_kernel<true, false, false>;
+    case 2: return transport_kernel<false, true, false>;
+    case 3: return transport_kernel<true, true, false>;
+    case 4: return transport_kernel<false, false, true>;
+    case 5: return transport_kernel<true, false, true>;
+    case 6: return transport_kernel<false, true, true>;
+    default: return transport_kernel<true, true, true>;
+  }
+}
+
+size_t transport_smem(int block, int depth) {
+  return static_cast<size_t>(block / kWave) * kT_Slots * sizeof(unsigned long long) +
+         static_cast<size_t>(depth) * block * sizeof(int);
+}
+
+hipError_t transport_launch(const TransportParams& P, int variant, int grid, int block,
+                            hipStream_t s) {
+  const size_t smem = transport_smem(block, P.stack_depth);
+  hipLaunchKernelGGL(pick(variant), dim3(grid), dim3(block), smem, s, P);
+  return hipGetLastError();
+}
+
+hipError_t transport_occupancy(int variant, int block, int depth, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, reinterpret_cast<const void*>(pick(variant)), block,
+      transport_smem(block, depth));
+}
+
+hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t locate_units(UnitRec* units, int n_units, const SceneRec* scenes,
+                        const SourceRec* sources, int depth, hipStream_t s) {
+  const int block = 64;
+  const int grid = (n_units + block - 1) / block;
+  hipLaunchKernelGGL(locate_units_kernel, dim3(grid), dim3(block), depth * block * sizeof(int), s,
+                     units, n_units, scenes, sources, depth);
+  return hipGetLastError();
+}
+
+hipError_t raycast(const SceneRec& sc, const float* o, const float* d, const int32_t* region,
+                   int64_t n, float* t, int32_t* tri, int32_t* region_after, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (n + block - 1) / block;
+  hipLaunchKernelGGL(raycast_kernel, dim3(static_cast<unsigned>(grid)), dim3(block),
+                     sc.depth * block * sizeof(int), s, sc, o, d, region, n, t, tri, region_after);
+  return hipGetLastError();
+}
+
+hipError_t locate(const SceneRec& sc, const float* p, int64_t n, int32_t* region, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (n + block - 1) / block;
+  hipLaunchKernelGGL(locate_kernel, dim3(static_cast<unsigned>(grid)), dim3(block),
+                     sc.depth * block * sizeof(int), s, sc, p, n, region);
+  return hipGetLastError();
+}
+
+hipError_t broaden(const double* in, double* out, int n_spectra, int n, double w, double a,
+                   double b, hipStream_t s) {
+  // widest window: 5 sigma at the top channel (sigma grows with E), in channels
+  const double emax = n * w;
+  const double smax = sqrt(a + b * emax) / (2.0 * sqrt(2.0 * log(2.0)));
+  const int reach = static_cast<int>(ceil(5.0 * smax / w)) + 1;
+  const int block = 256;
+  const int64_t total = static_cast<int64_t>(n_spectra) * n;
+  const int64_t grid = (total + block - 1) / block;
+  hipLaunchKernelGGL(broaden_kernel, dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, in, out,
+                     n_spectra, n, w, a, b, reach);
+  return hipGetLastError();
+}
+
+}  // namespace gadep

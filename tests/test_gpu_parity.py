@@ -1,0 +1,298 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C interface.
+
+Geometry queries (closest hit, parity localization) are deterministic and
+compared element by element; transport tallies are Monte Carlo estimates and
+are compared within 3 combined standard deviations (independent seeds), with
+closed forms where they exist.  Spectra use a chi-square homogeneity test.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from workloads import configs as C
+from workloads import meshgen as mg
+from workloads import xsgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2605_25963_amd import gadep
+    gadep.lib()
+    return gadep
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def loaded(G, ctx, w, scene=0):
+    G.load_workload(ctx, w, scene)
+    return ctx
+
+
+def sigma3(a, sa, b, sb, k=3.0):
+    return abs(a - b) <= k * math.hypot(sa, sb)
+
+
+def chi2_homogeneity(a, b, min_count=20):
+    """p-value that histograms a and b (different totals) share one shape."""
+    from scipy import stats
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    # merge adjacent bins until each merged bin holds >= min_count in both
+    ra, rb, ca, cb = [], [], 0.0, 0.0
+    for x, y in zip(a, b):
+        ca += x
+        cb += y
+        if ca >= min_count and cb >= min_count:
+            ra.append(ca)
+            rb.append(cb)
+            ca = cb = 0.0
+    if ra:
+        ra[-1] += ca
+        rb[-1] += cb
+    ra, rb = np.array(ra), np.array(rb)
+    na, nb = a.sum(), b.sum()
+    k1, k2 = math.sqrt(nb / na), math.sqrt(na / nb)
+    chi2 = (((k1 * ra - k2 * rb) ** 2) / (ra + rb)).sum()
+    dof = len(ra) - 1
+    return stats.chi2.sf(chi2, dof), chi2, dof
+
+
+# --------------------------------------------------------------------------
+# geometry
+
+def _random_rays(rng, n, lo, hi):
+    o = rng.uniform(lo, hi, size=(n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return o, d.astype(np.float32)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_raycast_matches_oracle(G, ctx, orc, cfg):
+    w = C.c1_bare() if cfg == "c1" else C.c2_hpge(n_histories=1)
+    loaded(G, ctx, w)
+    s = orc.scene_from_workload(w)
+    rng = np.random.default_rng(101)
+    lo, hi = ([-40, -40, -70], [40, 40, 20]) if cfg == "c1" else ([-45, -45, -105], [45, 45, 15])
+    n = 20000
+    o, d = _random_rays(rng, n, lo, hi)
+    region = np.array([s.locate(o[i].astype(np.float64)) for i in range(n)], np.int32)
+    t, tri, ra = ctx.raycast(o, d, region)
+    t_nf, tri_nf, ra_nf = ctx.raycast(o, d, None)
+    bad = 0
+    for i in range(n):
+        to, fo = s.closest_hit(o[i].astype(np.float64), d[i].astype(np.float64))
+        if fo < 0:
+            assert tri_nf[i] == -1 and not np.isfinite(t_nf[i])
+            continue
+        assert abs(t_nf[i] - to) <= 1e-5 * to + 4e-5, (i, t_nf[i], to)
+        if tri_nf[i] != fo:
+            # only an edge/vertex tie may pick the neighbouring facet
+            t2, _ = s.closest_hit(o[i].astype(np.float64), d[i].astype(np.float64), exclude=fo)
+            assert abs(t2 - to) <= 1e-5 * to + 4e-5
+            bad += 1
+        # with the region filter the same facet is found from the true region
+        assert abs(t[i] - to) <= 1e-5 * to + 4e-5
+        p = o[i] + (to + 2e-4) * d[i].astype(np.float64)
+        assert ra[i] == s.locate(p), i
+    assert bad <= n * 1e-3
+
+
+@pytest.mark.parametrize("cfg", ["c2", "spheres"])
+def test_locate_matches_oracle(G, ctx, orc, cfg):
+    if cfg == "c2":
+        w = C.c2_hpge(n_histories=1)
+        loaded(G, ctx, w)
+        sc = w.scene
+        lo, hi = [-45, -45, -105], [45, 45, 15]
+    else:
+        sc = C.nested_spheres((10.0, 20.0, 30.0))
+        regions = [(0, 0.0, -1, 0)] + [(1, 5.32, -1, 0)] * 3
+        ctx.set_xs(0, xsgen.grid(), *xsgen.constant_table())
+        ctx.set_xs(1, xsgen.grid(), *xsgen.material_table("Ge"))
+        ctx.load_scene(0, sc.xyz, sc.tri, sc.tri_region, regions)
+        lo, hi = [-35] * 3, [35] * 3
+    s = orc.Scene(sc.xyz, sc.tri, sc.tri_region, sc.n_regions)
+    rng = np.random.default_rng(102)
+    p = rng.uniform(lo, hi, size=(20000, 3)).astype(np.float32)
+    got = ctx.locate(p)
+    offs = 2e-3 * np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+    checked = 0
+    for i in range(len(p)):
+        ref = [s.locate(p[i].astype(np.float64) + q) for q in offs]
+        if len(set(ref)) != 1:
+            continue  # within 2 um of a surface: the FP32 and FP64 answers may differ
+        assert got[i] == ref[0], (i, p[i], got[i], ref[0])
+        checked += 1
+    assert checked > 19000
+
+
+# --------------------------------------------------------------------------
+# transport against closed forms
+
+def _slab(G, ctx, T, photo, compton=0.0, coherent=0.0):
+    scene, mats, tabs, grid = C.slab(T, photo, compton, coherent)
+    for m, t in tabs.items():
+        ctx.set_xs(m, grid, *t)
+    ctx.load_scene(0, scene.xyz, scene.tri, scene.tri_region, [(0, 0.0, -1, 0), (1, 1.0, 0, G.ACTIVE)])
+
+
+BEAM = C.Source(C.KIND_BEAM, pos=(0.1234, 0.4321, 10.0), direction=(0.0, 0.0, -1.0))
+
+
+def test_slab_photo_only(G, ctx):
+    _slab(G, ctx, 5.0, 2.0)
+    n = 4_000_000
+    r = ctx.run(BEAM, [661.7], n, 11)
+    t = r.tallies[0]
+    p, s = t.n_fep / n, math.sqrt(t.n_fep / n * (1 - t.n_fep / n) / n)
+    assert abs(p - (1 - math.exp(-1.0))) <= 3 * s
+    assert t.n_fep + t.n_escape == n and t.n_lost == 0 and t.n_glitch == 0
+
+
+def test_slab_uncollided_and_energy_balance(G, ctx):
+    _slab(G, ctx, 5.0, 0.5, 1.0, 0.3)
+    n = 4_000_000
+    r = ctx.run(BEAM, [300.0], n, 12)
+    t = r.tallies[0]
+    ex = math.exp(-0.18 * 5.0)
+    assert abs(t.n_uncollided / n - ex) <= 3 * math.sqrt(ex * (1 - ex) / n)
+    assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+    assert t.e_source_keV == pytest.approx(300.0 * n, rel=1e-12)
+
+
+@pytest.mark.parametrize("scale", [1.0, 1.3])
+def test_slab_gradient_closed_form(G, ctx, scale):
+    _slab(G, ctx, 5.0, 2.0)
+    r = ctx.run_grad(BEAM, [661.7], 4_000_000, 13, [scale])
+    g, gs = r.grad[0, 0], math.sqrt(r.grad_var[0, 0])
+    assert abs(g - math.exp(-scale)) <= 3 * gs
+    assert r.fepe()[0] == pytest.approx(1 - math.exp(-scale), abs=4 * r.fepe_sigma()[0])
+
+
+def test_slab_gradient_crn_finite_difference(G, ctx):
+    _slab(G, ctx, 5.0, 1.0, 1.0)
+    n, h = 4_000_000, 0.01
+    up = ctx.run_grad(BEAM, [200.0], n, 14, [1 + h]).fepe()[0]
+    dn = ctx.run_grad(BEAM, [200.0], n, 14, [1 - h]).fepe()[0]
+    fd = (up - dn) / (2 * h)
+    r = ctx.run_grad(BEAM, [200.0], n, 14, [1.0])
+    g, gs = r.grad[0, 0], math.sqrt(r.grad_var[0, 0])
+    assert abs(g - fd) <= max(0.02 * abs(fd), 3 * gs)
+
+
+def test_black_absorber_solid_angle(G, ctx):
+    b = C.bare_crystal(64)
+    sc = b.build()
+    lnE0, dlnE, n = xsgen.grid()
+    ctx.set_xs(0, (lnE0, dlnE, n), *xsgen.constant_table(n=n))
+    ctx.set_xs(1, (lnE0, dlnE, n), *xsgen.constant_table(1e4, 0, 0, n=n))
+    ctx.load_scene(0, sc.xyz, sc.tri, sc.tri_region, [(0, 0.0, -1, 0), (1, 5.32, 0, G.ACTIVE)])
+    N = 1_000_000_000  # sigma 0.02 %: resolves the 0.15 % facet-vs-disk difference
+    r = ctx.run(C.Source(C.KIND_POINT, pos=(0.0, 0.0, 100.0)), [661.7], N, 15)
+    p = r.tallies[0].n_fep / N
+    frac = 0.0210551  # Van Oosterom-Strackee solid angle of the 64-gon face / 4 pi
+    assert abs(p - frac) <= 3 * math.sqrt(frac * (1 - frac) / N)
+    disk = 0.5 * (1 - 100 / math.hypot(100, 30))
+    assert abs(p - disk) > 3 * math.sqrt(frac * (1 - frac) / N)  # resolves the faceting
+
+
+# --------------------------------------------------------------------------
+# transport against the oracle
+
+def test_c1_fepe_and_spectrum_match_oracle(G, ctx, orc):
+    w = C.c1_bare()
+    loaded(G, ctx, w)
+    ng, no = 20_000_000, 2_000_000
+    r = ctx.run(w.source, [661.7], ng, 1001, spectrum=(1024, 1.0))
+    t = r.tallies[0]
+    s = orc.scene_from_workload(w)
+    o = s.run(w.source, 661.7, no, 2001, n_channels=1024, channel_keV=1.0)
+    pg, po = t.n_fep / ng, o.fepe()
+    assert sigma3(pg, math.sqrt(pg * (1 - pg) / ng), po, o.fepe_sigma())
+    assert t.n_lost == 0 and t.n_killed == 0
+    assert t.n_glitch <= 1e-6 * ng
+    pval, chi2, dof = chi2_homogeneity(r.spectra[0], o.spectrum)
+    assert pval > 1e-3, (chi2, dof)
+    assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+
+
+def test_c2_near_source_matches_oracle(G, ctx, orc):
+    # C2 detector, point source 20 mm above the end-cap: many photons enter
+    w = C.c2_hpge(n_histories=1, distance=20.0)
+    loaded(G, ctx, w)
+    s = orc.scene_from_workload(w)
+    E = [40.0, 661.7, 2000.0]
+    ng, no = 4_000_000, 400_000
+    r = ctx.run(w.source, E, ng, 1002, spectrum=(2048, 0.75))
+    for k, e in enumerate(E):
+        t = r.tallies[k]
+        o = s.run(w.source, e, no, 2002 + k, n_channels=2048, channel_keV=0.75)
+        pg = t.n_fep / ng
+        assert sigma3(pg, math.sqrt(pg * (1 - pg) / ng), o.fepe(), o.fepe_sigma()), (e, pg, o.fepe())
+        pa_g = t.n_absorbed / ng
+        pa_o = o.tally.n_absorbed / no
+        assert sigma3(pa_g, math.sqrt(pa_g * (1 - pa_g) / ng), pa_o, math.sqrt(pa_o * (1 - pa_o) / no))
+        assert t.n_lost == 0 and t.n_killed == 0
+        assert t.n_glitch <= 1e-5 * ng
+        pval, chi2, dof = chi2_homogeneity(r.spectra[k], o.spectrum)
+        assert pval > 1e-3, (e, chi2, dof)
+        assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# determinism
+
+def test_tallies_independent_of_launch_shape_and_split(G, ctx):
+    w = C.c2_hpge(n_histories=1, distance=20.0)
+    loaded(G, ctx, w)
+    E = [100.0, 1000.0]
+    n = 1_000_000
+
+    def run(first=0, nn=n):
+        return ctx.run(w.source, E, nn, 77, first_history=first, spectrum=(512, 4.0))
+
+    base = run()
+    again = run()
+    ctx.set_option(G.OPT_BLOCK, 64)
+    ctx.set_option(G.OPT_CLAIM, 3)
+    shaped = run()
+    ctx.set_option(G.OPT_GRAPHS, 0)
+    eager = run()
+    ctx.set_option(G.OPT_BLOCK, 256)
+    ctx.set_option(G.OPT_CLAIM, 32)
+    ctx.set_option(G.OPT_GRAPHS, 1)
+    a = run(0, n // 3)
+    b = run(n // 3, n - n // 3)
+    fields = ["n_histories", "n_absorbed", "n_fep", "n_escape", "n_uncollided", "n_lost",
+              "edep_active_keV", "edep_total_keV", "e_escape_keV"]
+    for other in (again, shaped, eager):
+        for f in fields:
+            assert np.array_equal(base.field(f), other.field(f)), f
+        assert np.array_equal(base.spectra, other.spectra)
+    for f in ["n_histories", "n_absorbed", "n_fep", "n_escape", "n_uncollided"]:
+        assert np.array_equal(base.field(f), a.field(f) + b.field(f)), f
+    assert np.array_equal(base.spectra, a.spectra + b.spectra)
+    assert np.allclose(base.field("edep_total_keV"), a.field("edep_total_keV") + b.field("edep_total_keV"),
+                       rtol=0, atol=1e-9)
+
+
+def test_batched_equals_single(G, ctx):
+    w = C.c1_bare()
+    loaded(G, ctx, w)
+    src = w.source
+    single = ctx.run_batch([dict(source=src, energies=[300.0, 661.7], n_histories=500_000, stream=5)], 9)
+    batch = ctx.run_batch([
+        dict(source=src, energies=[100.0], n_histories=200_000, stream=1),
+        dict(source=src, energies=[300.0, 661.7], n_histories=500_000, stream=5),
+        dict(source=src, energies=[1500.0], n_histories=300_000, stream=7)], 9)
+    for f in ["n_histories", "n_fep", "n_absorbed", "edep_active_keV"]:
+        assert np.array_equal(single.field(f), batch.field(f)[1:3]), f

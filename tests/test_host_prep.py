@@ -1,0 +1,227 @@
+"""Host-side mesh preparation of the library (no GPU): exports, validation,
+parity-derived shell topology and BVH invariants."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from workloads import configs as C
+from workloads import meshgen as mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2605_25963_amd import gadep
+    gadep.lib()
+    return gadep
+
+
+def test_library_exports_every_declared_symbol(G):
+    header = open(os.path.join(ROOT, "include", "gadep.h")).read()
+    declared = set(re.findall(r"\b(gadep_[a-z_]+)\s*\(", header))
+    declared -= {"gadep_status"}
+    assert declared == set(G.EXPORTS)
+    L = ctypes.CDLL(G.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_create_without_gpu_fails_cleanly(G):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("GPU present")
+    except ImportError:
+        pass
+    with pytest.raises(G.GadepError) as e:
+        G.Context(0)
+    assert e.value.code in (-7, -1)
+
+
+def prep(G, scene, **kw):
+    return G.mesh_prepare(scene.xyz, scene.tri, scene.tri_region, scene.n_regions, **kw)
+
+
+def test_c1_single_shell(G):
+    sc = C.c1_bare().scene
+    r = prep(G, sc)
+    assert r["n_shells"] == 1 and r["genus_max"] == 0
+    assert (r["outside"] == 0).all()
+
+
+def test_hpge_topology_from_parity(G):
+    w = C.c2_hpge(n_seg=64, n_phi=8)
+    sc = w.scene
+    r = prep(G, sc)
+    assert r["n_shells"] == 10
+    expect_outside = {"air": "world", "endcap": "air", "window": "endcap", "interior": "endcap",
+                      "cup": "interior", "dead": "interior", "active": "dead", "bore": "active",
+                      "pin": "bore", "coldfinger": "interior"}
+    for name, first, n in sc.shells:
+        out = np.unique(r["outside"][first:first + n])
+        assert len(out) == 1
+        assert out[0] == sc.region_id(expect_outside[name]), name
+    assert r["min_gap_mm"] >= 1e-3 * 0.99
+
+
+def test_nested_spheres_topology(G):
+    sc = C.nested_spheres((10.0, 20.0, 30.0))
+    r = prep(G, sc)
+    for k, (name, first, n) in enumerate(sc.shells):
+        assert (r["outside"][first:first + n] == k).all()  # outer sphere's region encloses
+
+
+def _two_box_scene(lo2, hi2, lo1=(-10, -10, -10), hi1=(10, 10, 10)):
+    b = mg.SceneBuilder()
+    b.add("a", "Ge", 5.32, mg.box(lo1, hi1))
+    b.add("b", "Ge", 5.32, mg.box(lo2, hi2))
+    return b.build()
+
+
+def test_validator_rejects_open_shell(G):
+    sc = C.c1_bare().scene
+    with pytest.raises(G.GadepError) as e:
+        G.mesh_prepare(sc.xyz, sc.tri[1:], sc.tri_region[1:], sc.n_regions)
+    assert e.value.name == "GADEP_E_MESH_OPEN"
+
+
+def test_validator_rejects_flipped_facet(G):
+    sc = C.c1_bare().scene
+    tri = sc.tri.copy()
+    tri[5] = tri[5][[0, 2, 1]]
+    with pytest.raises(G.GadepError) as e:
+        G.mesh_prepare(sc.xyz, tri, sc.tri_region, sc.n_regions)
+    assert e.value.name == "GADEP_E_MESH_ORIENT"
+
+
+def test_validator_rejects_inward_shell(G):
+    sc = C.c1_bare().scene
+    with pytest.raises(G.GadepError) as e:
+        G.mesh_prepare(sc.xyz, sc.tri[:, [0, 2, 1]], sc.tri_region, sc.n_regions)
+    assert e.value.name == "GADEP_E_MESH_ORIENT"
+
+
+def test_validator_rejects_intersecting_shells(G):
+    sc = _two_box_scene((5, 5, 5), (15, 15, 15))
+    with pytest.raises(G.GadepError) as e:
+        prep(G, sc)
+    assert e.value.name == "GADEP_E_MESH_OVERLAP"
+
+
+def test_validator_rejects_coincident_faces(G):
+    # inner box shares its top face plane with the outer box
+    sc = _two_box_scene((-5, -5, -5), (5, 5, 10))
+    with pytest.raises(G.GadepError) as e:
+        prep(G, sc)
+    assert e.value.name == "GADEP_E_MESH_OVERLAP"
+
+
+def test_validator_min_gap(G):
+    sc = _two_box_scene((-5, -5, -5), (5, 5, 10 - 5e-5))
+    with pytest.raises(G.GadepError):
+        prep(G, sc, min_gap_mm=1e-4)
+    r = prep(G, sc, min_gap_mm=1e-5)
+    assert r["min_gap_mm"] == pytest.approx(5e-5, rel=1e-2)
+
+
+def test_validator_rejects_degenerate_input(G):
+    sc = C.c1_bare().scene
+    xyz = sc.xyz.copy()
+    xyz[3, 1] = np.nan
+    with pytest.raises(G.GadepError) as e:
+        G.mesh_prepare(xyz, sc.tri, sc.tri_region, sc.n_regions)
+    assert e.value.name == "GADEP_E_MESH_DEGENERATE"
+    with pytest.raises(G.GadepError) as e:
+        G.mesh_prepare(sc.xyz, sc.tri, np.full(len(sc.tri), 7, np.int32), sc.n_regions)
+    assert e.value.name == "GADEP_E_ARG"
+
+
+def test_validator_rejects_self_nested_region(G):
+    b = mg.SceneBuilder()
+    r = b.add("outer", "Ge", 5.32, mg.box((-10, -10, -10), (10, 10, 10)))
+    b.add_shell(r, mg.box((-5, -5, -5), (5, 5, 5)))
+    sc = b.build()
+    with pytest.raises(G.GadepError) as e:
+        prep(G, sc)
+    assert e.value.name == "GADEP_E_TOPOLOGY"
+
+
+def _torus(R, r, n1, n2):
+    V, F = [], []
+    for i in range(n1):
+        a = 2 * math.pi * i / n1
+        for j in range(n2):
+            b = 2 * math.pi * j / n2
+            V.append(((R + r * math.cos(b)) * math.cos(a), (R + r * math.cos(b)) * math.sin(a), r * math.sin(b)))
+    for i in range(n1):
+        for j in range(n2):
+            a0, a1 = i * n2 + j, ((i + 1) % n1) * n2 + j
+            b0, b1 = i * n2 + (j + 1) % n2, ((i + 1) % n1) * n2 + (j + 1) % n2
+            F += [(a0, a1, b1), (a0, b1, b0)]
+    return mg.Shell(np.array(V), np.array(F))
+
+
+def test_genus_one_shell_accepted(G):
+    t = _torus(20.0, 5.0, 48, 24)
+    assert mg.signed_volume(t.V, t.F) > 0
+    b = mg.SceneBuilder()
+    b.add("ring", "Cu", 8.96, t)
+    r = prep(G, b.build())
+    assert r["n_shells"] == 1 and r["genus_max"] == 1
+
+
+def _leaves(nodes):
+    out = []
+    for nd in nodes:
+        for c in (nd[12], nd[13]):
+            if c < 0:
+                x = ~int(c)
+                out.append((x >> 3, x & 7))
+    return out
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_bvh_invariants(G, cfg):
+    sc = (C.c1_bare() if cfg == "c1" else C.c2_hpge(n_seg=128, n_phi=20, n_histories=1)).scene
+    r = prep(G, sc, want_nodes=True)
+    nodes = r["nodes"]
+    order = r["order"]
+    nt = len(sc.tri)
+    assert sorted(order) == list(range(nt))
+    covered = np.zeros(nt, int)
+    for first, count in _leaves(nodes):
+        assert 0 <= count <= 4
+        covered[first:first + count] += 1
+    assert (covered == 1).all()
+    boxes = nodes[:, :12].copy().view(np.float32).reshape(-1, 2, 2, 3)  # [node][child][lo/hi][xyz]
+    V = sc.xyz[sc.tri[order]]  # facet vertices in BVH slot order
+
+    def subtree_box(idx):
+        nd = nodes[idx]
+        lo, hi = np.full(3, np.inf), np.full(3, -np.inf)
+        for k, c in enumerate((nd[12], nd[13])):
+            clo, chi = boxes[idx, k, 0], boxes[idx, k, 1]
+            if c >= 0:
+                slo, shi = subtree_box(int(c))
+            else:
+                x = ~int(c)
+                f, n = x >> 3, x & 7
+                if n == 0:
+                    continue
+                pts = V[f:f + n].reshape(-1, 3)
+                slo, shi = pts.min(0), pts.max(0)
+            assert (clo <= slo).all() and (chi >= shi).all()
+            lo, hi = np.minimum(lo, slo), np.maximum(hi, shi)
+        return lo, hi
+
+    import sys
+    sys.setrecursionlimit(10000)
+    subtree_box(0)
+    assert 1 <= r["depth"] <= 64
+    med = prep(G, sc, bvh_method=1)
+    assert r["sah_cost"] <= med["sah_cost"] * 1.0001
