@@ -55,7 +55,14 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
-    return ap.parse_args()
+    ap.add_argument("--quick", action="store_true",
+                    help="profiling run: 1e7 histories per energy, no grad, no CPU baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device three times (scales HBM byte counters)")
+    a = ap.parse_args()
+    if a.quick:
+        a.min_histories, a.pilot, a.no_grad, a.no_cpu_baseline = 1e7, 1e6, True, True
+    return a
 
 
 def cpu_baseline(w, target_s):
@@ -80,8 +87,25 @@ def cpu_baseline(w, target_s):
                       f"({n} total, {dt:.1f} s), same detector and source"}
 
 
+def copy_probe():
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch give the
+    factor that turns those counters into bytes."""
+    import torch
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "dispatches": 3}), flush=True)
+
+
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
               "the path shards over independent histories, see the design notes", file=sys.stderr)
@@ -105,7 +129,8 @@ def main():
     pilot = ctx.run_batch(jobs([a.pilot] * len(w.energies)), 999)
     p = np.maximum(pilot.fepe(), 1e-12)
     need = np.ceil((1 - p) / (p * 0.005 ** 2))
-    n_e = np.maximum(a.min_histories, need).astype(np.int64)
+    n_e = (np.maximum(a.min_histories, need) if not a.quick else
+           np.full(len(p), a.min_histories)).astype(np.int64)
     total = int(n_e.sum())
     J = jobs(n_e)
 

@@ -253,6 +253,8 @@ typedef struct {
   int32_t depth;          /* BVH depth = traversal stack needed */
   double sah_cost;        /* SAH cost with unit traversal and intersection cost */
   double min_gap_mm;      /* smallest distance found between different shells */
+  int32_t convex_exit;    /* 1: the world borders a single convex shell, so a photon
+                             leaving it into a void world escapes at once */
 } gadep_mesh_info;
 
 /* Validation + topology + BVH on the host, as gadep_load_mesh does, without

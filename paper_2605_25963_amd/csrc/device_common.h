@@ -8,6 +8,19 @@
 
 namespace gadep {
 
+// Loads through pointers fetched from memory are generic (flat) unless told
+// otherwise; flat loads wait on the LDS counter too.  These casts make the
+// hot fetches plain global loads.
+#define GADEP_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T gload(const T* p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const GADEP_GLOBAL T*)p)[i];
+#else
+  return p[i];  // host pass of device code: never executed
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // whose halves are mixed with the other counter words and the round key; the
@@ -197,19 +210,19 @@ __device__ __forceinline__ int wt_test(const Ray& r, const float4 a, const float
 
 __device__ __forceinline__ void load_node(const BvhNode* nodes, int i, float4& n0, float4& n1,
                                           float4& n2, int4& n3) {
-  const float4* p = reinterpret_cast<const float4*>(nodes + i);
-  n0 = p[0];
-  n1 = p[1];
-  n2 = p[2];
-  n3 = reinterpret_cast<const int4*>(p)[3];
+  const float4* p = reinterpret_cast<const float4*>(nodes) + 4 * static_cast<int64_t>(i);
+  n0 = gload(p, 0);
+  n1 = gload(p, 1);
+  n2 = gload(p, 2);
+  n3 = gload(reinterpret_cast<const int4*>(p), 3);
 }
 
 __device__ __forceinline__ void load_tri(const TriRec* tris, int i, float4& a, float4& b,
                                          float4& c) {
-  const float4* p = reinterpret_cast<const float4*>(tris + i);
-  a = p[0];
-  b = p[1];
-  c = p[2];
+  const float4* p = reinterpret_cast<const float4*>(tris) + 3 * static_cast<int64_t>(i);
+  a = gload(p, 0);
+  b = gload(p, 1);
+  c = gload(p, 2);
 }
 
 constexpr int kDone = INT32_MIN;

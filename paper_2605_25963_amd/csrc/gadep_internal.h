@@ -58,6 +58,9 @@ struct SceneRec {
   int32_t depth;
 };
 
+// UnitRec.flags
+constexpr int32_t kUnitExitEscapes = 1;  // entering the (void) world ends the history
+
 enum SourceKind : int32_t { kPoint = 0, kBeam = 1, kCyl = 2 };
 
 struct SourceRec {
@@ -81,7 +84,7 @@ struct UnitRec {
   uint32_t stream;      // random stream id: counter word 3
   int32_t src_region;   // region of a point/beam origin (set on the device)
   int32_t n_groups;
-  int32_t pad;
+  int32_t flags;        // kUnit* bits
 };
 
 // Per-unit tally slots (uint64 each).
@@ -136,6 +139,9 @@ struct PreparedMesh {
   int32_t n_shells = 0;
   int32_t genus_max = 0;
   double min_gap = 0.0;
+  // The world borders exactly one shell and that shell is convex: a photon
+  // that leaves it into the world can never meet another facet.
+  bool convex_exit = false;
 };
 
 // Returns a gadep_status value; fills err on failure.

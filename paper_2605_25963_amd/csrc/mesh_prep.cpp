@@ -132,10 +132,15 @@ class Builder {
   }
 
   int32_t subtree(int64_t b, int64_t e, int depth, Box& box) {
-    if (e - b <= kLeafMax) {
+    const int64_t n = e - b;
+    if (n <= kLeafMax) {
       box.reset();
       for (int64_t i = b; i < e; ++i) box.grow(refs_[i].box);
-      return leaf_code(b, static_cast<int32_t>(e - b));
+      // a small set stays a leaf unless splitting it is cheaper by the SAH
+      int64_t mid = -1;
+      if (n < 2 || method_ != 0 || depth >= kMaxDepth - 1 ||
+          best_split(b, e, &mid) >= kCostIsect * n * box.area())
+        return leaf_code(b, static_cast<int32_t>(n));
     }
     int32_t idx = static_cast<int32_t>(nodes_.size());
     nodes_.emplace_back();
@@ -143,66 +148,98 @@ class Builder {
     return idx;
   }
 
+  static constexpr double kCostTrav = 1.2;   // one node visit (two box tests)
+  static constexpr double kCostIsect = 1.0;  // one facet test
+
+  // Cheapest SAH split of refs[b, e): centroid bins along each axis, plus a
+  // split of large boxes from small ones (needed when large facets, such as
+  // the faces of a world box, share centroid coordinates with small ones).
+  // Partitions refs and sets *mid on success; returns the SAH cost or +inf.
+  double best_split(int64_t b, int64_t e, int64_t* mid) {
+    Box cb, all;
+    cb.reset();
+    all.reset();
+    for (int64_t i = b; i < e; ++i) {
+      cb.grow(refs_[i].c);
+      all.grow(refs_[i].box);
+    }
+    const double area = all.area();
+    double best = INFINITY;
+    int best_kind = -1, best_bin = -1;  // kind 0..2: centroid axis; 3: box size
+    float best_lo = 0, best_scale = 0;
+    auto value = [](const Ref& r, int kind) {
+      return kind < 3 ? r.c[kind] : logf(static_cast<float>(r.box.area()) + 1e-30f);
+    };
+    auto key = [&](const Ref& r, int kind, float lo, float scale) {
+      return std::min(kBins - 1, std::max(0, static_cast<int>((value(r, kind) - lo) * scale)));
+    };
+    for (int kind = 0; kind < 4; ++kind) {
+      float lo = INFINITY, hi = -INFINITY;
+      for (int64_t i = b; i < e; ++i) {
+        const float v = value(refs_[i], kind);
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+      }
+      const float ext = hi - lo;
+      if (!(ext > 0)) continue;
+      const float scale = kBins * (1.0f - 1e-6f) / ext;
+      Box bins[kBins];
+      int64_t cnt[kBins] = {0};
+      for (auto& bx : bins) bx.reset();
+      for (int64_t i = b; i < e; ++i) {
+        const int k = key(refs_[i], kind, lo, scale);
+        cnt[k]++;
+        bins[k].grow(refs_[i].box);
+      }
+      double right_area[kBins];
+      int64_t right_cnt[kBins];
+      Box acc;
+      acc.reset();
+      int64_t c = 0;
+      for (int k = kBins - 1; k > 0; --k) {
+        acc.grow(bins[k]);
+        c += cnt[k];
+        right_area[k] = acc.area();
+        right_cnt[k] = c;
+      }
+      acc.reset();
+      c = 0;
+      for (int k = 0; k < kBins - 1; ++k) {
+        acc.grow(bins[k]);
+        c += cnt[k];
+        if (c == 0 || right_cnt[k + 1] == 0) continue;
+        const double cost = kCostTrav * area +
+                            kCostIsect * (acc.area() * c + right_area[k + 1] * right_cnt[k + 1]);
+        if (cost < best) {
+          best = cost;
+          best_kind = kind;
+          best_bin = k;
+          best_lo = lo;
+          best_scale = scale;
+        }
+      }
+    }
+    if (best_kind < 0) return INFINITY;
+    auto it = std::partition(refs_.begin() + b, refs_.begin() + e, [&](const Ref& r) {
+      return key(r, best_kind, best_lo, best_scale) <= best_bin;
+    });
+    const int64_t m = it - refs_.begin();
+    if (m <= b || m >= e) return INFINITY;
+    *mid = m;
+    return best;
+  }
+
   int64_t split(int64_t b, int64_t e, int depth) {
+    int64_t mid = -1;
+    if (method_ == 0 && depth < kMaxDepth - 16 && best_split(b, e, &mid) < INFINITY) return mid;
+    // object median along the widest centroid extent
     Box cb;
     cb.reset();
     for (int64_t i = b; i < e; ++i) cb.grow(refs_[i].c);
-    if (method_ == 0 && depth < kMaxDepth - 16) {
-      double best = INFINITY;
-      int best_axis = -1, best_bin = -1;
-      for (int a = 0; a < 3; ++a) {
-        float ext = cb.hi[a] - cb.lo[a];
-        if (!(ext > 0)) continue;
-        Box bins[kBins];
-        int64_t cnt[kBins] = {0};
-        for (auto& bx : bins) bx.reset();
-        const float scale = kBins * (1.0f - 1e-6f) / ext;
-        for (int64_t i = b; i < e; ++i) {
-          int k = std::min(kBins - 1, static_cast<int>((refs_[i].c[a] - cb.lo[a]) * scale));
-          cnt[k]++;
-          bins[k].grow(refs_[i].box);
-        }
-        double right_area[kBins];
-        int64_t right_cnt[kBins];
-        Box acc;
-        acc.reset();
-        int64_t c = 0;
-        for (int k = kBins - 1; k > 0; --k) {
-          acc.grow(bins[k]);
-          c += cnt[k];
-          right_area[k] = acc.area();
-          right_cnt[k] = c;
-        }
-        acc.reset();
-        c = 0;
-        for (int k = 0; k < kBins - 1; ++k) {
-          acc.grow(bins[k]);
-          c += cnt[k];
-          if (c == 0 || right_cnt[k + 1] == 0) continue;
-          double cost = acc.area() * c + right_area[k + 1] * right_cnt[k + 1];
-          if (cost < best) {
-            best = cost;
-            best_axis = a;
-            best_bin = k;
-          }
-        }
-      }
-      if (best_axis >= 0) {
-        const int a = best_axis;
-        const float ext = cb.hi[a] - cb.lo[a];
-        const float scale = kBins * (1.0f - 1e-6f) / ext;
-        auto it = std::partition(refs_.begin() + b, refs_.begin() + e, [&](const Ref& r) {
-          return std::min(kBins - 1, static_cast<int>((r.c[a] - cb.lo[a]) * scale)) <= best_bin;
-        });
-        int64_t mid = it - refs_.begin();
-        if (mid > b && mid < e) return mid;
-      }
-    }
-    // object median along the widest centroid extent
     int a = 0;
     for (int k = 1; k < 3; ++k)
       if (cb.hi[k] - cb.lo[k] > cb.hi[a] - cb.lo[a]) a = k;
-    int64_t mid = b + (e - b) / 2;
+    mid = b + (e - b) / 2;
     std::nth_element(refs_.begin() + b, refs_.begin() + mid, refs_.begin() + e,
                      [a](const Ref& x, const Ref& y) {
                        return x.c[a] < y.c[a] || (x.c[a] == y.c[a] && x.id < y.id);
@@ -610,6 +647,9 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
 
   // ---- shells must not intersect or come closer than min_gap
   double gap_seen = INFINITY;
+  // candidate pairs: facets of different shells whose boxes lie within `reach`;
+  // the smallest distance among them is reported (exact when below reach)
+  const double reach = std::max(4.0 * min_gap, 1e-3);
   if (validate && ns > 1) {
     for (int64_t f = 0; f < nt; ++f) {
       Tri3 A = facet(static_cast<int32_t>(f));
@@ -622,8 +662,8 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
           mn = std::min(mn, c);
           mx = std::max(mx, c);
         }
-        blo[a] = mn - min_gap;
-        bhi[a] = mx + min_gap;
+        blo[a] = mn - reach;
+        bhi[a] = mx + reach;
       }
       int bad = -1;
       q.box_all(blo, bhi, [&](int32_t g) {
@@ -680,6 +720,41 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
       return fail(err, GADEP_E_TOPOLOGY,
                   "mesh: a shell of region " + std::to_string(own) +
                       " lies inside another shell of the same region");
+  }
+
+  // ---- is the world bounded by one convex shell?
+  {
+    int32_t top = -1, n_top = 0;
+    for (int32_t s = 0; s < ns; ++s)
+      if (container[s] == 0) {
+        top = s;
+        ++n_top;
+      }
+    out.convex_exit = false;
+    if (n_top == 1) {
+      std::vector<int32_t> fs, vs;
+      for (int64_t f = 0; f < nt; ++f)
+        if (shell[f] == top) {
+          fs.push_back(static_cast<int32_t>(f));
+          for (int k = 0; k < 3; ++k) vs.push_back(tv[3 * f + k]);
+        }
+      std::sort(vs.begin(), vs.end());
+      vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+      if (static_cast<double>(fs.size()) * static_cast<double>(vs.size()) <= 2e8) {
+        bool convex = true;
+        for (size_t i = 0; i < fs.size() && convex; ++i) {
+          Tri3 t = facet(fs[i]);
+          D3 n = cross(t.b - t.a, t.c - t.a);
+          const double tol = 1e-9 * len(n) * ext;
+          for (int32_t vi : vs)
+            if (dot(v[vi] - t.a, n) > tol) {
+              convex = false;
+              break;
+            }
+        }
+        out.convex_exit = convex;
+      }
+    }
   }
 
   // ---- outputs

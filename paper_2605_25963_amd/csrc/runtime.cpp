@@ -45,6 +45,7 @@ struct Scene {
   int32_t depth = 0;
   int64_t n_tri = 0;
   int64_t n_nodes = 0;
+  bool convex_exit = false;
   void* d_nodes = nullptr;
   void* d_tris = nullptr;
 };
@@ -322,6 +323,7 @@ gadep_status plan_jobs(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
       u.stream = (J.stream << 16) | static_cast<uint32_t>(e);
       u.src_region = 0;
       u.n_groups = grad ? GADEP_MAX_GROUPS : 0;
+      u.flags = (sc.convex_exit && P.regions[roff].mult == 0.0f) ? kUnitExitEscapes : 0;
       P.units.push_back(u);
       P.unit_energy.push_back(E);
       P.chunk_begin.push_back(chunks);
@@ -712,6 +714,7 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   sc.depth = pm.depth;
   sc.n_tri = nt;
   sc.n_nodes = static_cast<int64_t>(pm.nodes.size());
+  sc.convex_exit = pm.convex_exit;
   sc.loaded = true;
   if (ctx->graph) {
     hipGraphExecDestroy(ctx->graph);
@@ -984,6 +987,7 @@ gadep_status gadep_mesh_prepare(const float* xyz, int64_t nv, const int32_t* tri
     info->depth = pm.depth;
     info->sah_cost = pm.sah;
     info->min_gap_mm = pm.min_gap;
+    info->convex_exit = pm.convex_exit ? 1 : 0;
   }
   return GADEP_OK;
 }

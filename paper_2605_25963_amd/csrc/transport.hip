@@ -170,8 +170,8 @@ __device__ __forceinline__ Xs xs_index(float E, float ln_e0, float inv_dlne, int
 __device__ __forceinline__ void xs_mu(const float4* __restrict__ xs, int n_e, const RegionRec& rr,
                                       Xs ix, float& mp, float& mc, float& mh) {
   if (rr.mult > 0.0f) {
-    const float4 lo = xs[rr.material * n_e + ix.k];
-    const float4 hi = xs[rr.material * n_e + ix.k + 1];
+    const float4 lo = gload(xs, rr.material * n_e + ix.k);
+    const float4 hi = gload(xs, rr.material * n_e + ix.k + 1);
     mp = rr.mult * __expf(fmaf(ix.w, hi.x - lo.x, lo.x));
     mc = rr.mult * __expf(fmaf(ix.w, hi.y - lo.y, lo.y));
     mh = rr.mult * __expf(fmaf(ix.w, hi.z - lo.z, lo.z));
@@ -211,15 +211,32 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
   return x;
 }
 
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
 __device__ __forceinline__ unsigned long long fx(double v, double scale) {
   return static_cast<unsigned long long>(__double2ll_rn(v * scale));
 }
 
 // ---------------------------------------------------------------------------
 // transport kernel
+//
+// Persistent state machine.  Every iteration each lane with an open
+// traversal takes one traversal step (one BVH node, or one facet test), so a
+// long traversal no longer idles the rest of the wavefront.  A lane whose
+// traversal has finished parks; when at least `park` lanes are parked (or no
+// lane is traversing), the wavefront runs the segment outcome (boundary
+// crossing, interaction, escape, scoring), takes new histories for lanes that
+// need one and sets up the next traversals, for all parked lanes at once.
+
+enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3 };
 
 template <bool GRAD, bool SPEC, bool COUNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) transport_kernel(TransportParams P) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+transport_kernel(TransportParams P) {
   extern __shared__ unsigned long long smem[];
   const int lane = static_cast<int>(__lane_id());
   const int wave = static_cast<int>(threadIdx.x) / kWave;
@@ -231,6 +248,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 
   const uint32_t k0 = P.seed_lo, k1 = P.seed_hi;
   const int64_t total_chunks = P.chunk_begin[P.n_units];
+  const int park = P.period > 0 ? (P.period > kWave ? kWave : P.period) : 32;
 
   // wave-uniform claim state
   int cur = -1;             // current unit
@@ -242,9 +260,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   SceneRec S{};
   SourceRec Src{};
 
-  // lane state
-  bool alive = false;
-  float px = 0, py = 0, pz = 0, dx = 0, dy = 0, dz = 1, E = 0, E0 = 0, tau = 0;
+  // lane state: photon
+  int phase = kNeed;
+  float px = 0, py = 0, pz = 0, dx = 0, dy = 0, dz = 1, E = 0, tau = 0;
   float edep_act = 0, edep_tot = 0;
   int region = 0, last = -1, steps = 0;
   bool clean = true, interacted = false, touched = false;
@@ -253,12 +271,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   float sc[kMaxGroups];
 #pragma unroll
   for (int i = 0; i < kMaxGroups; ++i) sc[i] = 0.0f;
+  // lane state: current segment and its traversal
+  float mu = 0, mp = 0, mc = 0;
+  Ray ray{};
+  float tbest = 0, trej = INFINITY;
+  int node = kDone, sp = 0, tri_next = 0, tri_end = 0, best_slot = -1, best_reg = 0;
   // per-lane accumulators of the per-history (frequent) quantities
   unsigned long long acc_hist = 0, acc_eunc = 0, acc_esrc = 0;
   uint32_t ev[kEv_N];
 #pragma unroll
   for (int i = 0; i < kEv_N; ++i) ev[i] = 0;
-  uint32_t nvis_dummy = 0, ntri_dummy = 0;
 
   auto flush = [&]() {
     if (cur < 0) return;
@@ -292,7 +314,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   };
 
   auto end_history = [&](bool absorbed, bool escaped, bool lost, bool killed) {
-    alive = false;
+    phase = kNeed;
     acc_hist += 1;
     if (escaped) {
       if (interacted) {
@@ -334,257 +356,337 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
   };
 
   for (;;) {
-    // ---- refill dead lanes from the wavefront's current chunk
-    const uint64_t need = __ballot(!alive);
-    if (need) {
-      if (next_h >= end_h && pend < 0 && !exhausted) {
-        unsigned long long c = 0;
-        if (lane == 0) c = atomicAdd(P.cursor, 1ull);
-        c = __shfl(c, 0, kWave);
-        if (static_cast<int64_t>(c) >= total_chunks) {
-          exhausted = true;
-        } else {
-          int lo = 0, hi = P.n_units - 1;  // unit u: chunk_begin[u] <= c < chunk_begin[u+1]
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (P.chunk_begin[mid] <= static_cast<int64_t>(c))
-              lo = mid;
-            else
-              hi = mid - 1;
-          }
-          pend = lo;
-          const int64_t local = static_cast<int64_t>(c) - P.chunk_begin[lo];
-          pend_h0 = local * P.chunk;
-          const int64_t nu = P.units[lo].n;
-          pend_h1 = pend_h0 + P.chunk < nu ? pend_h0 + P.chunk : nu;
-        }
-      }
-      if (next_h >= end_h && pend >= 0 && (pend == cur || __ballot(alive) == 0)) {
-        if (pend != cur) {
-          flush();
-          cur = pend;
-          U = P.units[cur];
-          S = P.scenes[U.scene];
-          Src = P.sources[U.source];
-        }
-        next_h = pend_h0;
-        end_h = pend_h1;
-        pend = -1;
-      }
-      if (next_h < end_h) {
-        const uint64_t below = need & ((1ull << lane) - 1ull);
-        const int64_t h = next_h + __popcll(below);
-        if (!alive && h < end_h) {
-          // ---- emission
-          rng_start(g, static_cast<uint64_t>(U.first + h), U.stream);
-          if (COUNT) ev[kEv_Emissions]++;
-          if (Src.n_lines > 0) {
-            const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-            const float2* L = reinterpret_cast<const float2*>(P.lines) + Src.line_off;
-            int pick = Src.n_lines - 1;
-            for (int i = 0; i < Src.n_lines; ++i)
-              if (x < L[i].y) {
-                pick = i;
-                break;
-              }
-            E = L[pick].x;
-          } else {
-            E = U.energy;
-          }
-          E0 = E;
-          bool ok = true;
-          if (Src.kind == kCyl) {
-            ok = false;
-            const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
-            for (int attempt = 0; attempt < 1000 && !ok; ++attempt) {
-              const float rr = sqrtf(fmaf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
-              const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-              px = Src.pos[0] + rr * __builtin_amdgcn_cosf(uphi);
-              py = Src.pos[1] + rr * __builtin_amdgcn_sinf(uphi);
-              pz = Src.pos[2] + rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * Src.h;
-              if (COUNT) ev[kEv_Locates]++;
-              ok = locate_parity<COUNT>(S, px, py, pz, stack, stride, ev[kEv_NodeVisits],
-                                        ev[kEv_TriTests]) == Src.region;
-            }
-            region = Src.region;
-          } else {
-            px = Src.pos[0];
-            py = Src.pos[1];
-            pz = Src.pos[2];
-            region = U.src_region;
-            ok = region >= 0;
-          }
-          if (!ok) {
-            atomicAdd(&wt[kT_SrcFail], 1ull);
-            acc_hist += 1;
-          } else {
-            acc_esrc += fx(E0, kEnergyFix);
-            if (Src.kind == kBeam) {
-              dx = Src.dir[0];
-              dy = Src.dir[1];
-              dz = Src.dir[2];
-            } else {
-              const float ct = fmaf(2.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -1.0f);
-              const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-              const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-              dx = st * __builtin_amdgcn_cosf(uphi);
-              dy = st * __builtin_amdgcn_sinf(uphi);
-              dz = ct;
-            }
-            tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
-            ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
-            edep_act = edep_tot = 0.0f;
-            clean = true;
-            interacted = touched = false;
-            last = -1;
-            steps = 0;
-#pragma unroll
-            for (int i = 0; i < kMaxGroups; ++i) sc[i] = 0.0f;
-            alive = true;
-          }
-        }
-        next_h += __popcll(need);
-        if (next_h > end_h) next_h = end_h;
-      }
-    }
-    if (__ballot(alive) == 0) {
-      if (exhausted && pend < 0 && next_h >= end_h) break;
-      continue;
-    }
-    if (!alive) continue;
-
-    // ---- one segment of the live history
-    if (COUNT) ev[kEv_Segments]++;
-    const RegionRec rr = P.regions[U.region_off + region];
-    float mp, mc, mh;
-    xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ix, mp, mc, mh);
-    const float mu = mp + mc + mh;
-    const float tmax = mu > 0.0f ? tau / mu : INFINITY;
-    const int grp = rr.bits & 0xFF;
-    const bool active = (rr.bits >> 8) & 1;
-    const Ray ray = make_ray(px, py, pz, dx, dy, dz);
-    HitOut hit;
-    bool glitch = false;
-    const bool has_hit = closest_hit<COUNT>(S, ray, tmax, last, region, stack, stride, hit, glitch,
-                                            COUNT ? ev[kEv_NodeVisits] : nvis_dummy,
-                                            COUNT ? ev[kEv_TriTests] : ntri_dummy);
-    if (glitch) atomicAdd(&wt[kT_Glitch], 1ull);
-    if (++steps > P.max_steps) {
-      clean = false;
-      end_history(false, false, false, true);
-      continue;
-    }
-    if (has_hit) {
-      // boundary crossing
-      if (COUNT) ev[kEv_Crossings]++;
-      if (GRAD && grp < kMaxGroups) {
-        const float d0 = mu * rr.inv_scale * hit.t;
-#pragma unroll
-        for (int i = 0; i < kMaxGroups; ++i)
-          if (grp == i) sc[i] -= d0;
-        touched = true;
-      }
-      px = fmaf(hit.t, dx, px);
-      py = fmaf(hit.t, dy, py);
-      pz = fmaf(hit.t, dz, pz);
-      tau = fmaxf(0.0f, fmaf(-mu, hit.t, tau));
-      region = hit.region_after;
-      last = hit.slot;
-      continue;
-    }
-    if (mu > 0.0f) {
-      // interaction at the end of the flight
-      const float s = tau / mu;
-      px = fmaf(s, dx, px);
-      py = fmaf(s, dy, py);
-      pz = fmaf(s, dz, pz);
-      if (GRAD && grp < kMaxGroups) {
-        const float d = rr.inv_scale - mu * rr.inv_scale * s;
-#pragma unroll
-        for (int i = 0; i < kMaxGroups; ++i)
-          if (grp == i) sc[i] += d;
-        touched = true;
-      }
-      last = -1;
-      interacted = true;
-      const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * mu;
-      if (x < mp) {
-        if (COUNT) ev[kEv_Photo]++;
-        edep_tot += E;
-        if (active)
-          edep_act += E;
-        else
+    const uint64_t trav = __ballot(phase == kTrav);
+    if (trav == 0 || __popcll(__ballot(phase == kParked || phase == kNeed)) >= park) {
+      // ================= housekeeping for every parked lane =================
+      if (phase == kParked) {
+        // ---- outcome of the finished traversal
+        if (trej < tbest) atomicAdd(&wt[kT_Glitch], 1ull);
+        const RegionRec rr = gload(P.regions, U.region_off + region);
+        const int grp = rr.bits & 0xFF;
+        const bool active = (rr.bits >> 8) & 1;
+        phase = kSetup;
+        if (++steps > P.max_steps) {
           clean = false;
-        end_history(true, false, false, false);
-        continue;
-      }
-      if (x < mp + mc) {
-        // Klein-Nishina by the composition-rejection of Butcher and Messel
-        // (1960): eps = E'/E on [e0, 1] is drawn from the 1/eps or the eps
-        // part of (1/eps + eps) with weights ln(1/e0) and (1 - e0^2)/2, and
-        // accepted with probability 1 - eps sin^2 / (1 + eps^2).
-        if (COUNT) ev[kEv_Compton]++;
-        const float k = E * (1.0f / kMec2);
-        const float e0 = 1.0f / fmaf(2.0f, k, 1.0f);
-        const float e02 = e0 * e0;
-        const float a1 = -__logf(e0);
-        const float a2 = 0.5f * (1.0f - e02);
-        float eps = 1.0f, t = 0.0f;
-        for (int it = 0; it < 64; ++it) {
-          const float u1 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-          const float u2 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-          const float u3 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-          float eps2;
-          if (u1 * (a1 + a2) < a1) {
-            eps = __expf(-a1 * u2);
-            eps2 = eps * eps;
-          } else {
-            eps2 = fmaf(1.0f - e02, u2, e02);
-            eps = sqrtf(eps2);
+          end_history(false, false, false, true);
+        } else if (best_slot >= 0) {
+          // boundary crossing
+          if (COUNT) ev[kEv_Crossings]++;
+          if (GRAD && grp < kMaxGroups) {
+            const float d0 = mu * rr.inv_scale * tbest;
+#pragma unroll
+            for (int i = 0; i < kMaxGroups; ++i)
+              if (grp == i) sc[i] -= d0;
+            touched = true;
           }
-          t = (1.0f - eps) / (k * eps);
-          const float sin2 = t * (2.0f - t);
-          if (u3 * (1.0f + eps2) <= 1.0f + eps2 - eps * sin2) break;
-        }
-        const float Ep = eps * E;
-        const float dep = E - Ep;
-        edep_tot += dep;
-        if (active)
-          edep_act += dep;
-        else
-          clean = false;
-        turn(dx, dy, dz, 1.0f - t, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
-        E = Ep;
-        if (E < P.e_cut) {
-          edep_tot += E;
-          if (active)
-            edep_act += E;
-          else
+          px = fmaf(tbest, dx, px);
+          py = fmaf(tbest, dy, py);
+          pz = fmaf(tbest, dz, pz);
+          tau = fmaxf(0.0f, fmaf(-mu, tbest, tau));
+          region = best_reg;
+          last = best_slot;
+          if (region == 0 && (U.flags & kUnitExitEscapes)) {
+            // left the convex outermost shell into the void world: nothing ahead
             clean = false;
-          end_history(true, false, false, false);
-          continue;
+            end_history(false, true, false, false);
+          }
+        } else if (mu > 0.0f) {
+          // interaction at the end of the flight
+          const float s = tau / mu;
+          px = fmaf(s, dx, px);
+          py = fmaf(s, dy, py);
+          pz = fmaf(s, dz, pz);
+          if (GRAD && grp < kMaxGroups) {
+            const float d = rr.inv_scale - mu * rr.inv_scale * s;
+#pragma unroll
+            for (int i = 0; i < kMaxGroups; ++i)
+              if (grp == i) sc[i] += d;
+            touched = true;
+          }
+          last = -1;
+          interacted = true;
+          const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * mu;
+          if (x < mp) {
+            if (COUNT) ev[kEv_Photo]++;
+            edep_tot += E;
+            if (active)
+              edep_act += E;
+            else
+              clean = false;
+            end_history(true, false, false, false);
+          } else {
+            bool absorbed = false;
+            if (x < mp + mc) {
+              // Klein-Nishina by the composition-rejection of Butcher and Messel
+              // (1960): eps = E'/E on [e0, 1] is drawn from the 1/eps or the eps
+              // part of (1/eps + eps) with weights ln(1/e0) and (1 - e0^2)/2, and
+              // accepted with probability 1 - eps sin^2 / (1 + eps^2).
+              if (COUNT) ev[kEv_Compton]++;
+              const float k = E * (1.0f / kMec2);
+              const float e0 = 1.0f / fmaf(2.0f, k, 1.0f);
+              const float e02 = e0 * e0;
+              const float a1 = -__logf(e0);
+              const float a2 = 0.5f * (1.0f - e02);
+              float eps = 1.0f, t = 0.0f;
+              for (int it = 0; it < 64; ++it) {
+                const float u1 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                const float u2 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                const float u3 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                float eps2;
+                if (u1 * (a1 + a2) < a1) {
+                  eps = __expf(-a1 * u2);
+                  eps2 = eps * eps;
+                } else {
+                  eps2 = fmaf(1.0f - e02, u2, e02);
+                  eps = sqrtf(eps2);
+                }
+                t = (1.0f - eps) / (k * eps);
+                const float sin2 = t * (2.0f - t);
+                if (u3 * (1.0f + eps2) <= 1.0f + eps2 - eps * sin2) break;
+              }
+              const float Ep = eps * E;
+              const float dep = E - Ep;
+              edep_tot += dep;
+              if (active)
+                edep_act += dep;
+              else
+                clean = false;
+              turn(dx, dy, dz, 1.0f - t, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+              E = Ep;
+              if (E < P.e_cut) {
+                edep_tot += E;
+                if (active)
+                  edep_act += E;
+                else
+                  clean = false;
+                end_history(true, false, false, false);
+                absorbed = true;
+              } else {
+                ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+              }
+            } else {
+              // coherent: Thomson law 3/8 (1 + mu^2); its CDF (mu^3 + 3 mu + 4)/8
+              // inverts in closed form (Cardano): with a = 4u - 2,
+              // mu = c - 1/c, c = cbrt(a + sqrt(a^2 + 1)), taken on |a| for accuracy
+              if (COUNT) ev[kEv_Coherent]++;
+              const float a = fmaf(4.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -2.0f);
+              const float c = cbrtf(fabsf(a) + sqrtf(fmaf(a, a, 1.0f)));
+              const float ct = copysignf(c - 1.0f / c, a);
+              turn(dx, dy, dz, fminf(1.0f, fmaxf(-1.0f, ct)), rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+            }
+            if (!absorbed) tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+          }
+        } else {
+          // vacuum and no facet ahead: escape from the world, otherwise lost
+          clean = false;
+          if (region == 0)
+            end_history(false, true, false, false);
+          else
+            end_history(false, false, true, false);
         }
-        ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
-      } else {
-        // coherent: Thomson law 3/8 (1 + mu^2); its CDF (mu^3 + 3 mu + 4)/8
-        // inverts in closed form (Cardano): with a = 4u - 2,
-        // mu = c - 1/c, c = cbrt(a + sqrt(a^2 + 1)), taken on |a| for accuracy
-        if (COUNT) ev[kEv_Coherent]++;
-        const float a = fmaf(4.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -2.0f);
-        const float c = cbrtf(fabsf(a) + sqrtf(fmaf(a, a, 1.0f)));
-        const float ct = copysignf(c - 1.0f / c, a);
-        turn(dx, dy, dz, fminf(1.0f, fmaxf(-1.0f, ct)), rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
       }
-      tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
-      continue;
+
+      // ---- new histories for lanes that need one (chunks of the wave's unit)
+      const uint64_t need = __ballot(phase == kNeed);
+      if (need) {
+        if (next_h >= end_h && pend < 0 && !exhausted) {
+          unsigned long long c = 0;
+          if (lane == 0) c = atomicAdd(P.cursor, 1ull);
+          c = uniform_u64(__shfl(c, 0, kWave));
+          if (static_cast<int64_t>(c) >= total_chunks) {
+            exhausted = true;
+          } else {
+            int lo = 0, hi = P.n_units - 1;  // unit u: chunk_begin[u] <= c < chunk_begin[u+1]
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (P.chunk_begin[mid] <= static_cast<int64_t>(c))
+                lo = mid;
+              else
+                hi = mid - 1;
+            }
+            pend = lo;
+            const int64_t local = static_cast<int64_t>(c) - P.chunk_begin[lo];
+            pend_h0 = local * P.chunk;
+            const int64_t nu = P.units[lo].n;
+            pend_h1 = pend_h0 + P.chunk < nu ? pend_h0 + P.chunk : nu;
+          }
+        }
+        // a chunk of another unit starts only when no history of this one is open
+        if (next_h >= end_h && pend >= 0 && (pend == cur || __ballot(phase != kNeed) == 0)) {
+          if (pend != cur) {
+            flush();
+            cur = pend;
+            U = P.units[cur];
+            S = P.scenes[U.scene];
+            Src = P.sources[U.source];
+          }
+          next_h = pend_h0;
+          end_h = pend_h1;
+          pend = -1;
+        }
+        if (next_h < end_h) {
+          const uint64_t below = need & ((1ull << lane) - 1ull);
+          const int64_t h = next_h + __popcll(below);
+          if (phase == kNeed && h < end_h) {
+            // ---- emission
+            rng_start(g, static_cast<uint64_t>(U.first + h), U.stream);
+            if (COUNT) ev[kEv_Emissions]++;
+            if (Src.n_lines > 0) {
+              const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+              const float2* L = reinterpret_cast<const float2*>(P.lines) + Src.line_off;
+              int pick = Src.n_lines - 1;
+              for (int i = 0; i < Src.n_lines; ++i)
+                if (x < L[i].y) {
+                  pick = i;
+                  break;
+                }
+              E = L[pick].x;
+            } else {
+              E = U.energy;
+            }
+            const float E0 = E;
+            bool ok = true;
+            if (Src.kind == kCyl) {
+              ok = false;
+              const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
+              for (int attempt = 0; attempt < 1000 && !ok; ++attempt) {
+                const float rr2 = sqrtf(fmaf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
+                const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                px = Src.pos[0] + rr2 * __builtin_amdgcn_cosf(uphi);
+                py = Src.pos[1] + rr2 * __builtin_amdgcn_sinf(uphi);
+                pz = Src.pos[2] + rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * Src.h;
+                if (COUNT) ev[kEv_Locates]++;
+                uint32_t nv = 0, nt = 0;
+                ok = locate_parity<COUNT>(S, px, py, pz, stack, stride, COUNT ? ev[kEv_NodeVisits] : nv,
+                                          COUNT ? ev[kEv_TriTests] : nt) == Src.region;
+              }
+              region = Src.region;
+            } else {
+              px = Src.pos[0];
+              py = Src.pos[1];
+              pz = Src.pos[2];
+              region = U.src_region;
+              ok = region >= 0;
+            }
+            if (!ok) {
+              atomicAdd(&wt[kT_SrcFail], 1ull);
+              acc_hist += 1;
+            } else {
+              acc_esrc += fx(E0, kEnergyFix);
+              if (Src.kind == kBeam) {
+                dx = Src.dir[0];
+                dy = Src.dir[1];
+                dz = Src.dir[2];
+              } else {
+                const float ct = fmaf(2.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -1.0f);
+                const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+                const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                dx = st * __builtin_amdgcn_cosf(uphi);
+                dy = st * __builtin_amdgcn_sinf(uphi);
+                dz = ct;
+              }
+              tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+              ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+              edep_act = edep_tot = 0.0f;
+              clean = true;
+              interacted = touched = false;
+              last = -1;
+              steps = 0;
+#pragma unroll
+              for (int i = 0; i < kMaxGroups; ++i) sc[i] = 0.0f;
+              phase = kSetup;
+            }
+          }
+          next_h += __popcll(need);
+          if (next_h > end_h) next_h = end_h;
+        }
+      }
+
+      // ---- set up the next segment: attenuation, flight limit, ray
+      if (phase == kSetup) {
+        if (COUNT) ev[kEv_Segments]++;
+        const RegionRec rr = gload(P.regions, U.region_off + region);
+        float mh;
+        xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ix, mp, mc, mh);
+        mu = mp + mc + mh;
+        tbest = mu > 0.0f ? tau / mu : INFINITY;
+        ray = make_ray(px, py, pz, dx, dy, dz);
+        trej = INFINITY;
+        node = 0;
+        sp = 0;
+        tri_next = tri_end = 0;
+        best_slot = -1;
+        phase = kTrav;
+      }
+      if (__ballot(phase != kNeed) == 0 && exhausted && pend < 0 && next_h >= end_h) break;
     }
-    // vacuum and no facet ahead: escape from the world, otherwise lost
-    if (region == 0) {
-      clean = false;
-      end_history(false, true, false, false);
-    } else {
-      clean = false;
-      end_history(false, false, true, false);
+
+    // ================= one traversal step per traversing lane =================
+    if (phase == kTrav) {
+      if (tri_next >= tri_end && node < 0 && node != kDone) {
+        const int code = ~node;  // a leaf taken from the stack
+        tri_next = code >> 3;
+        tri_end = tri_next + (code & 7);
+        node = sp > 0 ? stack[(--sp) * stride] : kDone;
+      }
+      if (tri_next < tri_end) {
+        // one facet test, with the region-consistency filter
+        const int slot = tri_next++;
+        if (COUNT) ev[kEv_TriTests]++;
+        if (slot != last) {
+          float4 a, b, c;
+          load_tri(S.tris, slot, a, b, c);
+          float t;
+          bool enter;
+          if (wt_test(ray, a, b, c, tbest, t, enter) != kWtMiss) {
+            const uint32_t regs = __float_as_uint(c.y);
+            const int inside = static_cast<int>(regs & 0xFFFFu);
+            const int outside = static_cast<int>(regs >> 16);
+            if ((enter ? outside : inside) != region) {
+              trej = fminf(trej, t);
+            } else {
+              tbest = t;
+              best_slot = slot;
+              best_reg = enter ? inside : outside;
+            }
+          }
+        }
+      } else if (node >= 0) {
+        // one node: both child boxes against [0, tbest]
+        if (COUNT) ev[kEv_NodeVisits]++;
+        float4 n0, n1, n2;
+        int4 n3;
+        load_node(S.nodes, node, n0, n1, n2, n3);
+        const float tl = slab(ray, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, tbest);
+        const float tr = slab(ray, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, tbest);
+        const bool hl = tl != INFINITY, hr = tr != INFINITY;
+        int near = kDone, far = kDone;
+        if (hl && hr) {
+          const bool lfirst = tl <= tr;
+          near = lfirst ? n3.x : n3.y;
+          far = lfirst ? n3.y : n3.x;
+        } else if (hl) {
+          near = n3.x;
+        } else if (hr) {
+          near = n3.y;
+        }
+        if (near == kDone) {
+          node = sp > 0 ? stack[(--sp) * stride] : kDone;
+        } else if (near < 0) {
+          // nearest child is a leaf: test its facets next, then go to `far`
+          const int code = ~near;
+          tri_next = code >> 3;
+          tri_end = tri_next + (code & 7);
+          node = far != kDone ? far : (sp > 0 ? stack[(--sp) * stride] : kDone);
+        } else {
+          if (far != kDone && sp < S.depth) {
+            stack[sp * stride] = far;
+            ++sp;
+          }
+          node = near;
+        }
+      }
+      if (tri_next >= tri_end && node == kDone) phase = kParked;
     }
   }
   flush();
@@ -630,7 +732,7 @@ __global__ void raycast_kernel(SceneRec sc, const float* o, const float* d, cons
   if (closest_hit<false>(sc, r, INFINITY, -1, cur, lstack + threadIdx.x, blockDim.x, h, glitch, a,
                          b)) {
     t[i] = h.t;
-    tri[i] = sc.tris[h.slot].orig;
+    tri[i] = gload(sc.tris, h.slot).orig;
     region_after[i] = h.region_after;
   } else {
     t[i] = INFINITY;

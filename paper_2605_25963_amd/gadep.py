@@ -78,7 +78,8 @@ class Counters(C.Structure):
 
 class MeshInfo(C.Structure):
     _fields_ = [("n_shells", C.c_int32), ("genus_max", C.c_int32), ("n_nodes", C.c_int64),
-                ("depth", C.c_int32), ("sah_cost", C.c_double), ("min_gap_mm", C.c_double)]
+                ("depth", C.c_int32), ("sah_cost", C.c_double), ("min_gap_mm", C.c_double),
+                ("convex_exit", C.c_int32)]
 
 
 EXPORTS = [
@@ -420,7 +421,8 @@ def mesh_prepare(xyz, tri, tri_region, n_regions, min_gap_mm=1e-4, validate=True
         raise GadepError(rc, err.value.decode(errors="replace"))
     res = dict(outside=outside, shell=shell, order=order, n_shells=info.n_shells,
                genus_max=info.genus_max, n_nodes=info.n_nodes, depth=info.depth,
-               sah_cost=info.sah_cost, min_gap_mm=info.min_gap_mm)
+               sah_cost=info.sah_cost, min_gap_mm=info.min_gap_mm,
+               convex_exit=bool(info.convex_exit))
     if nodes is not None:
         res["nodes"] = nodes[: info.n_nodes]
     return res

@@ -225,3 +225,13 @@ def test_bvh_invariants(G, cfg):
     assert 1 <= r["depth"] <= 64
     med = prep(G, sc, bvh_method=1)
     assert r["sah_cost"] <= med["sah_cost"] * 1.0001
+
+
+def test_convex_exit_flag(G):
+    assert prep(G, C.c1_bare().scene)["convex_exit"]  # single convex prism
+    assert prep(G, C.c2_hpge(n_seg=32, n_phi=4).scene)["convex_exit"]  # air box encloses all
+    b = mg.SceneBuilder()
+    b.add("ring", "Cu", 8.96, _torus(20.0, 5.0, 24, 12))
+    assert not prep(G, b.build())["convex_exit"]  # non-convex outer shell
+    job = C.c3_jobs(2)[0]
+    assert not prep(G, C.c3_job_workload(job).scene)["convex_exit"]  # two top-level shells
