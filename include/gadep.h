@@ -70,7 +70,10 @@ const char* gadep_last_error(const gadep_ctx* ctx);
 typedef enum {
   GADEP_OPT_MAX_STEPS = 1,    /* per-history segment limit (watchdog), default 10000   */
   GADEP_OPT_BLOCK = 2,        /* threads per block of the transport kernel, 64..1024   */
-  GADEP_OPT_PERIOD = 3,       /* segments between block-wide compactions, 0 = never    */
+  GADEP_OPT_PERIOD = 3,       /* park threshold: lanes of a wavefront that finish their
+                                 traversal wait until this many (1..64) have, then the
+                                 wavefront runs physics, scoring and new histories for
+                                 all of them together; 0 = default (32)                */
   GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim            */
   GADEP_OPT_VALIDATE = 5,     /* 1 = validate meshes at load (default); 0 skips the
                                  closed/orientation/overlap checks (fault-injection
@@ -201,9 +204,10 @@ typedef struct {
 gadep_status gadep_run_batch(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
                              uint64_t seed, gadep_tally* out, double* grads, double* grads_var);
 
-/* Times short pilot launches of `jobs` over block sizes, compaction periods
- * and claim sizes, keeps the fastest in the context and returns it (any
- * output pointer may be NULL).  Tallies never depend on these settings. */
+/* Times short pilot launches of `jobs` (scaled down to about pilot_histories
+ * in total) over block sizes, park thresholds (GADEP_OPT_PERIOD) and claim
+ * sizes, keeps the fastest in the context and returns it (any output pointer
+ * may be NULL).  Tallies never depend on these settings. */
 gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
                             int64_t pilot_histories, int32_t* block, int32_t* period,
                             int32_t* claim);

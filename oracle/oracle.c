@@ -19,7 +19,9 @@
 #define R_E 2.8179403262e-13     /* classical electron radius [cm] */
 #define MAX_MATERIALS 64
 #define LEAF_MAX 4
-#define STEP_PAST 1.0e-6         /* mm: probe point just beyond a crossed facet */
+#define STEP_PAST 1.0e-6         /* mm along the flight, past a crossed facet */
+#define STEP_NORMAL 1.0e-7       /* mm along the facet normal: keeps grazing crossings
+                                    clear of the facet's degenerate band */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10: a 4x32-bit counter is enciphered with a 2x32-bit key by ten
@@ -682,7 +684,16 @@ static void one_history(worker* w, int64_t h) {
       tau -= mu * th;
       if (gidx >= 0 && gidx < w->ngroups) tau0[gidx] += mu0 * th;
       for (int a = 0; a < 3; ++a) p[a] += th * d[a];
-      double q[3] = {p[0] + STEP_PAST * d[0], p[1] + STEP_PAST * d[1], p[2] + STEP_PAST * d[2]};
+      /* probe point just past the crossed facet, on the side the flight goes to */
+      const double* fv = V(s, tri);
+      double e1[3], e2[3], fn[3];
+      sub3(fv + 3, fv, e1);
+      sub3(fv + 6, fv, e2);
+      cross3(e1, e2, fn);
+      const double fl = norm3(fn);
+      const double side = dot3(d, fn) >= 0.0 ? STEP_NORMAL / fl : -STEP_NORMAL / fl;
+      double q[3];
+      for (int a = 0; a < 3; ++a) q[a] = p[a] + STEP_PAST * d[a] + side * fn[a];
       region = orc_locate(s, q);
       last = tri;
       T->n_crossings++;

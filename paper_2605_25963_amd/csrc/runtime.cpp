@@ -632,7 +632,7 @@ gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t v) {
       ctx->block = v;
       return GADEP_OK;
     case GADEP_OPT_PERIOD:
-      if (v < 0 || v > 1024) return set_err(ctx, GADEP_E_ARG, "period out of range");
+      if (v < 0 || v > 64) return set_err(ctx, GADEP_E_ARG, "park threshold must be in [0, 64]");
       ctx->period = v;
       return GADEP_OK;
     case GADEP_OPT_CLAIM:
@@ -827,37 +827,51 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
   size_t units = 0;
   for (auto& j : pj) units += std::max(1, j.n_energies);
   std::vector<gadep_tally> out(units);
-  const int64_t saved_block = ctx->block, saved_claim = ctx->claim, saved_graphs = ctx->graphs;
+  const int64_t saved_block = ctx->block, saved_claim = ctx->claim, saved_period = ctx->period,
+                saved_graphs = ctx->graphs;
+  auto restore = [&]() {
+    ctx->block = saved_block;
+    ctx->claim = saved_claim;
+    ctx->period = saved_period;
+    ctx->graphs = saved_graphs;
+  };
   ctx->graphs = 0;
   float best = INFINITY;
-  int64_t best_block = saved_block, best_claim = saved_claim;
-  const int64_t blocks[] = {64, 128, 256};
-  const int64_t claims[] = {4, 16, 64};
+  int64_t best_block = saved_block, best_claim = saved_claim, best_period = saved_period;
+  // block size x claim size x park threshold (lanes parked before the wavefront
+  // runs the batched physics); tallies do not depend on any of them
+  const int64_t blocks[] = {128, 256};
+  const int64_t claims[] = {8, 32};
+  const int64_t periods[] = {16, 32, 48};
   for (int64_t b : blocks)
-    for (int64_t c : claims) {
-      ctx->block = b;
-      ctx->claim = c;
-      Plan P;
-      gadep_status s = plan_jobs(ctx, pj.data(), static_cast<int32_t>(pj.size()), out.data(), false, P);
-      if (s) {
-        ctx->block = saved_block, ctx->claim = saved_claim, ctx->graphs = saved_graphs;
-        return s;
+    for (int64_t c : claims)
+      for (int64_t q : periods) {
+        ctx->block = b;
+        ctx->claim = c;
+        ctx->period = q;
+        Plan P;
+        gadep_status s = plan_jobs(ctx, pj.data(), static_cast<int32_t>(pj.size()), out.data(), false, P);
+        if (s) {
+          restore();
+          return s;
+        }
+        float ms = 0, ms2 = 0;
+        s = execute(ctx, P, 12345, out.data(), nullptr, nullptr, 0, &ms);  // warm-up
+        if (!s) s = execute(ctx, P, 12345, out.data(), nullptr, nullptr, 0, &ms2);
+        if (s) {
+          restore();
+          return s;
+        }
+        if (ms2 < best) {
+          best = ms2;
+          best_block = b;
+          best_claim = c;
+          best_period = q;
+        }
       }
-      float ms = 0, ms2 = 0;
-      s = execute(ctx, P, 12345, out.data(), nullptr, nullptr, 0, &ms);  // warm-up
-      if (!s) s = execute(ctx, P, 12345, out.data(), nullptr, nullptr, 0, &ms2);
-      if (s) {
-        ctx->block = saved_block, ctx->claim = saved_claim, ctx->graphs = saved_graphs;
-        return s;
-      }
-      if (ms2 < best) {
-        best = ms2;
-        best_block = b;
-        best_claim = c;
-      }
-    }
   ctx->block = best_block;
   ctx->claim = best_claim;
+  ctx->period = best_period;
   ctx->graphs = saved_graphs;
   if (block_out) *block_out = static_cast<int32_t>(best_block);
   if (period_out) *period_out = static_cast<int32_t>(ctx->period);

@@ -430,3 +430,27 @@ def test_scales_apply_only_to_listed_groups(orc):
     assert np.allclose(scaled, 2.0 * base, rtol=1e-15)
     dead = w.scene.region_id("dead")  # group 0
     assert np.allclose(s.mu(dead, 100.0, scales=[3.0]), 3.0 * s.mu(dead, 100.0), rtol=1e-15)
+
+
+def test_grazing_crossings_keep_their_region(orc):
+    # a pencil beam almost parallel to a face (d.n = 2e-4) crosses into nested
+    # boxes; every crossing must still be localised (none lost) and the
+    # transmitted fraction must follow the attenuation along the actual path
+    b = mg.SceneBuilder("vacuum", 0.0)
+    b.add("outer", "synthetic", 1.0, mg.box((-50, -50, -50), (50, 50, 50)), group=0, active=True)
+    b.add("inner", "synthetic", 1.0, mg.box((-20, -20, -20), (20, 20, 20)), group=0, active=True)
+    scene = b.build()
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    s.set_region(0, 0, 0.0)
+    s.set_region(1, 1, 1.0, 0, True)
+    s.set_region(2, 1, 1.0, 0, True)
+    lnE0, dlnE, n = xsgen.grid()
+    s.set_xs(0, (lnE0, dlnE, n), *xsgen.constant_table(n=n))
+    s.set_xs(1, (lnE0, dlnE, n), *xsgen.constant_table(0.01, 0, 0, n=n))  # mu = 1e-3 /mm
+    d = np.array([1.0, 0.0, -2e-4])
+    d /= np.linalg.norm(d)
+    src = C.Source(C.KIND_BEAM, pos=(-60.0, 3.3, 20.0 + 40 * 2e-4 + 1e-3), direction=tuple(d))
+    r = s.run(src, 100.0, 100_000, 2111)
+    t = r.tally
+    assert t.n_lost == 0 and t.n_balance_fail == 0
+    assert t.n_crossings >= 2 * t.n_escape
