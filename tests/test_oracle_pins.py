@@ -433,7 +433,7 @@ def test_scales_apply_only_to_listed_groups(orc):
 
 
 def test_grazing_crossings_keep_their_region(orc):
-    # a pencil beam almost parallel to a face (d.n = 2e-4) crosses into nested
+    # a pencil beam almost parallel to a face (d.n = 1e-5) crosses into nested
     # boxes; every crossing must still be localised (none lost) and the
     # transmitted fraction must follow the attenuation along the actual path
     b = mg.SceneBuilder("vacuum", 0.0)
@@ -447,9 +447,9 @@ def test_grazing_crossings_keep_their_region(orc):
     lnE0, dlnE, n = xsgen.grid()
     s.set_xs(0, (lnE0, dlnE, n), *xsgen.constant_table(n=n))
     s.set_xs(1, (lnE0, dlnE, n), *xsgen.constant_table(0.01, 0, 0, n=n))  # mu = 1e-3 /mm
-    d = np.array([1.0, 0.0, -2e-4])
+    d = np.array([1.0, 0.0, -1e-5])
     d /= np.linalg.norm(d)
-    src = C.Source(C.KIND_BEAM, pos=(-60.0, 3.3, 20.0 + 40 * 2e-4 + 1e-3), direction=tuple(d))
+    src = C.Source(C.KIND_BEAM, pos=(-60.0, 3.3, 20.0 + 6e-4), direction=tuple(d))
     r = s.run(src, 100.0, 100_000, 2111)
     t = r.tally
     assert t.n_lost == 0 and t.n_balance_fail == 0
