@@ -94,13 +94,23 @@ _lib = None
 
 
 def lib():
-    """The loaded library; raises if it has not been built."""
+    """The loaded library; raises if it has not been built.
+
+    torch (when installed) is imported first: it carries its own HIP runtime
+    under the same soname, and loading it before libgadep.so makes the library
+    bind to that runtime, so one process has one HIP runtime and torch tensors
+    and streams can be handed to the library.
+    """
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(there is no CPU fallback)")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     p, i32, i64, u64, f32p, i32p, dp = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint64,
                                         C.POINTER(C.c_float), C.POINTER(C.c_int32),

@@ -1,0 +1,343 @@
+"""GPU tests of the remaining hot-path rows, through the C interface:
+volume sources, coherent scattering and line spectra, detector-scale
+gradients (oracle, CRN finite differences), broadening, batches with
+per-job scenes and overrides, autotuner, graph replay, error paths, fault
+counters, the full-size benchmark configuration, and the autograd wrapper."""
+import math
+
+import numpy as np
+import pytest
+
+from workloads import configs as C
+from workloads import meshgen as mg
+from workloads import xsgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2605_25963_amd import gadep
+    gadep.lib()
+    return gadep
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def binom_sigma(k, n):
+    p = k / n
+    return math.sqrt(max(p * (1 - p), 1.0 / n) / n)
+
+
+def close3(a, sa, b, sb, k=3.0):
+    return abs(a - b) <= k * math.hypot(sa, sb)
+
+
+def chi2_p(a, b, min_count=20):
+    from scipy import stats
+    ra, rb, ca, cb = [], [], 0.0, 0.0
+    for x, y in zip(np.asarray(a, float), np.asarray(b, float)):
+        ca += x
+        cb += y
+        if ca >= min_count and cb >= min_count:
+            ra.append(ca)
+            rb.append(cb)
+            ca = cb = 0.0
+    if ra:
+        ra[-1] += ca
+        rb[-1] += cb
+    ra, rb = np.array(ra), np.array(rb)
+    na, nb = ra.sum(), rb.sum()
+    k1, k2 = math.sqrt(nb / na), math.sqrt(na / nb)
+    chi2 = (((k1 * ra - k2 * rb) ** 2) / (ra + rb)).sum()
+    return stats.chi2.sf(chi2, len(ra) - 1)
+
+
+# --------------------------------------------------------------------------
+# volume source (bottle on the bare crystal)
+
+def test_volume_source_matches_oracle(G, ctx, orc):
+    job = C.c3_jobs(64)[0]
+    w = C.c3_job_workload(job)
+    G.load_workload(ctx, w)
+    s = orc.scene_from_workload(w)
+    E = [60.0, 300.0, 1200.0]
+    ng, no = 4_000_000, 200_000
+    r = ctx.run(w.source, E, ng, 31)
+    for k, e in enumerate(E):
+        t = r.tallies[k]
+        o = s.run(w.source, e, no, 2031 + k)
+        assert t.n_source_fail == 0 and t.n_lost == 0 and t.n_killed == 0
+        assert close3(t.n_fep / ng, binom_sigma(t.n_fep, ng), o.fepe(), o.fepe_sigma()), e
+        assert close3(t.n_absorbed / ng, binom_sigma(t.n_absorbed, ng),
+                      o.tally.n_absorbed / no, binom_sigma(o.tally.n_absorbed, no)), e
+        assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# gradients on the detector with a sample (6 density groups)
+
+def test_detector_gradients_match_oracle_and_crn_fd(G, ctx, orc):
+    w = C.c4_grad(n_histories=1)
+    G.load_workload(ctx, w)
+    s = orc.scene_from_workload(w)
+    ng, no = 10_000_000, 300_000
+    scales = [1.0] * 6
+    E = [100.0, 661.7]
+    r = ctx.run_grad(w.source, E, ng, 41, scales)
+    for k, e in enumerate(E):
+        o = s.run(w.source, e, no, 2041 + k, scales=scales)
+        t = r.tallies[k]
+        assert close3(t.n_fep / ng, binom_sigma(t.n_fep, ng), o.fepe(), o.fepe_sigma())
+        gg, gs = r.grad[k], np.sqrt(r.grad_var[k])
+        og, os_ = o.grad(6), o.grad_sigma(6)
+        for gi in range(6):
+            assert close3(gg[gi], gs[gi], og[gi], os_[gi]), (e, w.groups[gi], gg[gi], og[gi])
+    # common-random-number finite differences at +-1 % for three groups; the
+    # FD's own error comes from 10 independent batches (disjoint history ranges)
+    h, nb = 0.01, 10
+    for gi in (0, 1, 5):  # dead layer, crystal, matrix
+        up = list(scales)
+        dn = list(scales)
+        up[gi] += h
+        dn[gi] -= h
+        fds = []
+        for b in range(nb):
+            fu = ctx.run_grad(w.source, E, ng // nb, 41, up, first_history=b * (ng // nb)).fepe()
+            fl = ctx.run_grad(w.source, E, ng // nb, 41, dn, first_history=b * (ng // nb)).fepe()
+            fds.append((fu - fl) / (2 * h))
+        fds = np.array(fds)
+        fd, fd_sig = fds.mean(0), fds.std(0, ddof=1) / math.sqrt(nb)
+        for k in range(len(E)):
+            g, gs = r.grad[k, gi], math.sqrt(r.grad_var[k, gi])
+            tol = max(0.02 * abs(fd[k]), 3 * math.hypot(gs, fd_sig[k]))
+            assert abs(g - fd[k]) <= tol, (w.groups[gi], E[k], g, fd[k], fd_sig[k])
+
+
+# --------------------------------------------------------------------------
+# coherent scattering, line source, spectrum and its broadening
+
+def test_coherent_lines_spectrum_match_oracle(G, ctx, orc):
+    w = C.c5_stress(n_histories=1, n_seg=64, n_phi=8, z_slices=1)
+    G.load_workload(ctx, w)
+    s = orc.scene_from_workload(w)
+    ng, no = 4_000_000, 400_000
+    nch, width = 8192, 0.25
+    ctx.set_option(G.OPT_COUNTERS, 1)
+    r = ctx.run(w.source, None, ng, 51, spectrum=(nch, width))
+    ev = ctx.get_counters()
+    ctx.set_option(G.OPT_COUNTERS, 0)
+    o = s.run(w.source, 0.0, no, 2051, n_channels=nch, channel_keV=width)
+    t = r.tallies[0]
+    assert t.n_source_fail == 0 and t.n_lost == 0
+    assert close3(t.n_fep / ng, binom_sigma(t.n_fep, ng), o.fepe(), o.fepe_sigma())
+    # coherent and Compton interactions per history; a history can scatter
+    # several times, so the error of a mean count is taken as 2 sqrt(count)/n
+    for name, on in (("coherent", o.tally.n_coherent), ("compton", o.tally.n_compton)):
+        a, b = ev[name] / ng, on / no
+        assert close3(a, 2 * math.sqrt(ev[name]) / ng, b, 2 * math.sqrt(on) / no), name
+    assert chi2_p(r.spectra[0], o.spectrum) > 1e-3
+    # source-energy bookkeeping of the line draw: mean emitted energy
+    lines = np.array(C.TABLE3_LINES_KEV)
+    mean_e = t.e_source_keV / t.n_histories
+    assert abs(mean_e - lines.mean()) <= 4 * lines.std() / math.sqrt(ng)
+    assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+
+    # broadening on the device vs the oracle's, on the same measured spectrum
+    import torch
+    spec = torch.tensor(r.spectra[0].astype(np.float64), device="cuda")
+    out = torch.zeros_like(spec)
+    torch.cuda.synchronize()
+    ctx.broaden_dev(spec.data_ptr(), out.data_ptr(), 1, nch, width, 0.64, 0.0018)
+    ref = orc.broaden(r.spectra[0].astype(np.float64), width, 0.64, 0.0018)
+    got = out.cpu().numpy()
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-9)
+    # away from 0 keV (where part of a count is spread below channel 0) the
+    # broadening conserves counts up to the 5-sigma truncation
+    high = r.spectra[0].astype(np.float64)
+    high[: int(10.0 / width)] = 0.0
+    spec2 = torch.tensor(high, device="cuda")
+    ctx.broaden_dev(spec2.data_ptr(), out.data_ptr(), 1, nch, width, 0.64, 0.0018)
+    assert out.sum().item() == pytest.approx(high.sum(), rel=1e-5)
+
+
+# --------------------------------------------------------------------------
+# batches: per-job scenes and region overrides
+
+def test_batch_with_scenes_and_overrides(G, ctx):
+    jobs = C.c3_jobs(64)[:3]
+    ws = [C.c3_job_workload(j) for j in jobs]
+    for k, w in enumerate(ws):
+        G.load_workload(ctx, w, scene=k)
+    E = [100.0, 600.0]
+    spec = [dict(source=w.source, energies=E, n_histories=400_000, scene=k, stream=10 + k)
+            for k, w in enumerate(ws)]
+    batch = ctx.run_batch(spec, 61)
+    for k in range(3):
+        single = ctx.run_batch([spec[k]], 61)
+        for f in ("n_histories", "n_fep", "n_absorbed", "edep_active_keV", "e_escape_keV"):
+            assert np.array_equal(single.field(f), batch.field(f)[2 * k:2 * k + 2]), (k, f)
+    # a density override equals a scene loaded with that density
+    w = ws[1]
+    mat, rho, grp, act = w.region_arrays()
+    m = w.scene.region_id("matrix")
+    rho2 = rho.copy()
+    rho2[m] *= 2.0
+    regions2 = [(int(mat[r]), float(rho2[r]), int(grp[r]), G.ACTIVE if act[r] else 0)
+                for r in range(len(mat))]
+    ctx.load_scene(3, w.scene.xyz, w.scene.tri, w.scene.tri_region, regions2)
+    over = ctx.run_batch([dict(spec[1], density_override=rho2)], 62)
+    dens = ctx.run_batch([dict(spec[1], scene=3)], 62)
+    for f in ("n_fep", "n_absorbed", "edep_total_keV"):
+        assert np.array_equal(over.field(f), dens.field(f)), f
+    plain = ctx.run_batch([spec[1]], 62)
+    assert not np.array_equal(plain.field("n_absorbed"), over.field("n_absorbed"))
+
+
+# --------------------------------------------------------------------------
+# autotuner and graph replay do not change results
+
+def test_autotune_and_graph_replay_keep_tallies(G, ctx):
+    w = C.c2_hpge(n_histories=1, distance=20.0)
+    G.load_workload(ctx, w)
+    job = [dict(source=w.source, energies=[80.0, 700.0], n_histories=2_000_000, stream=3)]
+    base = ctx.run_batch(job, 71)
+    block, period, claim = ctx.autotune(job, 400_000)
+    assert block in (128, 256) and period in (16, 32, 48) and claim in (8, 32)
+    assert ctx.get_option(G.OPT_BLOCK) == block
+    tuned = ctx.run_batch(job, 71)
+    replays = [ctx.run_batch(job, 71) for _ in range(3)]
+    ctx.set_option(G.OPT_GRAPHS, 0)
+    eager = ctx.run_batch(job, 71)
+    ctx.set_option(G.OPT_GRAPHS, 1)
+    after = ctx.run_batch(job, 71)
+    for other in [tuned, eager, after] + replays:
+        for f in ("n_histories", "n_fep", "n_absorbed", "n_uncollided", "edep_active_keV"):
+            assert np.array_equal(base.field(f), other.field(f)), f
+    ctx.set_option(G.OPT_BLOCK, 256)
+    ctx.set_option(G.OPT_CLAIM, 32)
+    ctx.set_option(G.OPT_PERIOD, 0)
+
+
+# --------------------------------------------------------------------------
+# error handling and fault counters (all conditions forced from the host)
+
+def test_error_paths(G):
+    with G.Context(0) as c:
+        src = G.make_source(G.SRC_POINT, pos=(0, 0, 100))
+        with pytest.raises(G.GadepError) as e:
+            c.run(src, [661.7], 10, 1)
+        assert e.value.name == "GADEP_E_STATE"  # no cross sections yet
+        w = C.c1_bare()
+        for m, tab in w.tables.items():
+            c.set_xs(m, w.grid, *tab)
+        with pytest.raises(G.GadepError) as e:
+            c.run(src, [661.7], 10, 1)
+        assert e.value.name == "GADEP_E_STATE"  # no scene yet
+        G.load_workload(c, w)
+        with pytest.raises(G.GadepError) as e:
+            c.run(src, [5000.0], 10, 1)
+        assert e.value.name == "GADEP_E_XS"  # outside the table grid
+        with pytest.raises(G.GadepError) as e:
+            c.run_grad(src, [661.7], 10, 1, [0.0])
+        assert e.value.name == "GADEP_E_ARG"
+        with pytest.raises(G.GadepError) as e:
+            c.set_option(G.OPT_BLOCK, 96)
+        assert e.value.name == "GADEP_E_ARG"
+        with pytest.raises(G.GadepError) as e:
+            c.set_xs(1, (0.0, 0.01, 1024), np.full(1024, -1.0), np.ones(1024))
+        assert e.value.name == "GADEP_E_XS"
+        bad = G.make_source(G.SRC_CYL, pos=(0, 0, 0), r_out=5, h=5, region=99)
+        with pytest.raises(G.GadepError) as e:
+            c.run(bad, [661.7], 10, 1)
+        assert e.value.name == "GADEP_E_ARG"
+        r = c.run(src, [661.7], 0, 1)  # zero histories is a valid empty run
+        assert r.tallies[0].n_histories == 0
+
+
+def test_lost_and_watchdog_counters(G):
+    with G.Context(0) as c:
+        w = C.c2_hpge(n_histories=1, n_seg=32, n_phi=4, distance=20.0)
+        sc = w.scene
+        mat, rho, grp, act = w.region_arrays()
+        regions = [(int(mat[r]), float(rho[r]), int(grp[r]), G.ACTIVE if act[r] else 0)
+                   for r in range(len(mat))]
+        for m, tab in w.tables.items():
+            c.set_xs(m, w.grid, *tab)
+        # drop one facet of the vacuum interior shell: photons leak and are lost
+        name, first, n = [x for x in sc.shells if x[0] == "interior"][0]
+        keep = np.ones(len(sc.tri), bool)
+        keep[first + n // 2] = False
+        c.set_option(G.OPT_VALIDATE, 0)
+        c.load_mesh(sc.xyz, sc.tri[keep], sc.tri_region[keep], regions)
+        r = c.run(w.source, [661.7], 2_000_000, 81)
+        assert r.tallies[0].n_lost > 0
+        assert r.tallies[0].n_histories == 2_000_000
+        c.set_option(G.OPT_VALIDATE, 1)
+        with pytest.raises(G.GadepError) as e:
+            c.load_mesh(sc.xyz, sc.tri[keep], sc.tri_region[keep], regions)
+        assert e.value.name == "GADEP_E_MESH_OPEN"
+        G.load_workload(c, w)
+        c.set_option(G.OPT_MAX_STEPS, 1)
+        r = c.run(w.source, [661.7], 1_000_000, 82)
+        t = r.tallies[0]
+        assert t.n_killed > 0 and t.n_fep == 0
+        assert t.n_histories == 1_000_000
+
+
+# --------------------------------------------------------------------------
+# the benchmark configuration at full size
+
+def test_full_size_hpge_properties_and_oracle_sample(G, ctx, orc):
+    w = C.c2_hpge(n_histories=1)
+    G.load_workload(ctx, w)
+    n = 100_000_000
+    jobs = [dict(source=w.source, energies=[E], n_histories=n, stream=k)
+            for k, E in enumerate(w.energies)]
+    r = ctx.run_batch(jobs, 1002)
+    s = orc.scene_from_workload(w)
+    # no ray from the source reaches the ACTIVE core outside the cone of its
+    # front disk (r 31.3 at z = -0.7, source at z = 255.5)
+    d = 255.5 + 0.7
+    bound = 0.5 * (1 - d / math.hypot(d, 31.3))
+    no = 1_000_000
+    for k, E in enumerate(w.energies):
+        t = r.tallies[k]
+        assert t.n_histories == n and t.n_lost == 0 and t.n_killed == 0
+        assert t.n_glitch <= 1e-6 * n
+        p = t.n_fep / n
+        assert 0 < p < bound
+        assert math.sqrt((1 - p) / (n * p)) < 0.0065
+        assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+        o = s.run(w.source, E, no, 3002 + k)
+        assert close3(p, binom_sigma(t.n_fep, n), o.fepe(), o.fepe_sigma()), (E, p, o.fepe())
+
+
+# --------------------------------------------------------------------------
+# autograd wrapper
+
+def test_autograd_wrapper(G, ctx):
+    import torch
+    from paper_2605_25963_amd.autograd import GadepFEPE
+    scene, mats, tabs, grid = C.slab(5.0, 2.0)
+    for m, t in tabs.items():
+        ctx.set_xs(m, grid, *t)
+    ctx.load_scene(0, scene.xyz, scene.tri, scene.tri_region, [(0, 0.0, -1, 0), (1, 1.0, 0, G.ACTIVE)])
+    src = C.Source(C.KIND_BEAM, pos=(0.1234, 0.4321, 10.0), direction=(0.0, 0.0, -1.0))
+    job = dict(source=src, energies=[300.0, 661.7], n_histories=2_000_000, seed=91)
+    scales = torch.tensor([1.2], dtype=torch.float32, device="cuda", requires_grad=True)
+    fepe = GadepFEPE.apply(scales, ctx, job)
+    assert fepe.device.type == "cuda" and fepe.shape == (2,)
+    weights = torch.tensor([1.0, 0.5], dtype=torch.float64, device="cuda")
+    (fepe * weights).sum().backward()
+    r = ctx.run_grad(src, job["energies"], job["n_histories"], 91, [1.2])
+    expect = float(r.grad[0, 0] * 1.0 + r.grad[1, 0] * 0.5)
+    assert scales.grad.item() == pytest.approx(expect, rel=1e-6)
+    # and it estimates d/ds (1 - exp(-s mu t)) = mu t exp(-s mu t), mu t = 1
+    gsig = math.sqrt(r.grad_var[0, 0])
+    assert abs(r.grad[0, 0] - math.exp(-1.2)) <= 3 * gsig
