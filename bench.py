@@ -40,6 +40,7 @@ OPS_PER_EVENT = {
     "coherent": 70,      # Cardano inverse of the Thomson CDF, rotation
     "crossings": 10,     # region update, tau update, bookkeeping
     "locates": 40,       # probe-ray set-up (its traversal is in node_visits/tri_tests)
+    "plane_tests": 13,   # exit plane: two 3-term dot products, reciprocal, product, min
 }
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz one-lane-op slots per second
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -169,12 +170,18 @@ def main():
     ev = ctx.get_counters()
     ctx.set_option(gadep.OPT_COUNTERS, 0)
     ops = sum(OPS_PER_EVENT[k] * ev[k] for k in OPS_PER_EVENT)
+    # lanes busy per wavefront step: node visits per iteration with a node
+    # step, facet tests per iteration with a facet test
+    lanes = {"node": ev["node_visits"] / max(ev["iterations_node"], 1),
+             "facet": ev["tri_tests"] / max(ev["iterations_facet"], 1),
+             "iterations_per_pass": ev["iterations"] / max(ev["passes"], 1)}
     k_ms = float(np.mean(kernel_ms))
     achieved = ops / (k_ms * 1e-3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
             "kernel_ms": k_ms, "ops_per_history": ops / total,
-            "events_per_history": {k: ev[k] / total for k in ev}}
+            "events_per_history": {k: ev[k] / total for k in ev},
+            "active_lanes": lanes}
 
     base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
     line = {

@@ -69,7 +69,8 @@ const char* gadep_last_error(const gadep_ctx* ctx);
 /* Tunables and switches (gadep_set_option / gadep_get_option). */
 typedef enum {
   GADEP_OPT_MAX_STEPS = 1,    /* per-history segment limit (watchdog), default 10000   */
-  GADEP_OPT_BLOCK = 2,        /* threads per block of the transport kernel, 64..1024   */
+  GADEP_OPT_BLOCK = 2,        /* threads per block of the transport kernel: 64..256,
+                                 a multiple of 64 (256)                                 */
   GADEP_OPT_PERIOD = 3,       /* park threshold: lanes of a wavefront that finish their
                                  traversal wait until this many (1..64) have, then the
                                  wavefront runs physics, scoring and new histories for
@@ -81,7 +82,12 @@ typedef enum {
   GADEP_OPT_MIN_GAP_NM = 6,   /* smallest allowed distance between shells, nm (100)    */
   GADEP_OPT_GRAPHS = 7,       /* 1 = replay captured HIP graphs for repeated runs (1)  */
   GADEP_OPT_COUNTERS = 8,     /* 1 = count events (segments, node visits, ...) (0)     */
-  GADEP_OPT_GRID = 9          /* blocks of the persistent grid, 0 = from occupancy     */
+  GADEP_OPT_GRID = 9,         /* blocks of the persistent grid, 0 = from occupancy     */
+  GADEP_OPT_EXIT_PLANES = 10, /* 1 = leave a convex outermost shell through its planes
+                                 when the world is void (1); 0 = through its facets   */
+  GADEP_OPT_SPLIT_PCT = 11    /* extra facet slots the transport BVH may add by spatial
+                                 splits, % of its facets (100); 0 = no spatial splits;
+                                 applies to meshes loaded afterwards                  */
 } gadep_option;
 gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t value);
 gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* value);
@@ -216,6 +222,11 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
 typedef struct {
   uint64_t segments, crossings, node_visits, tri_tests, photo, compton, coherent, rng_calls,
       locates, emissions;
+  uint64_t plane_tests; /* exit-plane evaluations (see gadep_mesh_info.n_exit_planes) */
+  /* per wavefront: traversal-loop iterations, those in which some lane took a
+   * node step / a facet test, and passes of the batched per-segment work
+   * (outcomes, new histories, set-up) */
+  uint64_t iterations, iterations_node, iterations_facet, passes;
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 
@@ -253,28 +264,40 @@ gadep_status gadep_locate(gadep_ctx* ctx, int32_t scene, const float* p, int64_t
 typedef struct {
   int32_t n_shells;       /* connected closed surfaces */
   int32_t genus_max;      /* largest shell genus, from the Euler characteristic */
-  int64_t n_nodes;        /* BVH nodes (each holds two children) */
-  int32_t depth;          /* BVH depth = traversal stack needed */
-  double sah_cost;        /* SAH cost with unit traversal and intersection cost */
+  int64_t n_nodes;        /* nodes of the returned BVH (each holds two children) */
+  int32_t depth;          /* its depth = traversal stack needed */
+  double sah_cost;        /* its SAH cost, unit traversal and intersection costs */
+  int64_t n_slots;        /* its facet slots (more than n_tri when facets are split) */
   double min_gap_mm;      /* smallest distance found between different shells */
   int32_t convex_exit;    /* 1: the world borders a single convex shell, so a photon
                              leaving it into a void world escapes at once */
+  int32_t n_exit_planes;  /* > 0: that shell has this many distinct facet planes (at
+                             most 32); with a void world, a photon inside it then
+                             searches a BVH over the other shells only and leaves
+                             the outermost shell's own region through its planes */
 } gadep_mesh_info;
 
 /* Validation + topology + BVH on the host, as gadep_load_mesh does, without
  * a context.  tri_outside[n_tri] (nullable) receives the region outside each
- * facet, tri_shell[n_tri] (nullable) its shell index.  bvh_method 0 = binned
- * SAH (the one used for transport), 1 = object-median split.  nodes_out
- * (nullable, [cap_nodes][16] 32-bit words, the device layout: two child boxes
- * as 12 floats, then two child links as int32, then 2 words of padding) and
- * tri_order (nullable, [n_tri]: caller facet index of each BVH facet slot). */
+ * facet, tri_shell[n_tri] (nullable) its shell index.  bvh_method selects the
+ * BVH returned in nodes_out / tri_order and described by info: 0 = binned SAH
+ * over every facet (the one used for parity counts and geometry queries),
+ * 1 = object-median split, 2 = the transport BVH (binned SAH with spatial
+ * splits, Stich et al. 2009, over every facet but those of the outermost
+ * shell when n_exit_planes > 0; split_budget = extra slots allowed, as a
+ * fraction of its facets).  nodes_out (nullable, [cap_nodes][16] 32-bit
+ * words, the device layout: two child boxes as 12 floats, then two child
+ * links as int32 -- >= 0 a node, < 0 a leaf ~(first_slot << 3 | count) --
+ * then 2 words of padding) and tri_order (nullable, [cap_slots]: caller facet
+ * index of each slot).  A capacity below info->n_nodes or info->n_slots
+ * returns GADEP_E_ARG with info filled. */
 gadep_status gadep_mesh_prepare(const float* xyz_mm, int64_t n_vertices,
                                 const int32_t* tri_vertices, const int32_t* tri_region,
                                 int64_t n_tri, int32_t n_regions, double min_gap_mm,
-                                int32_t validate, int32_t bvh_method, int32_t* tri_outside,
-                                int32_t* tri_shell, void* nodes_out, int64_t cap_nodes,
-                                int32_t* tri_order, gadep_mesh_info* info,
-                                char* err, int32_t err_len);
+                                int32_t validate, int32_t bvh_method, double split_budget,
+                                int32_t* tri_outside, int32_t* tri_shell, void* nodes_out,
+                                int64_t cap_nodes, int32_t* tri_order, int64_t cap_slots,
+                                gadep_mesh_info* info, char* err, int32_t err_len);
 
 #ifdef __cplusplus
 }

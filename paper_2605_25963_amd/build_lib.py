@@ -22,8 +22,9 @@ COMMON = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libgadep.so; returns its path."""
+def build(verbose: bool = False, out: str | None = None) -> str:
+    """Compile every source and link libgadep.so (or `out`); returns its path."""
+    lib = out or LIB
     os.makedirs(BUILD, exist_ok=True)
     procs = []
     objs = []
@@ -47,14 +48,14 @@ def build(verbose: bool = False) -> str:
             print("\n".join(lines))
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, out=sys.argv[1] if len(sys.argv) > 1 else None)

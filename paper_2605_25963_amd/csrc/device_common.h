@@ -43,34 +43,45 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
   }
 }
 
-// Per-history stream: counter = (draw, history lo, history hi, stream id).
+// Per-history stream: counter = (draw, history lo, history hi, stream id); the
+// stream id is the unit's and is passed at each draw.
 // Four 32-bit outputs per call are consumed through a shift register.
 struct Rng {
   uint32_t b0, b1, b2, b3;
   uint32_t left;
   uint32_t draw;
-  uint32_t h_lo, h_hi, stream;
+  uint32_t h_lo, h_hi;
 };
 
-__device__ __forceinline__ void rng_start(Rng& g, uint64_t history, uint32_t stream) {
+__device__ __forceinline__ void rng_start(Rng& g, uint64_t history) {
   g.left = 0;
   g.draw = 0;
   g.h_lo = static_cast<uint32_t>(history);
   g.h_hi = static_cast<uint32_t>(history >> 32);
-  g.stream = stream;
+}
+
+// One Philox block for a history: the four outputs for counter
+// (draw, history lo, history hi, stream).  Kept out of line: it is called at
+// most once per four uniforms, and inlining it at every draw site would
+// multiply the kernel's code.
+__device__ __noinline__ uint4 philox_block(uint32_t draw, uint32_t h_lo, uint32_t h_hi,
+                                           uint32_t stream, uint32_t k0, uint32_t k1) {
+  uint32_t c0 = draw, c1 = h_lo, c2 = h_hi, c3 = stream;
+  philox4x32_10(c0, c1, c2, c3, k0, k1);
+  return make_uint4(c0, c1, c2, c3);
 }
 
 // Uniform in (0, 1): 23 random bits, (k + 1/2) 2^-23, exact in FP32 so that
 // neither 0 nor 1 can occur.
 template <bool COUNT>
-__device__ __forceinline__ float rng_u(Rng& g, uint32_t k0, uint32_t k1, uint32_t& nrng) {
+__device__ __forceinline__ float rng_u(Rng& g, uint32_t stream, uint32_t k0, uint32_t k1,
+                                      uint32_t& nrng) {
   if (g.left == 0) {
-    uint32_t c0 = g.draw, c1 = g.h_lo, c2 = g.h_hi, c3 = g.stream;
-    philox4x32_10(c0, c1, c2, c3, k0, k1);
-    g.b0 = c0;
-    g.b1 = c1;
-    g.b2 = c2;
-    g.b3 = c3;
+    const uint4 x = philox_block(g.draw, g.h_lo, g.h_hi, stream, k0, k1);
+    g.b0 = x.x;
+    g.b1 = x.y;
+    g.b2 = x.z;
+    g.b3 = x.w;
     g.draw += 1;
     g.left = 4;
     if (COUNT) nrng++;
@@ -86,13 +97,13 @@ __device__ __forceinline__ float rng_u(Rng& g, uint32_t k0, uint32_t k1, uint32_
 // ---------------------------------------------------------------------------
 // rays
 
+// Per-ray constants; the origin and direction themselves are passed
+// alongside (they are the photon's own position and direction).
 struct Ray {
-  float ox, oy, oz;
-  float dx, dy, dz;
   float ix, iy, iz;     // 1/d, zero components replaced by +-2^100 reciprocals
   float oix, oiy, oiz;  // o * (1/d), for one FMA per slab plane
-  int kx, ky, kz;       // watertight permutation: kz = dominant axis
   float sx, sy, sz;     // shear constants
+  int k;                // watertight permutation kx | ky << 2 | kz << 4, kz = dominant axis
 };
 
 __device__ __forceinline__ float pick3(float x, float y, float z, int k) {
@@ -107,12 +118,6 @@ __device__ __forceinline__ float safe_rcp(float d) {
 __device__ __forceinline__ Ray make_ray(float ox, float oy, float oz, float dx, float dy,
                                         float dz) {
   Ray r;
-  r.ox = ox;
-  r.oy = oy;
-  r.oz = oz;
-  r.dx = dx;
-  r.dy = dy;
-  r.dz = dz;
   r.ix = safe_rcp(dx);
   r.iy = safe_rcp(dy);
   r.iz = safe_rcp(dz);
@@ -129,9 +134,7 @@ __device__ __forceinline__ Ray make_ray(float ox, float oy, float oz, float dx, 
     kx = ky;
     ky = t;
   }
-  r.kx = kx;
-  r.ky = ky;
-  r.kz = kz;
+  r.k = kx | (ky << 2) | (kz << 4);
   r.sx = pick3(dx, dy, dz, kx) / dkz;
   r.sy = pick3(dx, dy, dz, ky) / dkz;
   r.sz = 1.0f / dkz;
@@ -167,19 +170,21 @@ enum { kWtMiss = 0, kWtHit = 1, kWtDegenerate = 2 };
 // sheared-frame distance T/det loses several digits, the plane form does not.
 // Hits must satisfy 0 < t <= tmax.  kWtDegenerate marks a crossing exactly on
 // an edge or vertex, or a ray lying in the facet plane.
-__device__ __forceinline__ int wt_test(const Ray& r, const float4 a, const float4 b,
+__device__ __forceinline__ int wt_test(const Ray& r, float ox, float oy, float oz, float dx,
+                                       float dy, float dz, const float4 a, const float4 b,
                                        const float4 c, float tmax, float& t, bool& entering) {
-  const float Ax = a.x - r.ox, Ay = a.y - r.oy, Az = a.z - r.oz;
-  const float Bx = a.w - r.ox, By = b.x - r.oy, Bz = b.y - r.oz;
-  const float Cx = b.z - r.ox, Cy = b.w - r.oy, Cz = c.x - r.oz;
-  const float akz = pick3(Ax, Ay, Az, r.kz), bkz = pick3(Bx, By, Bz, r.kz),
-              ckz = pick3(Cx, Cy, Cz, r.kz);
-  const float ax = fmaf(-r.sx, akz, pick3(Ax, Ay, Az, r.kx));
-  const float ay = fmaf(-r.sy, akz, pick3(Ax, Ay, Az, r.ky));
-  const float bx = fmaf(-r.sx, bkz, pick3(Bx, By, Bz, r.kx));
-  const float by = fmaf(-r.sy, bkz, pick3(Bx, By, Bz, r.ky));
-  const float cx = fmaf(-r.sx, ckz, pick3(Cx, Cy, Cz, r.kx));
-  const float cy = fmaf(-r.sy, ckz, pick3(Cx, Cy, Cz, r.ky));
+  const int kx = r.k & 3, ky = (r.k >> 2) & 3, kz = r.k >> 4;
+  const float Ax = a.x - ox, Ay = a.y - oy, Az = a.z - oz;
+  const float Bx = a.w - ox, By = b.x - oy, Bz = b.y - oz;
+  const float Cx = b.z - ox, Cy = b.w - oy, Cz = c.x - oz;
+  const float akz = pick3(Ax, Ay, Az, kz), bkz = pick3(Bx, By, Bz, kz),
+              ckz = pick3(Cx, Cy, Cz, kz);
+  const float ax = fmaf(-r.sx, akz, pick3(Ax, Ay, Az, kx));
+  const float ay = fmaf(-r.sy, akz, pick3(Ax, Ay, Az, ky));
+  const float bx = fmaf(-r.sx, bkz, pick3(Bx, By, Bz, kx));
+  const float by = fmaf(-r.sy, bkz, pick3(Bx, By, Bz, ky));
+  const float cx = fmaf(-r.sx, ckz, pick3(Cx, Cy, Cz, kx));
+  const float cy = fmaf(-r.sy, ckz, pick3(Cx, Cy, Cz, ky));
   float U = edge_fn(cx, by, cy, bx);
   float V = edge_fn(ax, cy, ay, cx);
   float W = edge_fn(bx, ay, by, ax);
@@ -200,7 +205,7 @@ __device__ __forceinline__ int wt_test(const Ray& r, const float4 a, const float
   const float ny = e1z * e2x - e1x * e2z;
   const float nz = e1x * e2y - e1y * e2x;
   const float num = Ax * nx + Ay * ny + Az * nz;
-  const float den = r.dx * nx + r.dy * ny + r.dz * nz;
+  const float den = dx * nx + dy * ny + dz * nz;
   const float th = num * __builtin_amdgcn_rcpf(den);
   if (!(th > 0.0f) || !(th <= tmax)) return kWtMiss;
   t = th;

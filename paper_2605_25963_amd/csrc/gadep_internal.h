@@ -14,6 +14,7 @@ constexpr int kLeafMax = 4;          // facets per BVH leaf
 constexpr int kMaxDepth = 64;        // hard cap on BVH depth (traversal stack)
 constexpr int kMaxRegions = 64;      // regions per scene (parity mask is 64-bit)
 constexpr int kMaxGroups = 8;        // density-scale groups
+constexpr int kMaxExitPlanes = 32;   // distinct facet planes of a convex outermost shell
 constexpr float kMec2 = 510.99895f;  // electron rest energy [keV]
 
 // Fixed-point scales of the 64-bit tally accumulators (exact, order-free sums).
@@ -51,15 +52,34 @@ struct alignas(16) RegionRec {
   int32_t bits;      // group (low 8 bits, 0xFF none) | ACTIVE << 8
 };
 
+// A scene's device tables.  Node 0 is the root of the plain BVH over every
+// facet (one record per facet), used for parity counts and geometry queries;
+// the transport BVH (spatial splits, root trans_root, its records after the
+// plain ones) follows.  When the outermost shell is convex with at most
+// kMaxExitPlanes distinct planes, the transport BVH leaves that shell out,
+// `planes` holds its planes (outward unit normal, offset n . x) and
+// trans_lo/trans_hi bound the transport BVH.  root_all is the BVH a segment
+// that may meet any facet searches: trans_root, or 0 when the transport BVH
+// leaves the outer shell out.
 struct SceneRec {
   const BvhNode* nodes;
   const TriRec* tris;
+  const float* planes;  // 4 floats per plane
   int32_t n_regions;
-  int32_t depth;
+  int32_t depth;        // deeper of the two BVHs
+  int32_t n_planes;     // 0: no exit planes
+  int32_t trans_root;
+  int32_t root_all;
+  int32_t outer_region;
+  float trans_lo[3], trans_hi[3];
 };
 
 // UnitRec.flags
 constexpr int32_t kUnitExitEscapes = 1;  // entering the (void) world ends the history
+// With kUnitExitEscapes and exit planes: segments inside the outermost shell
+// search only the transport BVH (which leaves that shell out), and the outer
+// shell's own region is left through its planes.
+constexpr int32_t kUnitExitPlanes = 2;
 
 enum SourceKind : int32_t { kPoint = 0, kBeam = 1, kCyl = 2 };
 
@@ -97,8 +117,12 @@ enum TallySlot : int {
 };
 enum EventSlot : int {
   kEv_Segments = 0, kEv_Crossings, kEv_NodeVisits, kEv_TriTests, kEv_Photo, kEv_Compton,
-  kEv_Coherent, kEv_Rng, kEv_Locates, kEv_Emissions, kEv_N
+  kEv_Coherent, kEv_Rng, kEv_Locates, kEv_Emissions, kEv_PlaneTests,
+  // wavefront-level: loop iterations, those with a node / facet step, passes
+  // of the batched per-segment work
+  kEv_Iters, kEv_ItersNode, kEv_ItersTri, kEv_Passes, kEv_N
 };
+static_assert(kT_Ev + kEv_N <= kT_Slots, "tally slots");
 
 struct TransportParams {
   const UnitRec* units;
@@ -142,11 +166,26 @@ struct PreparedMesh {
   // The world borders exactly one shell and that shell is convex: a photon
   // that leaves it into the world can never meet another facet.
   bool convex_exit = false;
+  // Set when that shell has at most kMaxExitPlanes distinct planes: its
+  // planes, 4 floats each (outward unit normal, offset n . x).
+  std::vector<float> planes;
+  int32_t outer_region = 0;
+  // Transport BVH, built with spatial splits (a facet may have several
+  // records): over the facets of every shell but the outermost one when
+  // `planes` is set, else over every facet.  Child indices and record slots
+  // are local to it.
+  std::vector<BvhNode> trans_nodes;
+  std::vector<TriRec> trans_tris;
+  int32_t trans_depth = 0;
+  double trans_sah = 0.0;
+  float trans_lo[3] = {0, 0, 0}, trans_hi[3] = {0, 0, 0};
 };
 
 // Returns a gadep_status value; fills err on failure.
+// split_budget: extra facet records the transport BVH may add, as a fraction
+// of its facets (0 = no spatial splits).
 int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t* tri_region,
                  int64_t nt, int32_t n_regions, double min_gap, bool validate, int bvh_method,
-                 PreparedMesh& out, std::string& err);
+                 double split_budget, PreparedMesh& out, std::string& err);
 
 }  // namespace gadep

@@ -277,6 +277,413 @@ class Builder {
 };
 
 // ---------------------------------------------------------------------------
+// Transport BVH with spatial splits (Stich, Friedrich and Dietrich, HPG 2009).
+//
+// Long, thin facets -- fan caps, full-height side walls -- have boxes far
+// larger than themselves, and no partition of whole facets separates them.
+// Besides the object partitions above, each node here also tries to split
+// space: a facet that straddles the plane is referenced from both sides, each
+// reference keeping only the box of the facet's part on its side, so a facet
+// may be listed in several leaves.  That is harmless for closest-hit search;
+// crossing-parity counts use the plain BVH instead.
+
+double nodes_sah(const std::vector<BvhNode>& nodes, double root_area) {
+  if (!(root_area > 0)) return 0.0;
+  double cost = 1.0;  // root visit
+  for (const BvhNode& nd : nodes) {
+    const float* lo[2] = {nd.lmin, nd.rmin};
+    const float* hi[2] = {nd.lmax, nd.rmax};
+    for (int c = 0; c < 2; ++c) {
+      Box b;
+      for (int a = 0; a < 3; ++a) {
+        b.lo[a] = lo[c][a];
+        b.hi[a] = hi[c][a];
+      }
+      const double f = b.area() / root_area;
+      cost += nd.child[c] >= 0 ? f : f * ((~nd.child[c]) & 7);
+    }
+  }
+  return cost;
+}
+
+class SplitBuilder {
+ public:
+  SplitBuilder(const float* xyz, const int32_t* tv, int64_t max_refs)
+      : xyz_(xyz), tv_(tv), max_refs_(max_refs) {}
+
+  // refs: one whole-facet reference per facet.  ids receives the facet of
+  // each reference slot in leaf order.
+  void run(std::vector<Ref> refs, std::vector<BvhNode>& nodes, std::vector<int32_t>& ids,
+           int32_t& depth, double& sah) {
+    nodes_.clear();
+    ids_.clear();
+    max_depth_ = 1;
+    n_refs_ = static_cast<int64_t>(refs.size());
+    Box all;
+    all.reset();
+    for (const Ref& r : refs) all.grow(r.box);
+    root_area_ = all.area();
+    nodes_.emplace_back();
+    if (static_cast<int>(refs.size()) <= kLeafMax) {
+      Box empty;
+      empty.reset();
+      const int32_t code = emit_leaf(refs);
+      set_node(0, all, code, empty, leaf_code(static_cast<int64_t>(ids_.size()), 0));
+    } else {
+      Box b;
+      build(0, std::move(refs), all, 1, b);
+    }
+    nodes.swap(nodes_);
+    ids.swap(ids_);
+    depth = max_depth_;
+    sah = nodes_sah(nodes, root_area_);
+  }
+
+ private:
+  const float* xyz_;
+  const int32_t* tv_;
+  int64_t max_refs_;
+  int64_t n_refs_ = 0;
+  double root_area_ = 0.0;
+  std::vector<BvhNode> nodes_;
+  std::vector<int32_t> ids_;
+  int32_t max_depth_ = 0;
+  static constexpr int kBins = 32;
+  static constexpr double kCostTrav = 1.2;
+  static constexpr double kCostIsect = 1.0;
+  static constexpr double kMinOverlap = 1e-5;  // spatial splits only where children overlap
+
+  struct Plan {
+    double cost = INFINITY;
+    int kind = -1;  // 0..2 centroid axis, 3 box size, 4 spatial
+    int axis = 0, bin = 0;
+    float lo = 0, scale = 0, pos = 0;
+    Box left, right;  // spatial: child boxes and reference counts from the bins
+    int64_t n_left = 0, n_right = 0;
+  };
+
+  void set_node(int32_t idx, const Box& l, int32_t lc, const Box& r, int32_t rc) {
+    BvhNode& nd = nodes_[idx];
+    for (int a = 0; a < 3; ++a) {
+      nd.lmin[a] = l.lo[a];
+      nd.lmax[a] = l.hi[a];
+      nd.rmin[a] = r.lo[a];
+      nd.rmax[a] = r.hi[a];
+    }
+    nd.child[0] = lc;
+    nd.child[1] = rc;
+    nd.pad[0] = nd.pad[1] = 0;
+  }
+
+  int32_t emit_leaf(const std::vector<Ref>& refs) {
+    const int64_t first = static_cast<int64_t>(ids_.size());
+    for (const Ref& r : refs) ids_.push_back(r.id);
+    return leaf_code(first, static_cast<int32_t>(refs.size()));
+  }
+
+  static Box bounds(const std::vector<Ref>& refs) {
+    Box b;
+    b.reset();
+    for (const Ref& r : refs) b.grow(r.box);
+    return b;
+  }
+
+  static void widen(Box& b) {
+    // one part in 2^22 outward, so rounding of the clipped corners never
+    // uncovers a sliver of the facet
+    for (int a = 0; a < 3; ++a) {
+      const float m = 2.4e-7f * std::max(fabsf(b.lo[a]), fabsf(b.hi[a])) + 1e-30f;
+      b.lo[a] -= m;
+      b.hi[a] += m;
+    }
+  }
+
+  // boxes of the parts of reference r on either side of the plane x[axis] = pos
+  void split_ref(const Ref& r, int axis, float pos, Box& L, Box& R) const {
+    L.reset();
+    R.reset();
+    const float* v[3] = {xyz_ + 3 * tv_[3 * r.id], xyz_ + 3 * tv_[3 * r.id + 1],
+                         xyz_ + 3 * tv_[3 * r.id + 2]};
+    for (int i = 0; i < 3; ++i) {
+      const float* p = v[i];
+      const float* q = v[(i + 1) % 3];
+      if (p[axis] <= pos) L.grow(p);
+      if (p[axis] >= pos) R.grow(p);
+      if ((p[axis] < pos && pos < q[axis]) || (p[axis] > pos && pos > q[axis])) {
+        const double t = (static_cast<double>(pos) - p[axis]) / (static_cast<double>(q[axis]) - p[axis]);
+        float x[3];
+        for (int k = 0; k < 3; ++k) x[k] = static_cast<float>(p[k] + t * (static_cast<double>(q[k]) - p[k]));
+        x[axis] = pos;
+        L.grow(x);
+        R.grow(x);
+      }
+    }
+    widen(L);
+    widen(R);
+    for (int a = 0; a < 3; ++a) {
+      L.lo[a] = std::max(L.lo[a], r.box.lo[a]);
+      L.hi[a] = std::min(L.hi[a], r.box.hi[a]);
+      R.lo[a] = std::max(R.lo[a], r.box.lo[a]);
+      R.hi[a] = std::min(R.hi[a], r.box.hi[a]);
+    }
+    L.hi[axis] = std::min(L.hi[axis], pos);
+    R.lo[axis] = std::max(R.lo[axis], pos);
+  }
+
+  static bool valid(const Box& b) {
+    return b.lo[0] <= b.hi[0] && b.lo[1] <= b.hi[1] && b.lo[2] <= b.hi[2];
+  }
+
+  static Box overlap(const Box& a, const Box& b) {
+    Box o;
+    for (int k = 0; k < 3; ++k) {
+      o.lo[k] = std::max(a.lo[k], b.lo[k]);
+      o.hi[k] = std::min(a.hi[k], b.hi[k]);
+    }
+    return o;
+  }
+
+  static float centroid_value(const Ref& r, int kind) {
+    return kind < 3 ? 0.5f * (r.box.lo[kind] + r.box.hi[kind])
+                    : logf(static_cast<float>(r.box.area()) + 1e-30f);
+  }
+
+  static int key(const Ref& r, int kind, float lo, float scale) {
+    return std::min(kBins - 1, std::max(0, static_cast<int>((centroid_value(r, kind) - lo) * scale)));
+  }
+
+  // best partition of whole references (centroid bins on three axes, box size)
+  void object_plan(const std::vector<Ref>& refs, double area, Plan& best, Box* lbox, Box* rbox) const {
+    for (int kind = 0; kind < 4; ++kind) {
+      float lo = INFINITY, hi = -INFINITY;
+      for (const Ref& r : refs) {
+        const float v = centroid_value(r, kind);
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+      }
+      if (!(hi - lo > 0)) continue;
+      const float scale = kBins * (1.0f - 1e-6f) / (hi - lo);
+      Box bins[kBins];
+      int64_t cnt[kBins] = {0};
+      for (Box& b : bins) b.reset();
+      for (const Ref& r : refs) {
+        const int k = key(r, kind, lo, scale);
+        cnt[k]++;
+        bins[k].grow(r.box);
+      }
+      Box rb[kBins];
+      int64_t rc[kBins];
+      Box acc;
+      acc.reset();
+      int64_t c = 0;
+      for (int k = kBins - 1; k > 0; --k) {
+        acc.grow(bins[k]);
+        c += cnt[k];
+        rb[k] = acc;
+        rc[k] = c;
+      }
+      acc.reset();
+      c = 0;
+      for (int k = 0; k < kBins - 1; ++k) {
+        acc.grow(bins[k]);
+        c += cnt[k];
+        if (c == 0 || rc[k + 1] == 0) continue;
+        const double cost = kCostTrav * area + kCostIsect * (acc.area() * c + rb[k + 1].area() * rc[k + 1]);
+        if (cost < best.cost) {
+          best.cost = cost;
+          best.kind = kind;
+          best.bin = k;
+          best.lo = lo;
+          best.scale = scale;
+          if (lbox) *lbox = acc;
+          if (rbox) *rbox = rb[k + 1];
+        }
+      }
+    }
+  }
+
+  // best plane splitting space (references straddling it are clipped)
+  void spatial_plan(const std::vector<Ref>& refs, const Box& node, double area, Plan& best) const {
+    for (int axis = 0; axis < 3; ++axis) {
+      const float lo = node.lo[axis], ext = node.hi[axis] - node.lo[axis];
+      if (!(ext > 0)) continue;
+      const float w = ext / kBins;
+      auto bin_of = [&](float x) {
+        return std::min(kBins - 1, std::max(0, static_cast<int>((x - lo) / w)));
+      };
+      Box bins[kBins];
+      int64_t enter[kBins] = {0}, leave[kBins] = {0};
+      for (Box& b : bins) b.reset();
+      for (const Ref& r : refs) {
+        const int b0 = bin_of(r.box.lo[axis]), b1 = bin_of(r.box.hi[axis]);
+        enter[b0]++;
+        leave[b1]++;
+        Ref cur = r;
+        for (int b = b0; b < b1; ++b) {
+          Box L, R;
+          split_ref(cur, axis, lo + (b + 1) * w, L, R);
+          if (valid(L)) bins[b].grow(L);
+          if (!valid(R)) break;
+          cur.box = R;
+        }
+        if (valid(cur.box)) bins[b1].grow(cur.box);
+      }
+      Box rb[kBins];
+      int64_t rc[kBins];
+      Box acc;
+      acc.reset();
+      int64_t c = 0;
+      for (int k = kBins - 1; k > 0; --k) {
+        acc.grow(bins[k]);
+        c += leave[k];
+        rb[k] = acc;
+        rc[k] = c;
+      }
+      acc.reset();
+      c = 0;
+      for (int k = 0; k < kBins - 1; ++k) {
+        acc.grow(bins[k]);
+        c += enter[k];
+        if (c == 0 || rc[k + 1] == 0) continue;
+        const double la = acc.area(), ra = rb[k + 1].area();
+        const double cost = kCostTrav * area + kCostIsect * (la * c + ra * rc[k + 1]);
+        if (cost < best.cost) {
+          best.cost = cost;
+          best.kind = 4;
+          best.axis = axis;
+          best.pos = lo + (k + 1) * w;
+          best.left = acc;
+          best.right = rb[k + 1];
+          best.n_left = c;
+          best.n_right = rc[k + 1];
+        }
+      }
+    }
+  }
+
+  bool apply(const std::vector<Ref>& refs, const Plan& p, std::vector<Ref>& left,
+             std::vector<Ref>& right) const {
+    left.clear();
+    right.clear();
+    if (p.kind < 4) {
+      for (const Ref& r : refs) (key(r, p.kind, p.lo, p.scale) <= p.bin ? left : right).push_back(r);
+    } else {
+      const double al = p.left.area(), ar = p.right.area();
+      const double nl = static_cast<double>(p.n_left), nr = static_cast<double>(p.n_right);
+      for (const Ref& r : refs) {
+        if (r.box.hi[p.axis] <= p.pos) {
+          left.push_back(r);
+          continue;
+        }
+        if (r.box.lo[p.axis] >= p.pos) {
+          right.push_back(r);
+          continue;
+        }
+        Box L, R;
+        split_ref(r, p.axis, p.pos, L, R);
+        // keep the whole reference on one side when that is cheaper
+        Box lu = p.left, ru = p.right;
+        lu.grow(r.box);
+        ru.grow(r.box);
+        const double c_split = al * nl + ar * nr;
+        const double c_left = lu.area() * nl + ar * (nr - 1);
+        const double c_right = al * (nl - 1) + ru.area() * nr;
+        if (!valid(R) || (valid(L) && c_left < c_split && c_left <= c_right)) {
+          left.push_back(r);
+        } else if (!valid(L) || c_right < c_split) {
+          right.push_back(r);
+        } else {
+          Ref a = r, b = r;
+          a.box = L;
+          b.box = R;
+          left.push_back(a);
+          right.push_back(b);
+        }
+      }
+    }
+    return !left.empty() && !right.empty() && left.size() < refs.size() &&
+           right.size() < refs.size();
+  }
+
+  void median(const std::vector<Ref>& refs, std::vector<Ref>& left, std::vector<Ref>& right) const {
+    Box cb;
+    cb.reset();
+    for (const Ref& r : refs) {
+      float c[3];
+      for (int a = 0; a < 3; ++a) c[a] = 0.5f * (r.box.lo[a] + r.box.hi[a]);
+      cb.grow(c);
+    }
+    int a = 0;
+    for (int k = 1; k < 3; ++k)
+      if (cb.hi[k] - cb.lo[k] > cb.hi[a] - cb.lo[a]) a = k;
+    std::vector<Ref> s = refs;
+    const size_t mid = s.size() / 2;
+    std::nth_element(s.begin(), s.begin() + mid, s.end(), [a](const Ref& x, const Ref& y) {
+      const float cx = x.box.lo[a] + x.box.hi[a], cy = y.box.lo[a] + y.box.hi[a];
+      return cx < cy || (cx == cy && x.id < y.id);
+    });
+    left.assign(s.begin(), s.begin() + mid);
+    right.assign(s.begin() + mid, s.end());
+  }
+
+  // splits refs (more than kLeafMax, or cheaper split) under node idx
+  void build(int32_t idx, std::vector<Ref> refs, const Box& box, int depth, Box& box_out) {
+    max_depth_ = std::max(max_depth_, depth);
+    std::vector<Ref> left, right;
+    choose(refs, box, depth, left, right);
+    refs.clear();
+    refs.shrink_to_fit();
+    Box lb = bounds(left), rb = bounds(right);
+    const int32_t lc = child(std::move(left), lb, depth);
+    const int32_t rc = child(std::move(right), rb, depth);
+    set_node(idx, lb, lc, rb, rc);
+    box_out = lb;
+    box_out.grow(rb);
+  }
+
+  void choose(const std::vector<Ref>& refs, const Box& box, int depth, std::vector<Ref>& left,
+              std::vector<Ref>& right) {
+    if (depth < kMaxDepth - 16) {
+      const double area = box.area();
+      Plan obj;
+      Box ol, orb;
+      object_plan(refs, area, obj, &ol, &orb);
+      Plan best = obj;
+      if (n_refs_ < max_refs_ && obj.kind >= 0) {
+        const Box ov = overlap(ol, orb);
+        if (valid(ov) && ov.area() > kMinOverlap * root_area_) spatial_plan(refs, box, area, best);
+      } else if (n_refs_ < max_refs_ && obj.kind < 0) {
+        spatial_plan(refs, box, area, best);
+      }
+      if (best.kind >= 0 && apply(refs, best, left, right)) {
+        n_refs_ += static_cast<int64_t>(left.size() + right.size()) - static_cast<int64_t>(refs.size());
+        return;
+      }
+      if (obj.kind >= 0 && best.kind == 4 && apply(refs, obj, left, right)) return;
+    }
+    median(refs, left, right);
+  }
+
+  int32_t child(std::vector<Ref> refs, const Box& box, int depth) {
+    const int64_t n = static_cast<int64_t>(refs.size());
+    if (n <= kLeafMax) {
+      bool leaf = n < 2 || depth >= kMaxDepth - 1;
+      if (!leaf) {
+        Plan p;
+        object_plan(refs, box.area(), p, nullptr, nullptr);
+        leaf = p.cost >= kCostIsect * n * box.area();
+      }
+      if (leaf) return emit_leaf(refs);
+    }
+    const int32_t idx = static_cast<int32_t>(nodes_.size());
+    nodes_.emplace_back();
+    Box b;
+    build(idx, std::move(refs), box, depth + 1, b);
+    return idx;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // FP64 queries over the flattened BVH (host preparation only)
 
 class HostQuery {
@@ -508,7 +915,7 @@ int fail(std::string& err, int code, const std::string& msg) {
 
 int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t* tri_region,
                  int64_t nt, int32_t n_regions, double min_gap, bool validate, int bvh_method,
-                 PreparedMesh& out, std::string& err) {
+                 double split_budget, PreparedMesh& out, std::string& err) {
   if (!xyz || !tri || !tri_region || nv < 3 || nt < 1)
     return fail(err, GADEP_E_ARG, "mesh: null array or empty mesh");
   if (n_regions < 2 || n_regions > kMaxRegions)
@@ -635,6 +1042,7 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
     for (int a = 0; a < 3; ++a) r.c[a] = 0.5f * (r.box.lo[a] + r.box.hi[a]);
     r.id = static_cast<int32_t>(f);
   }
+  const std::vector<Ref> refs_of = refs;  // whole-facet references by facet
   Builder builder(refs, bvh_method);
   builder.run(out.nodes, out.depth, out.sah);
   out.order.resize(static_cast<size_t>(nt));
@@ -723,8 +1131,9 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
   }
 
   // ---- is the world bounded by one convex shell?
+  int32_t top = -1;
   {
-    int32_t top = -1, n_top = 0;
+    int32_t n_top = 0;
     for (int32_t s = 0; s < ns; ++s)
       if (container[s] == 0) {
         top = s;
@@ -757,14 +1166,65 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
     }
   }
 
+  // ---- exit planes of that shell
+  out.planes.clear();
+  if (out.convex_exit) {
+    std::vector<D3> pn;
+    std::vector<double> pd;
+    bool few = true;
+    for (int64_t f = 0; f < nt && few; ++f) {
+      if (shell[f] != top) continue;
+      Tri3 t = facet(static_cast<int32_t>(f));
+      D3 n = cross(t.b - t.a, t.c - t.a);
+      n = (1.0 / len(n)) * n;
+      const double d = dot(n, (1.0 / 3.0) * (t.a + t.b + t.c));
+      bool seen = false;
+      for (size_t k = 0; k < pn.size() && !seen; ++k)
+        seen = dot(n, pn[k]) > 1.0 - 1e-12 && fabs(d - pd[k]) <= 1e-9 * ext;
+      if (seen) continue;
+      if (static_cast<int>(pn.size()) == kMaxExitPlanes) {
+        few = false;
+        break;
+      }
+      pn.push_back(n);
+      pd.push_back(d);
+    }
+    if (few) {
+      out.outer_region = tri_region[shell_first[top]];
+      for (size_t k = 0; k < pn.size(); ++k) {
+        out.planes.push_back(static_cast<float>(pn[k].x));
+        out.planes.push_back(static_cast<float>(pn[k].y));
+        out.planes.push_back(static_cast<float>(pn[k].z));
+        out.planes.push_back(static_cast<float>(pd[k]));
+      }
+    }
+  }
+
+  // ---- transport BVH (spatial splits)
+  {
+    const bool skip_outer = !out.planes.empty();
+    std::vector<Ref> trefs;
+    for (int64_t f = 0; f < nt; ++f)
+      if (!(skip_outer && shell[f] == top)) trefs.push_back(refs_of[f]);
+    const int64_t budget = static_cast<int64_t>(split_budget * static_cast<double>(trefs.size()));
+    std::vector<int32_t> ids;
+    SplitBuilder sb(xyz, tv.data(), static_cast<int64_t>(trefs.size()) + budget);
+    sb.run(std::move(trefs), out.trans_nodes, ids, out.trans_depth, out.trans_sah);
+    out.trans_tris.resize(ids.size());
+    for (size_t i = 0; i < ids.size(); ++i) out.trans_tris[i].orig = ids[i];
+    const BvhNode& root = out.trans_nodes[0];
+    for (int a = 0; a < 3; ++a) {
+      out.trans_lo[a] = std::min(root.lmin[a], root.rmin[a]);
+      out.trans_hi[a] = std::max(root.lmax[a], root.rmax[a]);
+    }
+  }
+
   // ---- outputs
   out.outside.resize(static_cast<size_t>(nt));
   out.shell = shell;
   for (int64_t f = 0; f < nt; ++f) out.outside[f] = container[shell[f]];
   out.tris.resize(static_cast<size_t>(nt));
-  for (int64_t i = 0; i < nt; ++i) {
-    int32_t f = out.order[i];
-    TriRec& r = out.tris[i];
+  auto record = [&](int32_t f, TriRec& r) {
     for (int k = 0; k < 3; ++k) {
       const float* p = xyz + 3 * tv[3 * f + k];
       float* dst = k == 0 ? r.v0 : (k == 1 ? r.v1 : r.v2);
@@ -773,7 +1233,9 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
     r.regions = uint32_t(tri_region[f]) | (uint32_t(out.outside[f]) << 16);
     r.orig = f;
     r.pad = 0;
-  }
+  };
+  for (int64_t i = 0; i < nt; ++i) record(out.order[i], out.tris[i]);
+  for (TriRec& r : out.trans_tris) record(r.orig, r);
   out.n_shells = ns;
   out.genus_max = genus_max;
   out.min_gap = gap_seen;

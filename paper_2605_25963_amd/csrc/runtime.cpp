@@ -46,9 +46,31 @@ struct Scene {
   int64_t n_tri = 0;
   int64_t n_nodes = 0;
   bool convex_exit = false;
+  int32_t n_planes = 0;
+  int32_t trans_root = 0;
+  int32_t root_all = 0;
+  int32_t outer_region = 0;
+  float trans_lo[3] = {0, 0, 0}, trans_hi[3] = {0, 0, 0};
   void* d_nodes = nullptr;
   void* d_tris = nullptr;
+  void* d_planes = nullptr;
 };
+
+void fill_scene_rec(const Scene& sc, SceneRec& sr) {
+  sr.nodes = static_cast<const BvhNode*>(sc.d_nodes);
+  sr.tris = static_cast<const TriRec*>(sc.d_tris);
+  sr.planes = static_cast<const float*>(sc.d_planes);
+  sr.n_regions = sc.n_regions;
+  sr.depth = sc.depth;
+  sr.n_planes = sc.n_planes;
+  sr.trans_root = sc.trans_root;
+  sr.root_all = sc.root_all;
+  sr.outer_region = sc.outer_region;
+  for (int a = 0; a < 3; ++a) {
+    sr.trans_lo[a] = sc.trans_lo[a];
+    sr.trans_hi[a] = sc.trans_hi[a];
+  }
+}
 
 struct Material {
   bool set = false;
@@ -84,6 +106,8 @@ struct gadep_ctx {
   int64_t graphs = 1;
   int64_t counters = 0;
   int64_t grid = 0;
+  int64_t exit_planes = 1;
+  int64_t split_pct = 100;
 
   DevBuf units, chunk_begin, scene_tab, sources, lines, regions, tally, spectra, cursor;
   void* h_tally = nullptr;  // pinned
@@ -323,7 +347,9 @@ gadep_status plan_jobs(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
       u.stream = (J.stream << 16) | static_cast<uint32_t>(e);
       u.src_region = 0;
       u.n_groups = grad ? GADEP_MAX_GROUPS : 0;
-      u.flags = (sc.convex_exit && P.regions[roff].mult == 0.0f) ? kUnitExitEscapes : 0;
+      u.flags = 0;
+      if (sc.convex_exit && P.regions[roff].mult == 0.0f)
+        u.flags = kUnitExitEscapes | (sc.n_planes > 0 && ctx->exit_planes ? kUnitExitPlanes : 0);
       P.units.push_back(u);
       P.unit_energy.push_back(E);
       P.chunk_begin.push_back(chunks);
@@ -373,10 +399,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   std::vector<SceneRec> st(ctx->scenes.size());
   for (size_t i = 0; i < ctx->scenes.size(); ++i) {
     if (!ctx->scenes[i] || !ctx->scenes[i]->loaded) continue;
-    st[i].nodes = static_cast<const BvhNode*>(ctx->scenes[i]->d_nodes);
-    st[i].tris = static_cast<const TriRec*>(ctx->scenes[i]->d_tris);
-    st[i].n_regions = ctx->scenes[i]->n_regions;
-    st[i].depth = ctx->scenes[i]->depth;
+    fill_scene_rec(*ctx->scenes[i], st[i]);
   }
   if ((s = upload(ctx, ctx->scene_tab, st.data(), st.size() * sizeof(SceneRec), "scene table"))) return s;
   if ((s = upload(ctx, ctx->units, P.units.data(), P.units.size() * sizeof(UnitRec), "unit table"))) return s;
@@ -417,7 +440,10 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   K.stack_depth = P.depth;
   K.period = static_cast<int32_t>(ctx->period);
 
-  const int variant = (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0);
+  bool vol = false;
+  for (const SourceRec& sr : P.sources) vol = vol || sr.kind == kCyl;
+  const int variant =
+      (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0) | (vol ? 8 : 0);
   const int block = static_cast<int>(ctx->block);
   int grid = static_cast<int>(ctx->grid);
   if (grid <= 0) {
@@ -537,6 +563,11 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     cnt.rng_calls += ev[kEv_Rng];
     cnt.locates += ev[kEv_Locates];
     cnt.emissions += ev[kEv_Emissions];
+    cnt.plane_tests += ev[kEv_PlaneTests];
+    cnt.iterations += ev[kEv_Iters];
+    cnt.iterations_node += ev[kEv_ItersNode];
+    cnt.iterations_facet += ev[kEv_ItersTri];
+    cnt.passes += ev[kEv_Passes];
   }
   if (ctx->counters) {
     ctx->last_counters = cnt;
@@ -607,6 +638,7 @@ void gadep_destroy(gadep_ctx* ctx) {
     if (sc) {
       if (sc->d_nodes) hipFree(sc->d_nodes);
       if (sc->d_tris) hipFree(sc->d_tris);
+      if (sc->d_planes) hipFree(sc->d_planes);
     }
   for (DevBuf* b : {&ctx->xs, &ctx->units, &ctx->chunk_begin, &ctx->scene_tab, &ctx->sources,
                     &ctx->lines, &ctx->regions, &ctx->tally, &ctx->spectra, &ctx->cursor})
@@ -656,6 +688,13 @@ gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t v) {
       if (v < 0 || v > (1 << 20)) return set_err(ctx, GADEP_E_ARG, "grid out of range");
       ctx->grid = v;
       return GADEP_OK;
+    case GADEP_OPT_EXIT_PLANES:
+      ctx->exit_planes = v ? 1 : 0;
+      return GADEP_OK;
+    case GADEP_OPT_SPLIT_PCT:
+      if (v < 0 || v > 1600) return set_err(ctx, GADEP_E_ARG, "split budget must be in [0, 1600] %");
+      ctx->split_pct = v;
+      return GADEP_OK;
     default:
       return set_err(ctx, GADEP_E_ARG, "unknown option");
   }
@@ -673,6 +712,8 @@ gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* v) 
     case GADEP_OPT_GRAPHS: *v = ctx->graphs; return GADEP_OK;
     case GADEP_OPT_COUNTERS: *v = ctx->counters; return GADEP_OK;
     case GADEP_OPT_GRID: *v = ctx->grid; return GADEP_OK;
+    case GADEP_OPT_EXIT_PLANES: *v = ctx->exit_planes; return GADEP_OK;
+    case GADEP_OPT_SPLIT_PCT: *v = ctx->split_pct; return GADEP_OK;
     default: return GADEP_E_ARG;
   }
 }
@@ -692,7 +733,7 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   PreparedMesh pm;
   std::string err;
   int rc = prepare_mesh(xyz, nv, tri, tri_region, nt, n_regions, ctx->min_gap_nm * 1e-6,
-                        ctx->validate != 0, 0, pm, err);
+                        ctx->validate != 0, 0, ctx->split_pct * 0.01, pm, err);
   if (rc != GADEP_OK) return set_err(ctx, static_cast<gadep_status>(rc), err);
   if (static_cast<int32_t>(ctx->scenes.size()) <= scene) ctx->scenes.resize(scene + 1);
   if (!ctx->scenes[scene]) ctx->scenes[scene].reset(new Scene());
@@ -701,17 +742,49 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   HIP_TRY(hipStreamSynchronize(ctx->stream), "sync");
   if (sc.d_nodes) hipFree(sc.d_nodes);
   if (sc.d_tris) hipFree(sc.d_tris);
-  sc.d_nodes = sc.d_tris = nullptr;
+  if (sc.d_planes) hipFree(sc.d_planes);
+  sc.d_nodes = sc.d_tris = sc.d_planes = nullptr;
   sc.loaded = false;
-  HIP_TRY(hipMalloc(&sc.d_nodes, pm.nodes.size() * sizeof(BvhNode)), "alloc nodes");
-  HIP_TRY(hipMalloc(&sc.d_tris, pm.tris.size() * sizeof(TriRec)), "alloc facets");
-  HIP_TRY(hipMemcpy(sc.d_nodes, pm.nodes.data(), pm.nodes.size() * sizeof(BvhNode), hipMemcpyHostToDevice),
+  // the transport BVH follows the plain one, its indices shifted to match
+  std::vector<BvhNode> nodes = pm.nodes;
+  std::vector<TriRec> tris = pm.tris;
+  const int32_t n_plain = static_cast<int32_t>(pm.nodes.size());
+  for (BvhNode nd : pm.trans_nodes) {
+    for (int c = 0; c < 2; ++c) {
+      if (nd.child[c] >= 0) {
+        nd.child[c] += n_plain;
+      } else {
+        const int32_t x = ~nd.child[c];
+        nd.child[c] = leaf_code((x >> 3) + nt, x & 7);
+      }
+    }
+    nodes.push_back(nd);
+  }
+  tris.insert(tris.end(), pm.trans_tris.begin(), pm.trans_tris.end());
+  const int32_t n_planes = static_cast<int32_t>(pm.planes.size() / 4);
+  HIP_TRY(hipMalloc(&sc.d_nodes, nodes.size() * sizeof(BvhNode)), "alloc nodes");
+  HIP_TRY(hipMalloc(&sc.d_tris, tris.size() * sizeof(TriRec)), "alloc facets");
+  HIP_TRY(hipMemcpy(sc.d_nodes, nodes.data(), nodes.size() * sizeof(BvhNode), hipMemcpyHostToDevice),
           "upload nodes");
-  HIP_TRY(hipMemcpy(sc.d_tris, pm.tris.data(), pm.tris.size() * sizeof(TriRec), hipMemcpyHostToDevice),
+  HIP_TRY(hipMemcpy(sc.d_tris, tris.data(), tris.size() * sizeof(TriRec), hipMemcpyHostToDevice),
           "upload facets");
+  if (n_planes > 0) {
+    HIP_TRY(hipMalloc(&sc.d_planes, pm.planes.size() * sizeof(float)), "alloc planes");
+    HIP_TRY(hipMemcpy(sc.d_planes, pm.planes.data(), pm.planes.size() * sizeof(float),
+                      hipMemcpyHostToDevice),
+            "upload planes");
+  }
+  sc.n_planes = n_planes;
+  sc.trans_root = n_plain;
+  sc.root_all = n_planes > 0 ? 0 : n_plain;
+  sc.outer_region = pm.outer_region;
+  for (int a = 0; a < 3; ++a) {
+    sc.trans_lo[a] = pm.trans_lo[a];
+    sc.trans_hi[a] = pm.trans_hi[a];
+  }
   sc.regions.assign(regions, regions + n_regions);
   sc.n_regions = n_regions;
-  sc.depth = pm.depth;
+  sc.depth = std::max(pm.depth, pm.trans_depth);
   sc.n_tri = nt;
   sc.n_nodes = static_cast<int64_t>(pm.nodes.size());
   sc.convex_exit = pm.convex_exit;
@@ -909,11 +982,7 @@ static gadep_status scene_rec(gadep_ctx* ctx, int32_t scene, SceneRec& sr) {
   if (scene < 0 || scene >= static_cast<int32_t>(ctx->scenes.size()) || !ctx->scenes[scene] ||
       !ctx->scenes[scene]->loaded)
     return set_err(ctx, GADEP_E_STATE, "scene not loaded");
-  const Scene& sc = *ctx->scenes[scene];
-  sr.nodes = static_cast<const BvhNode*>(sc.d_nodes);
-  sr.tris = static_cast<const TriRec*>(sc.d_tris);
-  sr.n_regions = sc.n_regions;
-  sr.depth = sc.depth;
+  fill_scene_rec(*ctx->scenes[scene], sr);
   return GADEP_OK;
 }
 
@@ -975,33 +1044,52 @@ gadep_status gadep_locate(gadep_ctx* ctx, int32_t scene, const float* p, int64_t
 gadep_status gadep_mesh_prepare(const float* xyz, int64_t nv, const int32_t* tri,
                                 const int32_t* tri_region, int64_t nt, int32_t n_regions,
                                 double min_gap_mm, int32_t validate, int32_t bvh_method,
-                                int32_t* tri_outside, int32_t* tri_shell, void* nodes_out,
-                                int64_t cap_nodes, int32_t* tri_order, gadep_mesh_info* info,
-                                char* err, int32_t err_len) {
+                                double split_budget, int32_t* tri_outside, int32_t* tri_shell,
+                                void* nodes_out, int64_t cap_nodes, int32_t* tri_order,
+                                int64_t cap_slots, gadep_mesh_info* info, char* err,
+                                int32_t err_len) {
+  if (bvh_method < 0 || bvh_method > 2 || !(split_budget >= 0) || split_budget > 16) {
+    if (err && err_len > 0) {
+      strncpy(err, "mesh: bvh_method or split_budget out of range", static_cast<size_t>(err_len) - 1);
+      err[err_len - 1] = 0;
+    }
+    return GADEP_E_ARG;
+  }
   PreparedMesh pm;
   std::string e;
   int rc = prepare_mesh(xyz, nv, tri, tri_region, nt, n_regions, min_gap_mm, validate != 0,
-                        bvh_method, pm, e);
+                        bvh_method == 1 ? 1 : 0, split_budget, pm, e);
   if (err && err_len > 0) {
     strncpy(err, e.c_str(), static_cast<size_t>(err_len) - 1);
     err[err_len - 1] = 0;
   }
   if (rc != GADEP_OK) return static_cast<gadep_status>(rc);
-  if (tri_outside) memcpy(tri_outside, pm.outside.data(), pm.outside.size() * 4);
-  if (tri_shell) memcpy(tri_shell, pm.shell.data(), pm.shell.size() * 4);
-  if (tri_order) memcpy(tri_order, pm.order.data(), pm.order.size() * 4);
-  if (nodes_out) {
-    if (cap_nodes < static_cast<int64_t>(pm.nodes.size())) return GADEP_E_ARG;
-    memcpy(nodes_out, pm.nodes.data(), pm.nodes.size() * sizeof(BvhNode));
-  }
+  const bool trans = bvh_method == 2;
+  const std::vector<BvhNode>& nodes = trans ? pm.trans_nodes : pm.nodes;
+  const int64_t n_slots = trans ? static_cast<int64_t>(pm.trans_tris.size()) : nt;
   if (info) {
     info->n_shells = pm.n_shells;
     info->genus_max = pm.genus_max;
-    info->n_nodes = static_cast<int64_t>(pm.nodes.size());
-    info->depth = pm.depth;
-    info->sah_cost = pm.sah;
+    info->n_nodes = static_cast<int64_t>(nodes.size());
+    info->depth = trans ? pm.trans_depth : pm.depth;
+    info->sah_cost = trans ? pm.trans_sah : pm.sah;
+    info->n_slots = n_slots;
     info->min_gap_mm = pm.min_gap;
     info->convex_exit = pm.convex_exit ? 1 : 0;
+    info->n_exit_planes = static_cast<int32_t>(pm.planes.size() / 4);
+  }
+  if (tri_outside) memcpy(tri_outside, pm.outside.data(), pm.outside.size() * 4);
+  if (tri_shell) memcpy(tri_shell, pm.shell.data(), pm.shell.size() * 4);
+  if (tri_order) {
+    if (cap_slots < n_slots) return GADEP_E_ARG;
+    if (trans)
+      for (int64_t i = 0; i < n_slots; ++i) tri_order[i] = pm.trans_tris[i].orig;
+    else
+      memcpy(tri_order, pm.order.data(), pm.order.size() * 4);
+  }
+  if (nodes_out) {
+    if (cap_nodes < static_cast<int64_t>(nodes.size())) return GADEP_E_ARG;
+    memcpy(nodes_out, nodes.data(), nodes.size() * sizeof(BvhNode));
   }
   return GADEP_OK;
 }

@@ -36,7 +36,8 @@ struct HitOut {
 // all).  Returns true on a hit; `glitch` is set when a rejected candidate lay
 // nearer than the accepted one.
 template <bool COUNT>
-__device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, float tmax,
+__device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, float ox, float oy,
+                                            float oz, float dx, float dy, float dz, float tmax,
                                             int exclude, int cur, int* stack, int stride,
                                             HitOut& h, bool& glitch, uint32_t& nvis,
                                             uint32_t& ntri) {
@@ -56,7 +57,7 @@ __device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, fl
       load_tri(tris, slot, a, b, c);
       float t;
       bool enter;
-      if (wt_test(r, a, b, c, tcur, t, enter) == kWtMiss) continue;
+      if (wt_test(r, ox, oy, oz, dx, dy, dz, a, b, c, tcur, t, enter) == kWtMiss) continue;
       const uint32_t regs = __float_as_uint(c.y);
       const int inside = static_cast<int>(regs & 0xFFFFu);
       const int outside = static_cast<int>(regs >> 16);
@@ -99,7 +100,8 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
                              int stride, uint32_t& nvis, uint32_t& ntri) {
   const TriRec* __restrict__ tris = sc.tris;
   for (int k = 0; k < 4; ++k) {
-    const Ray r = make_ray(px, py, pz, kProbe[k][0], kProbe[k][1], kProbe[k][2]);
+    const float qx = kProbe[k][0], qy = kProbe[k][1], qz = kProbe[k][2];
+    const Ray r = make_ray(px, py, pz, qx, qy, qz);
     uint64_t parity = 0;
     bool degenerate = false;
     float tm = INFINITY;
@@ -110,7 +112,7 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
         load_tri(tris, first + j, a, b, c);
         float t;
         bool enter;
-        const int w = wt_test(r, a, b, c, INFINITY, t, enter);
+        const int w = wt_test(r, px, py, pz, qx, qy, qz, a, b, c, INFINITY, t, enter);
         if (COUNT) ntri++;
         if (w == kWtMiss) continue;
         if (w == kWtDegenerate) degenerate = true;
@@ -133,7 +135,7 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
         float t;
         bool enter;
         if (COUNT) ntri++;
-        if (wt_test(r, a, b, c, tcur, t, enter) == kWtMiss) continue;
+        if (wt_test(r, px, py, pz, qx, qy, qz, a, b, c, tcur, t, enter) == kWtMiss) continue;
         if (t < best || (t == best && reg < best_reg)) {
           best = t;
           best_reg = reg;
@@ -233,8 +235,11 @@ __device__ __forceinline__ unsigned long long fx(double v, double scale) {
 // need one and sets up the next traversals, for all parked lanes at once.
 
 enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3 };
+constexpr int kExitPlane = -2;  // best_id of a crossing through an exit plane
 
-template <bool GRAD, bool SPEC, bool COUNT>
+// GRAD: score-function tallies; SPEC: pulse-height spectra; COUNT: event
+// counters; VOL: some unit has a volume source (emission needs localisation).
+template <bool GRAD, bool SPEC, bool COUNT, bool VOL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
 transport_kernel(TransportParams P) {
   extern __shared__ unsigned long long smem[];
@@ -275,7 +280,7 @@ transport_kernel(TransportParams P) {
   float mu = 0, mp = 0, mc = 0;
   Ray ray{};
   float tbest = 0, trej = INFINITY;
-  int node = kDone, sp = 0, tri_next = 0, tri_end = 0, best_slot = -1, best_reg = 0;
+  int node = kDone, sp = 0, tri_next = 0, tri_end = 0, best_id = -1, best_reg = 0;
   // per-lane accumulators of the per-history (frequent) quantities
   unsigned long long acc_hist = 0, acc_eunc = 0, acc_esrc = 0;
   uint32_t ev[kEv_N];
@@ -359,6 +364,7 @@ transport_kernel(TransportParams P) {
     const uint64_t trav = __ballot(phase == kTrav);
     if (trav == 0 || __popcll(__ballot(phase == kParked || phase == kNeed)) >= park) {
       // ================= housekeeping for every parked lane =================
+      if (COUNT && lane == 0) ev[kEv_Passes]++;
       if (phase == kParked) {
         // ---- outcome of the finished traversal
         if (trej < tbest) atomicAdd(&wt[kT_Glitch], 1ull);
@@ -369,8 +375,8 @@ transport_kernel(TransportParams P) {
         if (++steps > P.max_steps) {
           clean = false;
           end_history(false, false, false, true);
-        } else if (best_slot >= 0) {
-          // boundary crossing
+        } else if (best_id != -1) {
+          // boundary crossing (a facet, or the outermost shell's exit plane)
           if (COUNT) ev[kEv_Crossings]++;
           if (GRAD && grp < kMaxGroups) {
             const float d0 = mu * rr.inv_scale * tbest;
@@ -384,7 +390,7 @@ transport_kernel(TransportParams P) {
           pz = fmaf(tbest, dz, pz);
           tau = fmaxf(0.0f, fmaf(-mu, tbest, tau));
           region = best_reg;
-          last = best_slot;
+          last = best_id;
           if (region == 0 && (U.flags & kUnitExitEscapes)) {
             // left the convex outermost shell into the void world: nothing ahead
             clean = false;
@@ -405,7 +411,7 @@ transport_kernel(TransportParams P) {
           }
           last = -1;
           interacted = true;
-          const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * mu;
+          const float x = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]) * mu;
           if (x < mp) {
             if (COUNT) ev[kEv_Photo]++;
             edep_tot += E;
@@ -429,9 +435,9 @@ transport_kernel(TransportParams P) {
               const float a2 = 0.5f * (1.0f - e02);
               float eps = 1.0f, t = 0.0f;
               for (int it = 0; it < 64; ++it) {
-                const float u1 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-                const float u2 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
-                const float u3 = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                const float u1 = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+                const float u2 = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+                const float u3 = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
                 float eps2;
                 if (u1 * (a1 + a2) < a1) {
                   eps = __expf(-a1 * u2);
@@ -451,7 +457,7 @@ transport_kernel(TransportParams P) {
                 edep_act += dep;
               else
                 clean = false;
-              turn(dx, dy, dz, 1.0f - t, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+              turn(dx, dy, dz, 1.0f - t, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
               E = Ep;
               if (E < P.e_cut) {
                 edep_tot += E;
@@ -469,12 +475,12 @@ transport_kernel(TransportParams P) {
               // inverts in closed form (Cardano): with a = 4u - 2,
               // mu = c - 1/c, c = cbrt(a + sqrt(a^2 + 1)), taken on |a| for accuracy
               if (COUNT) ev[kEv_Coherent]++;
-              const float a = fmaf(4.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -2.0f);
+              const float a = fmaf(4.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -2.0f);
               const float c = cbrtf(fabsf(a) + sqrtf(fmaf(a, a, 1.0f)));
               const float ct = copysignf(c - 1.0f / c, a);
-              turn(dx, dy, dz, fminf(1.0f, fmaxf(-1.0f, ct)), rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+              turn(dx, dy, dz, fminf(1.0f, fmaxf(-1.0f, ct)), rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
             }
-            if (!absorbed) tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+            if (!absorbed) tau = -__logf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
           }
         } else {
           // vacuum and no facet ahead: escape from the world, otherwise lost
@@ -529,10 +535,10 @@ transport_kernel(TransportParams P) {
           const int64_t h = next_h + __popcll(below);
           if (phase == kNeed && h < end_h) {
             // ---- emission
-            rng_start(g, static_cast<uint64_t>(U.first + h), U.stream);
+            rng_start(g, static_cast<uint64_t>(U.first + h));
             if (COUNT) ev[kEv_Emissions]++;
             if (Src.n_lines > 0) {
-              const float x = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+              const float x = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
               const float2* L = reinterpret_cast<const float2*>(P.lines) + Src.line_off;
               int pick = Src.n_lines - 1;
               for (int i = 0; i < Src.n_lines; ++i)
@@ -546,15 +552,15 @@ transport_kernel(TransportParams P) {
             }
             const float E0 = E;
             bool ok = true;
-            if (Src.kind == kCyl) {
+            if (VOL && Src.kind == kCyl) {
               ok = false;
               const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
               for (int attempt = 0; attempt < 1000 && !ok; ++attempt) {
-                const float rr2 = sqrtf(fmaf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
-                const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                const float rr2 = sqrtf(fmaf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
+                const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
                 px = Src.pos[0] + rr2 * __builtin_amdgcn_cosf(uphi);
                 py = Src.pos[1] + rr2 * __builtin_amdgcn_sinf(uphi);
-                pz = Src.pos[2] + rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]) * Src.h;
+                pz = Src.pos[2] + rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]) * Src.h;
                 if (COUNT) ev[kEv_Locates]++;
                 uint32_t nv = 0, nt = 0;
                 ok = locate_parity<COUNT>(S, px, py, pz, stack, stride, COUNT ? ev[kEv_NodeVisits] : nv,
@@ -578,14 +584,14 @@ transport_kernel(TransportParams P) {
                 dy = Src.dir[1];
                 dz = Src.dir[2];
               } else {
-                const float ct = fmaf(2.0f, rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]), -1.0f);
+                const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
                 const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-                const float uphi = rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]);
+                const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
                 dx = st * __builtin_amdgcn_cosf(uphi);
                 dy = st * __builtin_amdgcn_sinf(uphi);
                 dz = ct;
               }
-              tau = -__logf(rng_u<COUNT>(g, k0, k1, ev[kEv_Rng]));
+              tau = -__logf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
               ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
               edep_act = edep_tot = 0.0f;
               clean = true;
@@ -612,16 +618,44 @@ transport_kernel(TransportParams P) {
         tbest = mu > 0.0f ? tau / mu : INFINITY;
         ray = make_ray(px, py, pz, dx, dy, dz);
         trej = INFINITY;
-        node = 0;
+        node = S.root_all;
         sp = 0;
         tri_next = tri_end = 0;
-        best_slot = -1;
-        phase = kTrav;
+        best_id = -1;
+        if ((U.flags & kUnitExitPlanes) && region != 0) {
+          // Inside the convex outermost shell: only the other shells can be
+          // met before its boundary, so the search runs on their BVH; from the
+          // outer shell's own region, the boundary itself is the nearest of
+          // the planes the ray runs towards.
+          node = S.trans_root;
+          if (region == S.outer_region) {
+            float te = INFINITY;
+            for (int i = 0; i < S.n_planes; ++i) {
+              const float4 pl = gload(reinterpret_cast<const float4*>(S.planes), i);
+              const float dn = pl.x * dx + pl.y * dy + pl.z * dz;
+              const float num = pl.w - (pl.x * px + pl.y * py + pl.z * pz);
+              if (dn > 0.0f) te = fminf(te, num * __builtin_amdgcn_rcpf(dn));
+            }
+            if (COUNT) ev[kEv_PlaneTests] += S.n_planes;
+            te = fmaxf(te, 0.0f);
+            if (te <= tbest) {
+              tbest = te;
+              best_id = kExitPlane;
+              best_reg = 0;
+            }
+          }
+          if (!(S.trans_lo[0] <= S.trans_hi[0]) ||
+              slab(ray, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0], S.trans_hi[1],
+                   S.trans_hi[2], tbest) == INFINITY)
+            node = kDone;  // no inner shell ahead within the flight
+        }
+        phase = node == kDone ? kParked : kTrav;
       }
       if (__ballot(phase != kNeed) == 0 && exhausted && pend < 0 && next_h >= end_h) break;
     }
 
     // ================= one traversal step per traversing lane =================
+    bool did_node = false, did_tri = false;
     if (phase == kTrav) {
       if (tri_next >= tri_end && node < 0 && node != kDone) {
         const int code = ~node;  // a leaf taken from the stack
@@ -630,30 +664,32 @@ transport_kernel(TransportParams P) {
         node = sp > 0 ? stack[(--sp) * stride] : kDone;
       }
       if (tri_next < tri_end) {
-        // one facet test, with the region-consistency filter
+        // one facet test, with the region-consistency filter; the facet just
+        // crossed is skipped (by its caller id: it may have several slots)
         const int slot = tri_next++;
         if (COUNT) ev[kEv_TriTests]++;
-        if (slot != last) {
-          float4 a, b, c;
-          load_tri(S.tris, slot, a, b, c);
-          float t;
-          bool enter;
-          if (wt_test(ray, a, b, c, tbest, t, enter) != kWtMiss) {
-            const uint32_t regs = __float_as_uint(c.y);
-            const int inside = static_cast<int>(regs & 0xFFFFu);
-            const int outside = static_cast<int>(regs >> 16);
-            if ((enter ? outside : inside) != region) {
-              trej = fminf(trej, t);
-            } else {
-              tbest = t;
-              best_slot = slot;
-              best_reg = enter ? inside : outside;
-            }
+        did_tri = true;
+        float4 a, b, c;
+        load_tri(S.tris, slot, a, b, c);
+        const int id = __float_as_int(c.z);
+        float t;
+        bool enter;
+        if (id != last && wt_test(ray, px, py, pz, dx, dy, dz, a, b, c, tbest, t, enter) != kWtMiss) {
+          const uint32_t regs = __float_as_uint(c.y);
+          const int inside = static_cast<int>(regs & 0xFFFFu);
+          const int outside = static_cast<int>(regs >> 16);
+          if ((enter ? outside : inside) != region) {
+            trej = fminf(trej, t);
+          } else {
+            tbest = t;
+            best_id = id;
+            best_reg = enter ? inside : outside;
           }
         }
       } else if (node >= 0) {
         // one node: both child boxes against [0, tbest]
         if (COUNT) ev[kEv_NodeVisits]++;
+        did_node = true;
         float4 n0, n1, n2;
         int4 n3;
         load_node(S.nodes, node, n0, n1, n2, n3);
@@ -687,6 +723,14 @@ transport_kernel(TransportParams P) {
         }
       }
       if (tri_next >= tri_end && node == kDone) phase = kParked;
+    }
+    if (COUNT) {
+      const bool any_node = __ballot(did_node) != 0, any_tri = __ballot(did_tri) != 0;
+      if (lane == 0) {
+        ev[kEv_Iters]++;
+        if (any_node) ev[kEv_ItersNode]++;
+        if (any_tri) ev[kEv_ItersTri]++;
+      }
     }
   }
   flush();
@@ -724,13 +768,15 @@ __global__ void raycast_kernel(SceneRec sc, const float* o, const float* d, cons
   extern __shared__ int lstack[];
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
-  const Ray r = make_ray(o[3 * i], o[3 * i + 1], o[3 * i + 2], d[3 * i], d[3 * i + 1], d[3 * i + 2]);
+  const float ox = o[3 * i], oy = o[3 * i + 1], oz = o[3 * i + 2];
+  const float dx = d[3 * i], dy = d[3 * i + 1], dz = d[3 * i + 2];
+  const Ray r = make_ray(ox, oy, oz, dx, dy, dz);
   HitOut h;
   bool glitch;
   uint32_t a = 0, b = 0;
   const int cur = region ? region[i] : -1;
-  if (closest_hit<false>(sc, r, INFINITY, -1, cur, lstack + threadIdx.x, blockDim.x, h, glitch, a,
-                         b)) {
+  if (closest_hit<false>(sc, r, ox, oy, oz, dx, dy, dz, INFINITY, -1, cur, lstack + threadIdx.x,
+                         blockDim.x, h, glitch, a, b)) {
     t[i] = h.t;
     tri[i] = gload(sc.tris, h.slot).orig;
     region_after[i] = h.region_after;
@@ -780,15 +826,23 @@ __global__ void broaden_kernel(const double* in, double* out, int n_spectra, int
 using TK = void (*)(TransportParams);
 
 static TK pick(int variant) {
-  switch (variant & 7) {
-    case 0: return transport_kernel<false, false, false>;
-    case 1: return transport_kernel<true, false, false>;
-    case 2: return transport_kernel<false, true, false>;
-    case 3: return transport_kernel<true, true, false>;
-    case 4: return transport_kernel<false, false, true>;
-    case 5: return transport_kernel<true, false, true>;
-    case 6: return transport_kernel<false, true, true>;
-    default: return transport_kernel<true, true, true>;
+  switch (variant & 15) {
+    case 0: return transport_kernel<false, false, false, false>;
+    case 1: return transport_kernel<true, false, false, false>;
+    case 2: return transport_kernel<false, true, false, false>;
+    case 3: return transport_kernel<true, true, false, false>;
+    case 4: return transport_kernel<false, false, true, false>;
+    case 5: return transport_kernel<true, false, true, false>;
+    case 6: return transport_kernel<false, true, true, false>;
+    case 7: return transport_kernel<true, true, true, false>;
+    case 8: return transport_kernel<false, false, false, true>;
+    case 9: return transport_kernel<true, false, false, true>;
+    case 10: return transport_kernel<false, true, false, true>;
+    case 11: return transport_kernel<true, true, false, true>;
+    case 12: return transport_kernel<false, false, true, true>;
+    case 13: return transport_kernel<true, false, true, true>;
+    case 14: return transport_kernel<false, true, true, true>;
+    default: return transport_kernel<true, true, true, true>;
   }
 }
 

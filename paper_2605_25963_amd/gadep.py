@@ -15,7 +15,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgadep.so")
+# GADEP_LIBRARY selects another build of the library (for A/B timing)
+LIB_PATH = os.environ.get("GADEP_LIBRARY") or os.path.join(HERE, "libgadep.so")
 
 MAX_REGIONS = 64
 MAX_GROUPS = 8
@@ -23,7 +24,7 @@ ACTIVE = 1
 SRC_POINT, SRC_BEAM, SRC_CYL = 0, 1, 2
 
 OPT_MAX_STEPS, OPT_BLOCK, OPT_PERIOD, OPT_CLAIM, OPT_VALIDATE, OPT_MIN_GAP_NM, OPT_GRAPHS, \
-    OPT_COUNTERS, OPT_GRID = range(1, 10)
+    OPT_COUNTERS, OPT_GRID, OPT_EXIT_PLANES, OPT_SPLIT_PCT = range(1, 12)
 
 STATUS = {
     0: "GADEP_OK", -1: "GADEP_E_ARG", -2: "GADEP_E_MESH_OPEN", -3: "GADEP_E_MESH_ORIENT",
@@ -73,13 +74,15 @@ class Job(C.Structure):
 class Counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "segments", "crossings", "node_visits", "tri_tests", "photo", "compton", "coherent",
-        "rng_calls", "locates", "emissions")]
+        "rng_calls", "locates", "emissions", "plane_tests", "iterations", "iterations_node",
+        "iterations_facet", "passes")]
 
 
 class MeshInfo(C.Structure):
     _fields_ = [("n_shells", C.c_int32), ("genus_max", C.c_int32), ("n_nodes", C.c_int64),
-                ("depth", C.c_int32), ("sah_cost", C.c_double), ("min_gap_mm", C.c_double),
-                ("convex_exit", C.c_int32)]
+                ("depth", C.c_int32), ("sah_cost", C.c_double), ("n_slots", C.c_int64),
+                ("min_gap_mm", C.c_double), ("convex_exit", C.c_int32),
+                ("n_exit_planes", C.c_int32)]
 
 
 EXPORTS = [
@@ -136,8 +139,8 @@ def lib():
         "gadep_raycast": (i32, [p, i32, f32p, f32p, i32p, i64, f32p, i32p, i32p]),
         "gadep_locate": (i32, [p, i32, f32p, i64, i32p]),
         "gadep_mesh_prepare": (i32, [f32p, i64, i32p, i32p, i64, i32, C.c_double, i32, i32,
-                                     i32p, i32p, p, i64, i32p, C.POINTER(MeshInfo),
-                                     C.c_char_p, i32]),
+                                     C.c_double, i32p, i32p, p, i64, i32p, i64,
+                                     C.POINTER(MeshInfo), C.c_char_p, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -409,32 +412,39 @@ class Context:
 
 
 def mesh_prepare(xyz, tri, tri_region, n_regions, min_gap_mm=1e-4, validate=True, bvh_method=0,
-                 want_nodes=False):
-    """Host-only validation/topology/BVH (gadep_mesh_prepare)."""
+                 want_nodes=False, split_budget=1.0):
+    """Host-only validation/topology/BVH (gadep_mesh_prepare).  bvh_method 2
+    returns the transport BVH (spatial splits) instead of the plain one."""
     L = lib()
     xyz, tri, reg = _f32(xyz, (-1, 3)), _i32(tri).reshape(-1, 3), _i32(tri_region)
     nt = len(tri)
     outside = np.zeros(nt, np.int32)
     shell = np.zeros(nt, np.int32)
-    order = np.zeros(nt, np.int32)
     info = MeshInfo()
     err = C.create_string_buffer(512)
-    cap = 2 * nt + 2
-    nodes = np.zeros((cap, 16), np.int32) if want_nodes else None
-    rc = L.gadep_mesh_prepare(_ptr(xyz, C.c_float), len(xyz), _ptr(tri, C.c_int32),
-                              _ptr(reg, C.c_int32), nt, int(n_regions), float(min_gap_mm),
-                              1 if validate else 0, int(bvh_method), _ptr(outside, C.c_int32),
-                              _ptr(shell, C.c_int32),
-                              None if nodes is None else nodes.ctypes.data_as(C.c_void_p),
-                              cap, _ptr(order, C.c_int32), C.byref(info), err, 512)
+
+    def call(nodes, cap_nodes, order, cap_slots):
+        return L.gadep_mesh_prepare(
+            _ptr(xyz, C.c_float), len(xyz), _ptr(tri, C.c_int32), _ptr(reg, C.c_int32), nt,
+            int(n_regions), float(min_gap_mm), 1 if validate else 0, int(bvh_method),
+            float(split_budget), _ptr(outside, C.c_int32), _ptr(shell, C.c_int32),
+            None if nodes is None else nodes.ctypes.data_as(C.c_void_p), cap_nodes,
+            None if order is None else _ptr(order, C.c_int32), cap_slots, C.byref(info), err, 512)
+
+    rc = call(None, 0, None, 0)
+    if rc:
+        raise GadepError(rc, err.value.decode(errors="replace"))
+    order = np.zeros(info.n_slots, np.int32)
+    nodes = np.zeros((info.n_nodes, 16), np.int32) if want_nodes else None
+    rc = call(nodes, info.n_nodes, order, info.n_slots)
     if rc:
         raise GadepError(rc, err.value.decode(errors="replace"))
     res = dict(outside=outside, shell=shell, order=order, n_shells=info.n_shells,
                genus_max=info.genus_max, n_nodes=info.n_nodes, depth=info.depth,
-               sah_cost=info.sah_cost, min_gap_mm=info.min_gap_mm,
-               convex_exit=bool(info.convex_exit))
+               sah_cost=info.sah_cost, n_slots=info.n_slots, min_gap_mm=info.min_gap_mm,
+               convex_exit=bool(info.convex_exit), n_exit_planes=info.n_exit_planes)
     if nodes is not None:
-        res["nodes"] = nodes[: info.n_nodes]
+        res["nodes"] = nodes
     return res
 
 

@@ -285,6 +285,46 @@ def test_tallies_independent_of_launch_shape_and_split(G, ctx):
                        rtol=0, atol=1e-9)
 
 
+@pytest.mark.parametrize("where", ["inside", "outside"])
+def test_exit_planes_agree_with_facet_exit(G, ctx, orc, where):
+    # The air box is left through its six planes (default) or through its
+    # facets: same histories, same outcomes, up to rounding of the exit
+    # distance.  A beam that starts outside the box, in the void world, first
+    # crosses into it through the BVH over every facet.
+    w = C.c2_hpge(n_histories=1, distance=20.0)
+    if where == "outside":
+        w.source = C.Source(C.KIND_BEAM, pos=(3.0, 2.0, 700.0), direction=(0.0, 0.0, -1.0))
+    loaded(G, ctx, w)
+    E = [100.0, 661.7]
+    n = 2_000_000
+
+    def run(planes):
+        ctx.set_option(G.OPT_EXIT_PLANES, planes)
+        ctx.set_option(G.OPT_COUNTERS, 1)
+        r = ctx.run(w.source, E, n, 55, spectrum=(1024, 2.0))
+        c = ctx.get_counters()
+        ctx.set_option(G.OPT_COUNTERS, 0)
+        ctx.set_option(G.OPT_EXIT_PLANES, 1)
+        return r, c
+
+    facets, cf = run(0)
+    planes, cp = run(1)
+    assert cf["plane_tests"] == 0 and cp["plane_tests"] > 0
+    assert cp["node_visits"] < cf["node_visits"]
+    for f in ["n_histories", "n_absorbed", "n_fep", "n_escape", "n_uncollided"]:
+        a, b = facets.field(f), planes.field(f)
+        assert np.all(np.abs(a.astype(np.int64) - b.astype(np.int64)) <= 1e-5 * n), (f, a, b)
+    assert np.allclose(facets.field("edep_active_keV"), planes.field("edep_active_keV"), rtol=1e-5)
+    s = orc.scene_from_workload(w)
+    for k, e in enumerate(E):
+        t = planes.tallies[k]
+        assert t.n_lost == 0 and t.n_killed == 0 and t.n_glitch <= 1e-5 * n
+        assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+        o = s.run(w.source, e, 200_000, 4402 + k)
+        pg = t.n_fep / n
+        assert sigma3(pg, math.sqrt(pg * (1 - pg) / n), o.fepe(), o.fepe_sigma()), (e, pg, o.fepe())
+
+
 def test_batched_equals_single(G, ctx):
     w = C.c1_bare()
     loaded(G, ctx, w)

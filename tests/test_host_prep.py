@@ -228,10 +228,83 @@ def test_bvh_invariants(G, cfg):
 
 
 def test_convex_exit_flag(G):
-    assert prep(G, C.c1_bare().scene)["convex_exit"]  # single convex prism
-    assert prep(G, C.c2_hpge(n_seg=32, n_phi=4).scene)["convex_exit"]  # air box encloses all
+    c1 = prep(G, C.c1_bare().scene)
+    assert c1["convex_exit"]  # single convex prism
+    assert c1["n_exit_planes"] == 0  # 130 distinct planes: more than the plane list holds
+    c2 = prep(G, C.c2_hpge(n_seg=32, n_phi=4).scene)
+    assert c2["convex_exit"]  # air box encloses all
+    assert c2["n_exit_planes"] == 6  # its 12 facets lie on the 6 box planes
     b = mg.SceneBuilder()
     b.add("ring", "Cu", 8.96, _torus(20.0, 5.0, 24, 12))
-    assert not prep(G, b.build())["convex_exit"]  # non-convex outer shell
+    t = prep(G, b.build())
+    assert not t["convex_exit"] and t["n_exit_planes"] == 0  # non-convex outer shell
     job = C.c3_jobs(2)[0]
-    assert not prep(G, C.c3_job_workload(job).scene)["convex_exit"]  # two top-level shells
+    c3 = prep(G, C.c3_job_workload(job).scene)
+    assert not c3["convex_exit"] and c3["n_exit_planes"] == 0  # two top-level shells
+
+
+def test_exit_planes_of_a_lone_box(G):
+    # a single box: planes found, and the BVH of the other shells is empty
+    b = mg.SceneBuilder()
+    b.add("a", "Ge", 5.32, mg.box((-1, -2, -3), (4, 5, 6)))
+    r = prep(G, b.build())
+    assert r["convex_exit"] and r["n_exit_planes"] == 6
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_transport_bvh_covers_every_facet(G, cfg):
+    # Spatial splits clip facet references to boxes; every point of every facet
+    # searched by transport must still lie in the box of a leaf that lists it.
+    w = C.c1_bare() if cfg == "c1" else C.c2_hpge(n_seg=64, n_phi=8, n_histories=1)
+    sc = w.scene
+    r = prep(G, sc, bvh_method=2, want_nodes=True, split_budget=1.0)
+    plain = prep(G, sc)
+    nodes, ids = r["nodes"], r["order"]
+    assert r["n_slots"] == len(ids) >= 1
+    boxes = nodes[:, :12].copy().view(np.float32).reshape(-1, 2, 2, 3)
+    # leaf ranges partition the slots; child boxes nest
+    seen = np.zeros(len(ids), int)
+    leaf_box = {}
+    for i, nd in enumerate(nodes):
+        for k, c in enumerate((nd[12], nd[13])):
+            if c < 0:
+                x = ~int(c)
+                f, n = x >> 3, x & 7
+                assert n <= 4
+                seen[f:f + n] += 1
+                for j in range(f, f + n):
+                    leaf_box[j] = boxes[i, k]
+            else:
+                lo, hi = boxes[i, k]
+                clo = boxes[int(c), :, 0].min(0)
+                chi = boxes[int(c), :, 1].max(0)
+                ok = np.isfinite(clo) & np.isfinite(chi)
+                assert (lo[ok] <= clo[ok]).all() and (hi[ok] >= chi[ok]).all()
+    assert (seen == 1).all()
+    # which facets: all, or all but the outer shell's when exit planes exist
+    shell = plain["shell"]
+    if r["n_exit_planes"] > 0:
+        outer = shell[sc.shells[0][1]]
+        want = set(np.nonzero(shell != outer)[0])
+    else:
+        want = set(range(len(sc.tri)))
+    assert set(ids.tolist()) == want
+    slots_of = {}
+    for j, f in enumerate(ids):
+        slots_of.setdefault(int(f), []).append(j)
+    rng = np.random.default_rng(7)
+    V = sc.xyz.astype(np.float64)
+    for f in sorted(want)[:: max(1, len(want) // 600)]:
+        a, b, c = V[sc.tri[f]]
+        u = rng.random((24, 2))
+        u[u.sum(1) > 1] = 1 - u[u.sum(1) > 1]
+        pts = np.vstack([a, b, c, (a + b) / 2, (b + c) / 2, (a + c) / 2,
+                         a + u[:, :1] * (b - a) + u[:, 1:] * (c - a)])
+        for q in pts:
+            tol = 1e-6 * (1 + np.abs(q))
+            assert any(((leaf_box[j][0] - tol <= q) & (q <= leaf_box[j][1] + tol)).all()
+                       for j in slots_of[f]), (f, q)
+    assert r["sah_cost"] > 0
+    r0 = prep(G, sc, bvh_method=2, split_budget=0.0)
+    assert r0["n_slots"] == len(want)  # no spatial splits: one slot per facet
+    assert r["sah_cost"] <= r0["sah_cost"] * 1.0001
