@@ -85,9 +85,16 @@ typedef enum {
   GADEP_OPT_GRID = 9,         /* blocks of the persistent grid, 0 = from occupancy     */
   GADEP_OPT_EXIT_PLANES = 10, /* 1 = leave a convex outermost shell through its planes
                                  when the world is void (1); 0 = through its facets   */
-  GADEP_OPT_SPLIT_PCT = 11    /* extra facet slots the transport BVH may add by spatial
+  GADEP_OPT_SPLIT_PCT = 11,   /* extra facet slots the transport BVH may add by spatial
                                  splits, % of its facets (100); 0 = no spatial splits;
                                  applies to meshes loaded afterwards                  */
+  GADEP_OPT_SCREEN = 12       /* 1 = first-flight screening (1): with exit planes and a
+                                 point or beam source in the outermost shell's region,
+                                 each wavefront follows 64 new histories at a time to
+                                 the end of their first flight, tallies those that
+                                 leave through the planes without nearing the inner
+                                 shells, and transports the rest in full.  Tallies
+                                 are identical either way                             */
 } gadep_option;
 gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t value);
 gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* value);
@@ -127,7 +134,9 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz_mm
  * material).  Interpolation is linear in ln E of ln(mu/rho), per partial.
  * Any partial may be NULL (absent); a present partial must be all-positive or
  * all-zero.  The lowest grid energy is the photon cut-off: below it the
- * remaining energy is deposited locally.  Errors: GADEP_E_ARG, GADEP_E_XS. */
+ * remaining energy is deposited locally.  Source energies must lie on the
+ * grid and below 65536 keV (energy tallies count 2^-16 keV units).
+ * Errors: GADEP_E_ARG, GADEP_E_XS. */
 gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0_keV, double dlnE,
                           int32_t n_E, const float* mu_rho_photo, const float* mu_rho_compton,
                           const float* mu_rho_coherent);

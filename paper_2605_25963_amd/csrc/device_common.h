@@ -71,8 +71,13 @@ __device__ __noinline__ uint4 philox_block(uint32_t draw, uint32_t h_lo, uint32_
   return make_uint4(c0, c1, c2, c3);
 }
 
-// Uniform in (0, 1): 23 random bits, (k + 1/2) 2^-23, exact in FP32 so that
-// neither 0 nor 1 can occur.
+// Uniform in (0, 1) from one 32-bit output: 23 random bits, (k + 1/2) 2^-23,
+// exact in FP32 so that neither 0 nor 1 can occur.
+__device__ __forceinline__ float unit_float(uint32_t x) {
+  return (static_cast<float>(x >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+// The next uniform of a history's stream.
 template <bool COUNT>
 __device__ __forceinline__ float rng_u(Rng& g, uint32_t stream, uint32_t k0, uint32_t k1,
                                       uint32_t& nrng) {
@@ -91,7 +96,7 @@ __device__ __forceinline__ float rng_u(Rng& g, uint32_t stream, uint32_t k0, uin
   g.b1 = g.b2;
   g.b2 = g.b3;
   g.left -= 1;
-  return (static_cast<float>(x >> 9) + 0.5f) * (1.0f / 8388608.0f);
+  return unit_float(x);
 }
 
 // ---------------------------------------------------------------------------

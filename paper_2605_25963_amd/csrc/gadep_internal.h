@@ -142,11 +142,12 @@ struct TransportParams {
   unsigned long long* spectra; // [n_units][n_channels] or null
   int32_t n_channels;
   float inv_channel_kev;
-  unsigned long long* cursor;  // chunk cursor
+  unsigned long long* cursor;  // [n_units] chunk cursors
   uint32_t seed_lo, seed_hi;
   int32_t max_steps;
   int32_t stack_depth;
   int32_t period;
+  int32_t screen;              // 1: first-flight screening where it applies
 };
 
 // ---------------------------------------------------------------------------

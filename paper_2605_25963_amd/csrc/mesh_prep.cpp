@@ -688,9 +688,8 @@ class SplitBuilder {
 
 class HostQuery {
  public:
-  HostQuery(const std::vector<BvhNode>& nodes, const std::vector<int32_t>& order,
-            const std::vector<D3>& v, const std::vector<int32_t>& tri, double margin)
-      : nodes_(nodes), order_(order), v_(v), tri_(tri), m_(margin) {}
+  HostQuery(const std::vector<BvhNode>& nodes, const std::vector<int32_t>& order, double margin)
+      : nodes_(nodes), order_(order), m_(margin) {}
 
   template <class F>
   void ray_all(D3 o, D3 d, F&& visit) const {
@@ -742,8 +741,6 @@ class HostQuery {
  private:
   const std::vector<BvhNode>& nodes_;
   const std::vector<int32_t>& order_;
-  const std::vector<D3>& v_;
-  const std::vector<int32_t>& tri_;
   double m_;
 
   bool ray_box(D3 o, D3 d, const float* lo, const float* hi) const {
@@ -1051,7 +1048,7 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
   auto facet = [&](int32_t f) {
     return Tri3{v[tv[3 * f]], v[tv[3 * f + 1]], v[tv[3 * f + 2]]};
   };
-  HostQuery q(out.nodes, out.order, v, tv, 1e-9 * ext + 1e-12);
+  HostQuery q(out.nodes, out.order, 1e-9 * ext + 1e-12);
 
   // ---- shells must not intersect or come closer than min_gap
   double gap_seen = INFINITY;

@@ -15,7 +15,7 @@
 
 namespace gadep {
 // kernels.hip
-size_t transport_smem(int block, int depth);
+size_t transport_smem(int block, int depth, bool grad);
 hipError_t transport_launch(const TransportParams& P, int variant, int grid, int block,
                             hipStream_t s);
 hipError_t transport_occupancy(int variant, int block, int depth, int* blocks_per_cu);
@@ -108,6 +108,7 @@ struct gadep_ctx {
   int64_t grid = 0;
   int64_t exit_planes = 1;
   int64_t split_pct = 100;
+  int64_t screen = 1;
 
   DevBuf units, chunk_begin, scene_tab, sources, lines, regions, tally, spectra, cursor;
   void* h_tally = nullptr;  // pinned
@@ -145,8 +146,8 @@ gadep_status ensure(gadep_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return GADEP_OK;
   if (b.p) {
-    hipStreamSynchronize(ctx->stream);
-    hipFree(b.p);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
   }
@@ -155,7 +156,7 @@ gadep_status ensure(gadep_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
   b.cap = cap;
   // cached graphs refer to the old buffer
   if (ctx->graph) {
-    hipGraphExecDestroy(ctx->graph);
+    (void)hipGraphExecDestroy(ctx->graph);
     ctx->graph = nullptr;
     ctx->graph_key.clear();
   }
@@ -163,7 +164,7 @@ gadep_status ensure(gadep_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
 }
 
 void free_buf(DevBuf& b) {
-  if (b.p) hipFree(b.p);
+  if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.cap = 0;
 }
@@ -241,6 +242,8 @@ gadep_status check_energy(gadep_ctx* ctx, double E) {
   const double lo = exp(ctx->lnE0), hi = exp(ctx->lnE0 + ctx->dlnE * (ctx->nE - 1));
   if (!(E >= lo * (1 - 1e-12) && E <= hi * (1 + 1e-12)))
     return set_err(ctx, GADEP_E_XS, "energy " + std::to_string(E) + " keV outside the table grid");
+  if (!(E < 65536.0))  // energy tallies count 2^-16 keV units in 32 bits per history
+    return set_err(ctx, GADEP_E_ARG, "energy " + std::to_string(E) + " keV: at most 65536 keV");
   return GADEP_OK;
 }
 
@@ -413,7 +416,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   const int64_t spec_words = P.spectrum ? static_cast<int64_t>(nu) * P.n_channels : 0;
   if ((s = ensure(ctx, ctx->tally, tally_words * 8, "tally"))) return s;
   if ((s = ensure(ctx, ctx->spectra, std::max<int64_t>(spec_words, 1) * 8, "spectra"))) return s;
-  if ((s = ensure(ctx, ctx->cursor, 64, "cursor"))) return s;
+  if ((s = ensure(ctx, ctx->cursor, std::max<int64_t>(nu, 8) * 8, "cursor"))) return s;
 
   TransportParams K{};
   K.units = static_cast<const UnitRec*>(ctx->units.p);
@@ -439,6 +442,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   K.max_steps = static_cast<int32_t>(ctx->max_steps);
   K.stack_depth = P.depth;
   K.period = static_cast<int32_t>(ctx->period);
+  K.screen = static_cast<int32_t>(ctx->screen);
 
   bool vol = false;
   for (const SourceRec& sr : P.sources) vol = vol || sr.kind == kCyl;
@@ -464,7 +468,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   auto enqueue = [&]() -> hipError_t {
     hipError_t e = fill_u64(K.tally, tally_words, 0, ctx->stream);
     if (e == hipSuccess && spec_words) e = fill_u64(K.spectra, spec_words, 0, ctx->stream);
-    if (e == hipSuccess) e = fill_u64(K.cursor, 1, 0, ctx->stream);
+    if (e == hipSuccess) e = fill_u64(K.cursor, nu, 0, ctx->stream);
     if (e == hipSuccess)
       e = locate_units(static_cast<UnitRec*>(ctx->units.p), nu,
                        static_cast<const SceneRec*>(ctx->scene_tab.p),
@@ -476,7 +480,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   if (!ctx->graphs) {
     hipError_t e = fill_u64(K.tally, tally_words, 0, ctx->stream);
     if (e == hipSuccess && spec_words) e = fill_u64(K.spectra, spec_words, 0, ctx->stream);
-    if (e == hipSuccess) e = fill_u64(K.cursor, 1, 0, ctx->stream);
+    if (e == hipSuccess) e = fill_u64(K.cursor, nu, 0, ctx->stream);
     if (e == hipSuccess)
       e = locate_units(static_cast<UnitRec*>(ctx->units.p), nu,
                        static_cast<const SceneRec*>(ctx->scene_tab.p),
@@ -487,7 +491,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   if (ctx->graphs) {
     if (!ctx->graph || ctx->graph_key != key) {
       if (ctx->graph) {
-        hipGraphExecDestroy(ctx->graph);
+        (void)hipGraphExecDestroy(ctx->graph);
         ctx->graph = nullptr;
       }
       hipGraph_t g = nullptr;
@@ -495,12 +499,12 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
       hipError_t ce = enqueue();
       hipError_t ee = hipStreamEndCapture(ctx->stream, &g);
       if (ce != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return hip_err(ctx, ce, "capture transport");
       }
       HIP_TRY(ee, "end capture");
       hipError_t ie = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       HIP_TRY(ie, "graph instantiate");
       ctx->graph_key = key;
     }
@@ -513,7 +517,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   // read back
   const size_t need = static_cast<size_t>(tally_words) * 8;
   if (ctx->h_tally_cap < need) {
-    if (ctx->h_tally) hipHostFree(ctx->h_tally);
+    if (ctx->h_tally) (void)hipHostFree(ctx->h_tally);
     ctx->h_tally = nullptr;
     HIP_TRY(hipHostMalloc(&ctx->h_tally, need), "pinned tally");
     ctx->h_tally_cap = need;
@@ -631,22 +635,22 @@ gadep_status gadep_create(int device, void* hip_stream, gadep_ctx** out) {
 
 void gadep_destroy(gadep_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
-  if (ctx->graph) hipGraphExecDestroy(ctx->graph);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
   for (auto& sc : ctx->scenes)
     if (sc) {
-      if (sc->d_nodes) hipFree(sc->d_nodes);
-      if (sc->d_tris) hipFree(sc->d_tris);
-      if (sc->d_planes) hipFree(sc->d_planes);
+      if (sc->d_nodes) (void)hipFree(sc->d_nodes);
+      if (sc->d_tris) (void)hipFree(sc->d_tris);
+      if (sc->d_planes) (void)hipFree(sc->d_planes);
     }
   for (DevBuf* b : {&ctx->xs, &ctx->units, &ctx->chunk_begin, &ctx->scene_tab, &ctx->sources,
                     &ctx->lines, &ctx->regions, &ctx->tally, &ctx->spectra, &ctx->cursor})
     free_buf(*b);
-  if (ctx->h_tally) hipHostFree(ctx->h_tally);
-  if (ctx->ev0) hipEventDestroy(ctx->ev0);
-  if (ctx->ev1) hipEventDestroy(ctx->ev1);
-  if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+  if (ctx->h_tally) (void)hipHostFree(ctx->h_tally);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -695,6 +699,9 @@ gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t v) {
       if (v < 0 || v > 1600) return set_err(ctx, GADEP_E_ARG, "split budget must be in [0, 1600] %");
       ctx->split_pct = v;
       return GADEP_OK;
+    case GADEP_OPT_SCREEN:
+      ctx->screen = v ? 1 : 0;
+      return GADEP_OK;
     default:
       return set_err(ctx, GADEP_E_ARG, "unknown option");
   }
@@ -714,6 +721,7 @@ gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* v) 
     case GADEP_OPT_GRID: *v = ctx->grid; return GADEP_OK;
     case GADEP_OPT_EXIT_PLANES: *v = ctx->exit_planes; return GADEP_OK;
     case GADEP_OPT_SPLIT_PCT: *v = ctx->split_pct; return GADEP_OK;
+    case GADEP_OPT_SCREEN: *v = ctx->screen; return GADEP_OK;
     default: return GADEP_E_ARG;
   }
 }
@@ -740,9 +748,9 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   Scene& sc = *ctx->scenes[scene];
   HIP_TRY(hipSetDevice(ctx->device), "set device");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "sync");
-  if (sc.d_nodes) hipFree(sc.d_nodes);
-  if (sc.d_tris) hipFree(sc.d_tris);
-  if (sc.d_planes) hipFree(sc.d_planes);
+  if (sc.d_nodes) (void)hipFree(sc.d_nodes);
+  if (sc.d_tris) (void)hipFree(sc.d_tris);
+  if (sc.d_planes) (void)hipFree(sc.d_planes);
   sc.d_nodes = sc.d_tris = sc.d_planes = nullptr;
   sc.loaded = false;
   // the transport BVH follows the plain one, its indices shifted to match
@@ -790,7 +798,7 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   sc.convex_exit = pm.convex_exit;
   sc.loaded = true;
   if (ctx->graph) {
-    hipGraphExecDestroy(ctx->graph);
+    (void)hipGraphExecDestroy(ctx->graph);
     ctx->graph = nullptr;
     ctx->graph_key.clear();
   }
@@ -1014,7 +1022,7 @@ gadep_status gadep_raycast(gadep_ctx* ctx, int32_t scene, const float* o, const 
   if (e == hipSuccess) e = hipMemcpyAsync(tri, d_tri, 4 * nb, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(region_after, d_ra, 4 * nb, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  hipFree(buf);
+  (void)hipFree(buf);
   if (e != hipSuccess) return hip_err(ctx, e, "raycast");
   return GADEP_OK;
 }
@@ -1036,7 +1044,7 @@ gadep_status gadep_locate(gadep_ctx* ctx, int32_t scene, const float* p, int64_t
   if (e == hipSuccess) e = locate(sr, d_p, n, d_r, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(region, d_r, 4 * nb, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  hipFree(buf);
+  (void)hipFree(buf);
   if (e != hipSuccess) return hip_err(ctx, e, "locate");
   return GADEP_OK;
 }

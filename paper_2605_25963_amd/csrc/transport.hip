@@ -219,6 +219,12 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) 
   return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// Energies in keV (0 <= E < 65536) in units of 2^-16 keV: E * 2^16 is exact in
+// FP32, so rounding it to an integer in FP32 gives the same value as FP64.
+__device__ __forceinline__ unsigned long long fx_kev(float e) {
+  return static_cast<unsigned long long>(__float2uint_rn(e * 65536.0f));
+}
+
 __device__ __forceinline__ unsigned long long fx(double v, double scale) {
   return static_cast<unsigned long long>(__double2ll_rn(v * scale));
 }
@@ -234,13 +240,21 @@ __device__ __forceinline__ unsigned long long fx(double v, double scale) {
 // crossing, interaction, escape, scoring), takes new histories for lanes that
 // need one and sets up the next traversals, for all parked lanes at once.
 
-enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3 };
+// kSample: draw a volume-source point; kLaunch: emission point settled,
+// draw direction and first flight
+enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3, kSample = 4, kLaunch = 5 };
+constexpr int kMaxEmitAttempts = 1000;  // volume-source rejection tries per history
+constexpr int kQueue = 128;             // screened histories a wavefront can hold
+// probe direction for localising volume-source points (generic: no axis or
+// facet plane of the synthetic meshes is parallel to it)
+__constant__ float kLocateDir[3] = {0.4830462f, 0.3714437f, 0.7929236f};
 constexpr int kExitPlane = -2;  // best_id of a crossing through an exit plane
 
 // GRAD: score-function tallies; SPEC: pulse-height spectra; COUNT: event
-// counters; VOL: some unit has a volume source (emission needs localisation).
+// counters; VOL: some unit has a volume source (emission points are
+// localised by probe traversals).
 template <bool GRAD, bool SPEC, bool COUNT, bool VOL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 transport_kernel(TransportParams P) {
   extern __shared__ unsigned long long smem[];
   const int lane = static_cast<int>(__lane_id());
@@ -249,13 +263,39 @@ transport_kernel(TransportParams P) {
   unsigned long long* wt = smem + wave * kT_Slots;  // this wavefront's tally
   int* stack = reinterpret_cast<int*>(smem + nwaves * kT_Slots) + threadIdx.x;
   const int stride = static_cast<int>(blockDim.x);
+  // per-history scores of the scale groups, one LDS column per thread
+  float* sc = reinterpret_cast<float*>(stack) + P.stack_depth * stride;
+  // per-wavefront queue of screened histories that need full transport
+  int64_t* queue = reinterpret_cast<int64_t*>(
+                       reinterpret_cast<char*>(smem + nwaves * kT_Slots) +
+                       static_cast<size_t>(P.stack_depth) * stride * sizeof(int) +
+                       (GRAD ? static_cast<size_t>(kMaxGroups) * stride * sizeof(float) : 0)) +
+                   wave * kQueue;
   for (int i = lane; i < kT_Slots; i += kWave) wt[i] = 0;
 
   const uint32_t k0 = P.seed_lo, k1 = P.seed_hi;
   const int64_t total_chunks = P.chunk_begin[P.n_units];
   const int park = P.period > 0 ? (P.period > kWave ? kWave : P.period) : 32;
 
-  // wave-uniform claim state
+  // wave-uniform claim state.  Each unit has its own chunk cursor; a
+  // wavefront starts on the unit that owns its share of all chunks and moves
+  // to the next unit only when that one is used up, so it rarely has to
+  // drain (let its open histories finish) for a change of unit.
+  int claim_unit = 0;
+  {
+    const int64_t n_w = static_cast<int64_t>(gridDim.x) * nwaves;
+    const int64_t gw = static_cast<int64_t>(blockIdx.x) * nwaves + wave;
+    const int64_t x = (gw * total_chunks + total_chunks / 2) / n_w;
+    int lo = 0, hi = P.n_units - 1;  // unit u: chunk_begin[u] <= x < chunk_begin[u+1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (P.chunk_begin[mid] <= x)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    claim_unit = lo;
+  }
   int cur = -1;             // current unit
   int64_t next_h = 0, end_h = 0;
   int pend = -1;            // claimed chunk waiting for a drain
@@ -264,18 +304,19 @@ transport_kernel(TransportParams P) {
   UnitRec U{};
   SceneRec S{};
   SourceRec Src{};
+  // first-flight screening (see the refill below) and its queue
+  bool screen = false;
+  int q_head = 0, q_n = 0;
 
   // lane state: photon
   int phase = kNeed;
   float px = 0, py = 0, pz = 0, dx = 0, dy = 0, dz = 1, E = 0, tau = 0;
   float edep_act = 0, edep_tot = 0;
   int region = 0, last = -1, steps = 0;
+  int attempts = 0;  // > 0: localising a volume-source emission point (try number)
   bool clean = true, interacted = false, touched = false;
   Xs ix{0, 0.0f};
   Rng g{};
-  float sc[kMaxGroups];
-#pragma unroll
-  for (int i = 0; i < kMaxGroups; ++i) sc[i] = 0.0f;
   // lane state: current segment and its traversal
   float mu = 0, mp = 0, mc = 0;
   Ray ray{};
@@ -324,9 +365,9 @@ transport_kernel(TransportParams P) {
     if (escaped) {
       if (interacted) {
         atomicAdd(&wt[kT_CollEscape], 1ull);
-        atomicAdd(&wt[kT_EEsc], fx(E, kEnergyFix));
+        atomicAdd(&wt[kT_EEsc], fx_kev(E));
       } else {
-        acc_eunc += fx(E, kEnergyFix);
+        acc_eunc += fx_kev(E);
       }
     }
     const bool fep = absorbed && clean;
@@ -334,9 +375,9 @@ transport_kernel(TransportParams P) {
     if (fep) atomicAdd(&wt[kT_Fep], 1ull);
     if (lost) atomicAdd(&wt[kT_Lost], 1ull);
     if (killed) atomicAdd(&wt[kT_Killed], 1ull);
-    if (edep_tot > 0.0f) atomicAdd(&wt[kT_EdepTot], fx(edep_tot, kEnergyFix));
+    if (edep_tot > 0.0f) atomicAdd(&wt[kT_EdepTot], fx_kev(edep_tot));
     if (edep_act > 0.0f) {
-      atomicAdd(&wt[kT_EdepAct], fx(edep_act, kEnergyFix));
+      atomicAdd(&wt[kT_EdepAct], fx_kev(edep_act));
       if (SPEC) {
         const float ch = floorf(edep_act * P.inv_channel_kev);
         if (ch < static_cast<float>(P.n_channels))
@@ -347,10 +388,10 @@ transport_kernel(TransportParams P) {
       }
     }
     if (GRAD && touched) {
-#pragma unroll
-      for (int i = 0; i < kMaxGroups; ++i) {
-        if (i >= U.n_groups || sc[i] == 0.0f) continue;
-        const double s = static_cast<double>(sc[i]);
+      for (int i = 0; i < U.n_groups; ++i) {
+        const float si = sc[i * stride];
+        if (si == 0.0f) continue;
+        const double s = static_cast<double>(si);
         atomicAdd(&wt[kT_Score + i], fx(s, kScoreFix));
         if (fep) {
           atomicAdd(&wt[kT_FepScore + i], fx(s, kScoreFix));
@@ -360,12 +401,65 @@ transport_kernel(TransportParams P) {
     }
   };
 
+  // a point of a volume source, uniform in its cylindrical annulus
+  auto sample_point = [&]() {
+    const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
+    const float rr2 = sqrtf(fmaf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
+    const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+    px = Src.pos[0] + rr2 * __builtin_amdgcn_cosf(uphi);
+    py = Src.pos[1] + rr2 * __builtin_amdgcn_sinf(uphi);
+    pz = Src.pos[2] + rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]) * Src.h;
+  };
+
+  // the emission point is settled (region known): direction, first flight
+  auto begin_flight = [&]() {
+    acc_esrc += fx_kev(E);
+    if (Src.kind == kBeam) {
+      dx = Src.dir[0];
+      dy = Src.dir[1];
+      dz = Src.dir[2];
+    } else {
+      const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
+      const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+      const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+      dx = st * __builtin_amdgcn_cosf(uphi);
+      dy = st * __builtin_amdgcn_sinf(uphi);
+      dz = ct;
+    }
+    tau = -__logf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
+    ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+    edep_act = edep_tot = 0.0f;
+    clean = true;
+    interacted = touched = false;
+    last = -1;
+    steps = 0;
+    if (GRAD)
+      for (int i = 0; i < U.n_groups; ++i) sc[i * stride] = 0.0f;
+    phase = kSetup;
+  };
+
   for (;;) {
     const uint64_t trav = __ballot(phase == kTrav);
     if (trav == 0 || __popcll(__ballot(phase == kParked || phase == kNeed)) >= park) {
       // ================= housekeeping for every parked lane =================
       if (COUNT && lane == 0) ev[kEv_Passes]++;
-      if (phase == kParked) {
+      if (VOL && phase == kParked && attempts > 0) {
+        // ---- a volume-source point was localised: the region on the near
+        // side of the first facet along the probe ray (the world if none)
+        const int here = best_id != -1 ? (best_reg >> 8) : 0;
+        if (here == Src.region) {
+          attempts = 0;
+          region = here;
+          phase = kLaunch;
+        } else if (attempts < kMaxEmitAttempts) {
+          phase = kSample;
+        } else {
+          attempts = 0;
+          atomicAdd(&wt[kT_SrcFail], 1ull);
+          acc_hist += 1;
+          phase = kNeed;
+        }
+      } else if (phase == kParked) {
         // ---- outcome of the finished traversal
         if (trej < tbest) atomicAdd(&wt[kT_Glitch], 1ull);
         const RegionRec rr = gload(P.regions, U.region_off + region);
@@ -379,17 +473,14 @@ transport_kernel(TransportParams P) {
           // boundary crossing (a facet, or the outermost shell's exit plane)
           if (COUNT) ev[kEv_Crossings]++;
           if (GRAD && grp < kMaxGroups) {
-            const float d0 = mu * rr.inv_scale * tbest;
-#pragma unroll
-            for (int i = 0; i < kMaxGroups; ++i)
-              if (grp == i) sc[i] -= d0;
+            sc[grp * stride] -= mu * rr.inv_scale * tbest;
             touched = true;
           }
           px = fmaf(tbest, dx, px);
           py = fmaf(tbest, dy, py);
           pz = fmaf(tbest, dz, pz);
           tau = fmaxf(0.0f, fmaf(-mu, tbest, tau));
-          region = best_reg;
+          region = best_reg & 0xFF;
           last = best_id;
           if (region == 0 && (U.flags & kUnitExitEscapes)) {
             // left the convex outermost shell into the void world: nothing ahead
@@ -403,10 +494,7 @@ transport_kernel(TransportParams P) {
           py = fmaf(s, dy, py);
           pz = fmaf(s, dz, pz);
           if (GRAD && grp < kMaxGroups) {
-            const float d = rr.inv_scale - mu * rr.inv_scale * s;
-#pragma unroll
-            for (int i = 0; i < kMaxGroups; ++i)
-              if (grp == i) sc[i] += d;
+            sc[grp * stride] += rr.inv_scale - mu * rr.inv_scale * s;
             touched = true;
           }
           last = -1;
@@ -495,121 +583,206 @@ transport_kernel(TransportParams P) {
       // ---- new histories for lanes that need one (chunks of the wave's unit)
       const uint64_t need = __ballot(phase == kNeed);
       if (need) {
-        if (next_h >= end_h && pend < 0 && !exhausted) {
-          unsigned long long c = 0;
-          if (lane == 0) c = atomicAdd(P.cursor, 1ull);
-          c = uniform_u64(__shfl(c, 0, kWave));
-          if (static_cast<int64_t>(c) >= total_chunks) {
-            exhausted = true;
-          } else {
-            int lo = 0, hi = P.n_units - 1;  // unit u: chunk_begin[u] <= c < chunk_begin[u+1]
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (P.chunk_begin[mid] <= static_cast<int64_t>(c))
-                lo = mid;
-              else
-                hi = mid - 1;
+        const int n_need = __popcll(need);
+        for (;;) {
+          if (next_h >= end_h && pend < 0 && !exhausted) {
+            // next chunk of the claim unit, else of the units after it in turn
+            for (int t = 0; t < P.n_units; ++t) {
+              unsigned long long c = 0;
+              if (lane == 0) c = atomicAdd(P.cursor + claim_unit, 1ull);
+              c = uniform_u64(__shfl(c, 0, kWave));
+              const int64_t n_chunks = P.chunk_begin[claim_unit + 1] - P.chunk_begin[claim_unit];
+              if (static_cast<int64_t>(c) < n_chunks) {
+                pend = claim_unit;
+                pend_h0 = static_cast<int64_t>(c) * P.chunk;
+                const int64_t nu = P.units[claim_unit].n;
+                pend_h1 = pend_h0 + P.chunk < nu ? pend_h0 + P.chunk : nu;
+                break;
+              }
+              claim_unit = claim_unit + 1 == P.n_units ? 0 : claim_unit + 1;
             }
-            pend = lo;
-            const int64_t local = static_cast<int64_t>(c) - P.chunk_begin[lo];
-            pend_h0 = local * P.chunk;
-            const int64_t nu = P.units[lo].n;
-            pend_h1 = pend_h0 + P.chunk < nu ? pend_h0 + P.chunk : nu;
+            if (pend < 0) exhausted = true;
           }
-        }
-        // a chunk of another unit starts only when no history of this one is open
-        if (next_h >= end_h && pend >= 0 && (pend == cur || __ballot(phase != kNeed) == 0)) {
-          if (pend != cur) {
-            flush();
-            cur = pend;
-            U = P.units[cur];
-            S = P.scenes[U.scene];
-            Src = P.sources[U.source];
+          // a chunk of another unit starts only when no history of this one
+          // is open or queued
+          if (next_h >= end_h && pend >= 0 &&
+              (pend == cur || (q_n == 0 && __ballot(phase != kNeed) == 0))) {
+            if (pend != cur) {
+              flush();
+              cur = pend;
+              U = P.units[cur];
+              S = P.scenes[U.scene];
+              Src = P.sources[U.source];
+              const RegionRec ro = gload(P.regions, U.region_off + S.outer_region);
+              screen = P.screen && (U.flags & kUnitExitPlanes) && Src.kind != kCyl &&
+                       U.src_region == S.outer_region && (!GRAD || (ro.bits & 0xFF) == 0xFF);
+            }
+            next_h = pend_h0;
+            end_h = pend_h1;
+            pend = -1;
           }
-          next_h = pend_h0;
-          end_h = pend_h1;
-          pend = -1;
-        }
-        if (next_h < end_h) {
-          const uint64_t below = need & ((1ull << lane) - 1ull);
-          const int64_t h = next_h + __popcll(below);
-          if (phase == kNeed && h < end_h) {
-            // ---- emission
-            rng_start(g, static_cast<uint64_t>(U.first + h));
-            if (COUNT) ev[kEv_Emissions]++;
+          if (!(screen && q_n < n_need && next_h < end_h)) break;
+          // ---- first-flight screening: every lane takes one of the next 64
+          // histories and follows it to the end of its first flight.  Those
+          // that leave the outermost shell through its planes without coming
+          // near the inner shells (the common case for a distant source) are
+          // tallied here; the rest are queued for full transport, which
+          // repeats the same draws and arithmetic.
+          const int64_t h = next_h + lane;
+          next_h = next_h + kWave < end_h ? next_h + kWave : end_h;
+          bool survivor = false;
+          if (h < end_h) {
+            const uint64_t hist = static_cast<uint64_t>(U.first + h);
+            const uint4 w = philox_block(0u, static_cast<uint32_t>(hist),
+                                         static_cast<uint32_t>(hist >> 32), U.stream, k0, k1);
+            float u0 = unit_float(w.x), u1 = unit_float(w.y), u2 = unit_float(w.z);
+            const float u3 = unit_float(w.w);
+            float e = U.energy;
             if (Src.n_lines > 0) {
-              const float x = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
               const float2* L = reinterpret_cast<const float2*>(P.lines) + Src.line_off;
               int pick = Src.n_lines - 1;
               for (int i = 0; i < Src.n_lines; ++i)
-                if (x < L[i].y) {
+                if (u0 < L[i].y) {
                   pick = i;
                   break;
                 }
-              E = L[pick].x;
-            } else {
-              E = U.energy;
+              e = L[pick].x;
+              u0 = u1;
+              u1 = u2;
+              u2 = u3;
             }
-            const float E0 = E;
-            bool ok = true;
-            if (VOL && Src.kind == kCyl) {
-              ok = false;
-              const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
-              for (int attempt = 0; attempt < 1000 && !ok; ++attempt) {
-                const float rr2 = sqrtf(fmaf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
-                const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
-                px = Src.pos[0] + rr2 * __builtin_amdgcn_cosf(uphi);
-                py = Src.pos[1] + rr2 * __builtin_amdgcn_sinf(uphi);
-                pz = Src.pos[2] + rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]) * Src.h;
-                if (COUNT) ev[kEv_Locates]++;
-                uint32_t nv = 0, nt = 0;
-                ok = locate_parity<COUNT>(S, px, py, pz, stack, stride, COUNT ? ev[kEv_NodeVisits] : nv,
-                                          COUNT ? ev[kEv_TriTests] : nt) == Src.region;
-              }
-              region = Src.region;
-            } else {
-              px = Src.pos[0];
-              py = Src.pos[1];
-              pz = Src.pos[2];
-              region = U.src_region;
-              ok = region >= 0;
+            float qx = Src.dir[0], qy = Src.dir[1], qz = Src.dir[2];
+            if (Src.kind != kBeam) {
+              const float ct = fmaf(2.0f, u0, -1.0f);
+              const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+              qx = st * __builtin_amdgcn_cosf(u1);
+              qy = st * __builtin_amdgcn_sinf(u1);
+              qz = ct;
+              u0 = u2;
             }
-            if (!ok) {
-              atomicAdd(&wt[kT_SrcFail], 1ull);
+            const float tau0 = -__logf(u0);
+            const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
+            float m_p, m_c, m_h;
+            xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr,
+                  xs_index(e, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
+            const float m = m_p + m_c + m_h;
+            const float tfl = m > 0.0f ? tau0 / m : INFINITY;
+            const float ox = Src.pos[0], oy = Src.pos[1], oz = Src.pos[2];
+            float te = INFINITY;
+            for (int i = 0; i < S.n_planes; ++i) {
+              const float4 pl = gload(reinterpret_cast<const float4*>(S.planes), i);
+              const float dn = pl.x * qx + pl.y * qy + pl.z * qz;
+              const float num = pl.w - (pl.x * ox + pl.y * oy + pl.z * oz);
+              if (dn > 0.0f) te = fminf(te, num * __builtin_amdgcn_rcpf(dn));
+            }
+            te = fmaxf(te, 0.0f);
+            bool escapes = te <= tfl;
+            if (escapes && S.trans_lo[0] <= S.trans_hi[0]) {
+              const Ray r0 = make_ray(ox, oy, oz, qx, qy, qz);
+              escapes = slab(r0, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0],
+                             S.trans_hi[1], S.trans_hi[2], te) == INFINITY;
+            }
+            if (escapes) {
               acc_hist += 1;
-            } else {
-              acc_esrc += fx(E0, kEnergyFix);
-              if (Src.kind == kBeam) {
-                dx = Src.dir[0];
-                dy = Src.dir[1];
-                dz = Src.dir[2];
-              } else {
-                const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
-                const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-                const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
-                dx = st * __builtin_amdgcn_cosf(uphi);
-                dy = st * __builtin_amdgcn_sinf(uphi);
-                dz = ct;
+              acc_esrc += fx_kev(e);
+              acc_eunc += fx_kev(e);
+              if (COUNT) {
+                ev[kEv_Emissions]++;
+                ev[kEv_Segments]++;
+                ev[kEv_Crossings]++;
+                ev[kEv_Rng]++;
+                ev[kEv_PlaneTests] += S.n_planes;
               }
-              tau = -__logf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
-              ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
-              edep_act = edep_tot = 0.0f;
-              clean = true;
-              interacted = touched = false;
-              last = -1;
-              steps = 0;
-#pragma unroll
-              for (int i = 0; i < kMaxGroups; ++i) sc[i] = 0.0f;
-              phase = kSetup;
+            } else {
+              survivor = true;
             }
           }
-          next_h += __popcll(need);
+          const uint64_t surv = __ballot(survivor);
+          if (survivor) {
+            const int rank = __popcll(surv & ((1ull << lane) - 1ull));
+            queue[(q_head + q_n + rank) & (kQueue - 1)] = h;
+          }
+          __builtin_amdgcn_wave_barrier();
+          q_n += __popcll(surv);
+        }
+        // hand out histories: from the queue when screening, else in order
+        const uint64_t below = need & ((1ull << lane) - 1ull);
+        const int rank = __popcll(below);
+        int64_t h = -1;
+        if (screen) {
+          if (phase == kNeed && rank < q_n) h = queue[(q_head + rank) & (kQueue - 1)];
+          __builtin_amdgcn_wave_barrier();
+          const int taken = n_need < q_n ? n_need : q_n;
+          q_head = (q_head + taken) & (kQueue - 1);
+          q_n -= taken;
+        } else if (next_h < end_h) {
+          if (phase == kNeed && next_h + rank < end_h) h = next_h + rank;
+          next_h += n_need;
           if (next_h > end_h) next_h = end_h;
+        }
+        if (phase == kNeed && h >= 0) {
+          // ---- emission
+          rng_start(g, static_cast<uint64_t>(U.first + h));
+          if (COUNT) ev[kEv_Emissions]++;
+          if (Src.n_lines > 0) {
+            const float x = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+            const float2* L = reinterpret_cast<const float2*>(P.lines) + Src.line_off;
+            int pick = Src.n_lines - 1;
+            for (int i = 0; i < Src.n_lines; ++i)
+              if (x < L[i].y) {
+                pick = i;
+                break;
+              }
+            E = L[pick].x;
+          } else {
+            E = U.energy;
+          }
+          if (VOL && Src.kind == kCyl) {
+            // rejection sampling: each point is localised by a probe traversal
+            attempts = 0;
+            phase = kSample;
+          } else {
+            px = Src.pos[0];
+            py = Src.pos[1];
+            pz = Src.pos[2];
+            region = U.src_region;
+            if (region >= 0) {
+              phase = kLaunch;
+            } else {
+              atomicAdd(&wt[kT_SrcFail], 1ull);
+              acc_hist += 1;
+            }
+          }
         }
       }
 
+      if (VOL && phase == kSample) {
+        // next try of a volume-source point
+        ++attempts;
+        sample_point();
+        phase = kSetup;
+      }
+      if (phase == kLaunch) begin_flight();
+
       // ---- set up the next segment: attenuation, flight limit, ray
-      if (phase == kSetup) {
+      if (VOL && phase == kSetup && attempts > 0) {
+        // probe ray of a volume-source point: nearest facet of any region
+        if (COUNT) ev[kEv_Locates]++;
+        dx = kLocateDir[0];
+        dy = kLocateDir[1];
+        dz = kLocateDir[2];
+        ray = make_ray(px, py, pz, dx, dy, dz);
+        region = -1;
+        last = -1;
+        mu = 0.0f;
+        tbest = INFINITY;
+        trej = INFINITY;
+        node = S.root_all;
+        sp = 0;
+        tri_next = tri_end = 0;
+        best_id = -1;
+        phase = kTrav;
+      } else if (phase == kSetup) {
         if (COUNT) ev[kEv_Segments]++;
         const RegionRec rr = gload(P.regions, U.region_off + region);
         float mh;
@@ -651,10 +824,12 @@ transport_kernel(TransportParams P) {
         }
         phase = node == kDone ? kParked : kTrav;
       }
-      if (__ballot(phase != kNeed) == 0 && exhausted && pend < 0 && next_h >= end_h) break;
+      if (__ballot(phase != kNeed) == 0 && exhausted && pend < 0 && next_h >= end_h && q_n == 0)
+        break;
     }
 
     // ================= one traversal step per traversing lane =================
+    // the facets of a pending leaf first (one per step), else one node
     bool did_node = false, did_tri = false;
     if (phase == kTrav) {
       if (tri_next >= tri_end && node < 0 && node != kDone) {
@@ -678,12 +853,13 @@ transport_kernel(TransportParams P) {
           const uint32_t regs = __float_as_uint(c.y);
           const int inside = static_cast<int>(regs & 0xFFFFu);
           const int outside = static_cast<int>(regs >> 16);
-          if ((enter ? outside : inside) != region) {
+          const int before = enter ? outside : inside;
+          if (region >= 0 && before != region) {
             trej = fminf(trej, t);
           } else {
             tbest = t;
             best_id = id;
-            best_reg = enter ? inside : outside;
+            best_reg = (enter ? inside : outside) | (before << 8);  // after | before << 8
           }
         }
       } else if (node >= 0) {
@@ -846,14 +1022,17 @@ static TK pick(int variant) {
   }
 }
 
-size_t transport_smem(int block, int depth) {
+// LDS: per-wavefront tallies, the traversal stacks, and (GRAD) the scores
+size_t transport_smem(int block, int depth, bool grad) {
   return static_cast<size_t>(block / kWave) * kT_Slots * sizeof(unsigned long long) +
-         static_cast<size_t>(depth) * block * sizeof(int);
+         static_cast<size_t>(depth) * block * sizeof(int) +
+         (grad ? static_cast<size_t>(kMaxGroups) * block * sizeof(float) : 0) +
+         static_cast<size_t>(block / kWave) * kQueue * sizeof(int64_t);
 }
 
 hipError_t transport_launch(const TransportParams& P, int variant, int grid, int block,
                             hipStream_t s) {
-  const size_t smem = transport_smem(block, P.stack_depth);
+  const size_t smem = transport_smem(block, P.stack_depth, variant & 1);
   hipLaunchKernelGGL(pick(variant), dim3(grid), dim3(block), smem, s, P);
   return hipGetLastError();
 }
@@ -861,7 +1040,7 @@ hipError_t transport_launch(const TransportParams& P, int variant, int grid, int
 hipError_t transport_occupancy(int variant, int block, int depth, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks_per_cu, reinterpret_cast<const void*>(pick(variant)), block,
-      transport_smem(block, depth));
+      transport_smem(block, depth, variant & 1));
 }
 
 hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {

@@ -24,7 +24,7 @@ ACTIVE = 1
 SRC_POINT, SRC_BEAM, SRC_CYL = 0, 1, 2
 
 OPT_MAX_STEPS, OPT_BLOCK, OPT_PERIOD, OPT_CLAIM, OPT_VALIDATE, OPT_MIN_GAP_NM, OPT_GRAPHS, \
-    OPT_COUNTERS, OPT_GRID, OPT_EXIT_PLANES, OPT_SPLIT_PCT = range(1, 12)
+    OPT_COUNTERS, OPT_GRID, OPT_EXIT_PLANES, OPT_SPLIT_PCT, OPT_SCREEN = range(1, 13)
 
 STATUS = {
     0: "GADEP_OK", -1: "GADEP_E_ARG", -2: "GADEP_E_MESH_OPEN", -3: "GADEP_E_MESH_ORIENT",

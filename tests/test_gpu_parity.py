@@ -325,6 +325,40 @@ def test_exit_planes_agree_with_facet_exit(G, ctx, orc, where):
         assert sigma3(pg, math.sqrt(pg * (1 - pg) / n), o.fepe(), o.fepe_sigma()), (e, pg, o.fepe())
 
 
+@pytest.mark.parametrize("case", ["point", "lines", "grad"])
+def test_first_flight_screening_is_exact(G, ctx, case):
+    # Screening tallies the histories that leave the air box on their first
+    # flight without nearing the detector, and repeats the same draws and
+    # arithmetic as full transport: every tally must be identical with it off.
+    w = C.c2_hpge(n_histories=1)
+    loaded(G, ctx, w)
+    src, E = w.source, [60.0, 661.7]
+    if case == "lines":
+        src = C.Source(C.KIND_POINT, pos=w.source.pos, lines_keV=[59.54, 661.66, 1332.5],
+                       lines_prob=[0.36, 0.85, 1.0])
+        E = None
+    n = 3_000_000
+
+    def run(on):
+        ctx.set_option(G.OPT_SCREEN, on)
+        if case == "grad":
+            r = ctx.run_grad(src, E, n, 91, scales=[1.0] * len(w.groups))
+        else:
+            r = ctx.run(src, E, n, 91, spectrum=(1024, 2.0))
+        ctx.set_option(G.OPT_SCREEN, 1)
+        return r
+
+    off, on = run(0), run(1)
+    for f in ["n_histories", "n_absorbed", "n_fep", "n_escape", "n_uncollided", "n_lost",
+              "n_killed", "n_glitch", "edep_active_keV", "edep_total_keV", "e_escape_keV",
+              "e_source_keV"]:
+        assert np.array_equal(off.field(f), on.field(f)), f
+    if case == "grad":
+        assert np.array_equal(off.grad, on.grad)
+    else:
+        assert np.array_equal(off.spectra, on.spectra)
+
+
 def test_batched_equals_single(G, ctx):
     w = C.c1_bare()
     loaded(G, ctx, w)
