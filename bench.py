@@ -12,6 +12,11 @@ five detector density groups (fwd+grad / fwd cost), the ALU roofline of the
 transport kernel and the CPU oracle on a bounded sample.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
+python bench.py --workload {c2near,c3,c4,c5,build} [--steps K] [--warmup W]
+    secondary workloads (one JSON line each, not the metric): the same detector
+    with the source at 100 mm; 64 bottle jobs batched against one launch per job;
+    volume source with gradients; the ~1M-facet Marinelli stress case; mesh
+    preparation times.
 """
 from __future__ import annotations
 
@@ -21,6 +26,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -84,6 +91,12 @@ def parse():
                     help="profiling run: 1e7 histories per energy, no grad, no CPU baseline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device three times (scales HBM byte counters)")
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c2near", "c3", "c4", "c5", "build"],
+                    help="c2: the metric (default); c2near: same at 100 mm; c3: 64 bottle jobs "
+                         "batched vs one launch each; c4: volume source, fwd+grad/fwd; c5: "
+                         "~1M facets, Marinelli, 16 matrices, lines, spectra; build: mesh "
+                         "preparation + upload times")
     a = ap.parse_args()
     if a.quick:
         a.min_histories, a.pilot, a.no_grad, a.no_cpu_baseline = 1e7, 1e6, True, True
@@ -135,12 +148,15 @@ def main():
         print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
               "the path shards over independent histories, see the design notes", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_2605_25963_amd import gadep
     from workloads import configs as C
 
-    w = C.c2_hpge(n_histories=0)
+    if a.workload not in ("c2", "c2near"):
+        print(json.dumps(OTHER[a.workload](a, torch, gadep, C)), flush=True)
+        return
+    distance = 250.0 if a.workload == "c2" else 100.0
+    w = C.c2_hpge(n_histories=0, distance=distance)
     stream = torch.cuda.current_stream()
     ctx = gadep.Context(0, stream if stream.cuda_stream else None)
     gadep.load_workload(ctx, w)
@@ -199,12 +215,16 @@ def main():
     lanes = {"node": ev["node_visits"] / max(ev["iterations_node"], 1),
              "facet": ev["tri_tests"] / max(ev["iterations_facet"], 1),
              "iterations_per_pass": ev["iterations"] / max(ev["passes"], 1)}
+    # where the wavefronts' time goes (counting variant, shader-clock cycles)
+    cyc = {k[7:]: ev[k] for k in ev if k.startswith("cycles_")}
+    cyc_total = max(sum(cyc.values()), 1)
+    lanes["time_share"] = {k: v / cyc_total for k, v in cyc.items()}
     k_ms = float(np.mean(kernel_ms))
     achieved = ops / (k_ms * 1e-3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": measured_traffic(),
             "kernel_ms": k_ms, "ops_per_history": ops / total,
-            "events_per_history": {k: ev[k] / total for k in ev},
+            "events_per_history": {k: ev[k] / total for k in ev if not k.startswith("cycles_")},
             "active_lanes": lanes}
 
     base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
@@ -221,7 +241,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "hpge_coaxial_20236_facets_point_250mm_12_energies",
+        "config": {"workload": f"hpge_coaxial_20236_facets_point_{distance:.0f}mm_12_energies",
                    "n_facets": int(len(w.scene.tri)), "energies_keV": [round(e, 3) for e in w.energies],
                    "histories_per_energy": [int(x) for x in n_e], "histories_per_step": total,
                    "max_fepe_rse": float(rse.max())},
@@ -232,6 +252,153 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# secondary workloads (one JSON line each; not the metric)
+
+def _timed(ctx, torch, fn, steps, warmup):
+    for i in range(warmup):
+        fn()
+        print(f"bench: warm-up step {i + 1} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ks = []
+    for i in range(steps):
+        fn()
+        ks.append(ctx.get_last_launch_ms())
+        print(f"bench: step {i + 1} done ({ks[-1]:.1f} ms)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, float(np.mean(ks)) if ks else None
+
+
+def _line(metric, value, unit, a, dt, workload, extra, higher=True):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": a.steps,
+         "warmup": a.warmup, "ms_per_step": dt * 1e3, "higher_is_better": higher,
+         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+         "config": {"workload": workload}}
+    d.update(extra)
+    return d
+
+
+def _rates(ctx, gadep, run, k_ms):
+    """Event counts of one run (counting variant) as rates over the timed launch."""
+    ctx.set_option(gadep.OPT_COUNTERS, 1)
+    run()
+    ev = ctx.get_counters()
+    ctx.set_option(gadep.OPT_COUNTERS, 0)
+    s = k_ms * 1e-3
+    return {"node_visits_per_s": ev["node_visits"] / s, "facet_tests_per_s": ev["tri_tests"] / s,
+            "interactions_per_s": (ev["photo"] + ev["compton"] + ev["coherent"]) / s,
+            "segments_per_s": ev["segments"] / s}
+
+
+def bench_c3(a, torch, gadep, C):
+    jobs = C.c3_jobs(64)
+    ws = [C.c3_job_workload(j) for j in jobs]
+    ctx = gadep.Context(0)
+    for k, w in enumerate(ws):
+        gadep.load_workload(ctx, w, scene=k)
+    spec = [dict(source=w.source, energies=w.energies, n_histories=max(1, j["n_total"] // len(w.energies)),
+                 scene=k, stream=k) for k, (j, w) in enumerate(zip(jobs, ws))]
+    total = sum(s["n_histories"] * len(s["energies"]) for s in spec)
+    dt, k_ms = _timed(ctx, torch, lambda: ctx.run_batch(spec, 1003), a.steps, a.warmup)
+    singles = 0.0
+    for s1 in spec:
+        ctx.run_batch([s1], 1003)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run_batch([s1], 1003)
+        torch.cuda.synchronize()
+        singles += time.perf_counter() - t0
+    return _line("histories/s, 64 bottle jobs x 20 energies in one launch", total / dt, "histories/s",
+                 a, dt, "c3_64_bottle_jobs_on_256_facet_crystal_20_energies",
+                 {"histories_per_step": total, "kernel_ms": k_ms, "sum_of_single_job_launches_s": singles,
+                  "batched_over_single_speedup": singles / dt,
+                  "rates": _rates(ctx, gadep, lambda: ctx.run_batch(spec, 1003), k_ms)})
+
+
+def bench_c4(a, torch, gadep, C):
+    w = C.c4_grad()
+    ctx = gadep.Context(0)
+    gadep.load_workload(ctx, w)
+    ng = len(w.groups)
+    J = [dict(source=w.source, energies=w.energies, n_histories=w.n_histories, stream=0)]
+    JG = [dict(J[0], scales=[1.0] * ng)]
+    total = w.n_histories * len(w.energies)
+    dt, k_ms = _timed(ctx, torch, lambda: ctx.run_batch(J, 1004), a.steps, a.warmup)
+    dtg, kg_ms = _timed(ctx, torch, lambda: ctx.run_batch(JG, 1004, grad=True), a.steps, a.warmup)
+    return _line("histories/s, C2 detector + water sample, volume source, 20 energies",
+                 total / dt, "histories/s", a, dt, "c4_hpge_water_sample_volume_source_20_energies",
+                 {"histories_per_step": total, "kernel_ms": k_ms, "grad_kernel_ms": kg_ms,
+                  "fwd_grad_over_fwd": dtg / dt,
+                  "rates": _rates(ctx, gadep, lambda: ctx.run_batch(J, 1004), k_ms)})
+
+
+def bench_c5(a, torch, gadep, C):
+    t0 = time.perf_counter()
+    w = C.c5_stress()
+    t_gen = time.perf_counter() - t0
+    ctx = gadep.Context(0)
+    print(f"bench: {len(w.scene.tri)} facets generated", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    gadep.load_workload(ctx, w)
+    t_load = time.perf_counter() - t0
+    print(f"bench: mesh loaded in {t_load:.1f} s", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(3005)
+    mat, rho, grp, act = w.region_arrays()
+    m = w.scene.region_id("matrix")
+    ng = len(w.groups)
+    n_job = w.n_histories  # 2e9 histories over 16 matrices
+    jobs = []
+    for j in range(16):
+        mo, do = mat.copy(), rho.copy()
+        mo[m] = w.materials.index("water" if j % 2 == 0 else "soil")
+        do[m] = float(rng.uniform(0.8, 1.6))
+        jobs.append(dict(source=w.source, energies=None, n_histories=n_job, stream=j,
+                         scales=[1.0] * ng, material_override=mo, density_override=do))
+    total = n_job * 16
+    nch, width = 8192, 0.25
+    holder = {}
+
+    def run():
+        holder["r"] = ctx.run_batch(jobs, 1005, grad=True, spectrum=(nch, width))
+
+    dt, k_ms = _timed(ctx, torch, run, a.steps, a.warmup)
+    spec = torch.tensor(holder["r"].spectra.astype(np.float64), device="cuda")
+    out = torch.empty_like(spec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.broaden_dev(spec.data_ptr(), out.data_ptr(), 16, nch, width, 0.64, 0.0018)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    return _line("histories/s, ~1M-facet detector + Marinelli, 16 matrices, lines, spectra, gradients",
+                 total / dt, "histories/s", a, dt, "c5_marinelli_962572_facets_16_matrices_13_lines",
+                 {"histories_per_step": total, "kernel_ms": k_ms, "n_facets": int(len(w.scene.tri)),
+                  "mesh_generation_s": t_gen, "load_mesh_s": t_load, "broadening_16x8192_ms": t_b * 1e3})
+
+
+def bench_build(a, torch, gadep, C):
+    ctx = gadep.Context(0)
+    out = {}
+    for name, make in (("c1_256", lambda: C.c1_bare()), ("c2_20236", lambda: C.c2_hpge(n_histories=1)),
+                       ("c5_962572", lambda: C.c5_stress(n_histories=1))):
+        w = make()
+        mat, rho, grp, act = w.region_arrays()
+        regions = [(int(mat[r]), float(rho[r]), int(grp[r]), gadep.ACTIVE if act[r] else 0)
+                   for r in range(len(mat))]
+        t0 = time.perf_counter()
+        ctx.load_scene(0, w.scene.xyz, w.scene.tri, w.scene.tri_region, regions)
+        torch.cuda.synchronize()
+        out[name] = {"facets": int(len(w.scene.tri)), "seconds": time.perf_counter() - t0}
+        print(f"bench: {name} loaded", file=sys.stderr, flush=True)
+    tot = sum(v["seconds"] for v in out.values())
+    return _line("seconds to validate, derive topology, build both BVHs and upload a mesh",
+                 tot, "s", a, tot, "load_mesh_256_20236_962572_facets", {"per_mesh": out},
+                 higher=False)
+
+
+OTHER = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "build": bench_build}
 
 
 if __name__ == "__main__":

@@ -74,8 +74,8 @@ typedef enum {
   GADEP_OPT_PERIOD = 3,       /* park threshold: lanes of a wavefront that finish their
                                  traversal wait until this many (1..64) have, then the
                                  wavefront runs physics, scoring and new histories for
-                                 all of them together; 0 = default (32)                */
-  GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim            */
+                                 all of them together; 0 = default (24)                */
+  GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim (8)        */
   GADEP_OPT_VALIDATE = 5,     /* 1 = validate meshes at load (default); 0 skips the
                                  closed/orientation/overlap checks (fault-injection
                                  tests only: results are undefined on a bad mesh)      */
@@ -236,6 +236,10 @@ typedef struct {
    * node step / a facet test, and passes of the batched per-segment work
    * (outcomes, new histories, set-up) */
   uint64_t iterations, iterations_node, iterations_facet, passes;
+  /* per wavefront, shader-clock cycles spent in: outcomes of finished
+   * segments, handing out new histories (with screening), drawing emission
+   * directions, segment set-up, traversal steps */
+  uint64_t cycles_outcome, cycles_refill, cycles_launch, cycles_setup, cycles_traversal;
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 

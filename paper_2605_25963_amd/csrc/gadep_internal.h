@@ -120,7 +120,9 @@ enum EventSlot : int {
   kEv_Coherent, kEv_Rng, kEv_Locates, kEv_Emissions, kEv_PlaneTests,
   // wavefront-level: loop iterations, those with a node / facet step, passes
   // of the batched per-segment work
-  kEv_Iters, kEv_ItersNode, kEv_ItersTri, kEv_Passes, kEv_N
+  kEv_Iters, kEv_ItersNode, kEv_ItersTri, kEv_Passes,
+  // wavefront-level shader-clock cycles per section of the loop
+  kEv_CycOutcome, kEv_CycRefill, kEv_CycLaunch, kEv_CycSetup, kEv_CycTrav, kEv_N
 };
 static_assert(kT_Ev + kEv_N <= kT_Slots, "tally slots");
 

@@ -100,7 +100,7 @@ struct gadep_ctx {
   int64_t max_steps = 10000;
   int64_t block = 256;
   int64_t period = 0;
-  int64_t claim = 32;
+  int64_t claim = 8;
   int64_t validate = 1;
   int64_t min_gap_nm = 100;
   int64_t graphs = 1;
@@ -572,6 +572,11 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     cnt.iterations_node += ev[kEv_ItersNode];
     cnt.iterations_facet += ev[kEv_ItersTri];
     cnt.passes += ev[kEv_Passes];
+    cnt.cycles_outcome += ev[kEv_CycOutcome];
+    cnt.cycles_refill += ev[kEv_CycRefill];
+    cnt.cycles_launch += ev[kEv_CycLaunch];
+    cnt.cycles_setup += ev[kEv_CycSetup];
+    cnt.cycles_traversal += ev[kEv_CycTrav];
   }
   if (ctx->counters) {
     ctx->last_counters = cnt;
@@ -923,7 +928,7 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
   // runs the batched physics); tallies do not depend on any of them
   const int64_t blocks[] = {128, 256};
   const int64_t claims[] = {8, 32};
-  const int64_t periods[] = {16, 32, 48};
+  const int64_t periods[] = {16, 24, 32};
   for (int64_t b : blocks)
     for (int64_t c : claims)
       for (int64_t q : periods) {

@@ -275,7 +275,7 @@ transport_kernel(TransportParams P) {
 
   const uint32_t k0 = P.seed_lo, k1 = P.seed_hi;
   const int64_t total_chunks = P.chunk_begin[P.n_units];
-  const int park = P.period > 0 ? (P.period > kWave ? kWave : P.period) : 32;
+  const int park = P.period > 0 ? (P.period > kWave ? kWave : P.period) : 24;
 
   // wave-uniform claim state.  Each unit has its own chunk cursor; a
   // wavefront starts on the unit that owns its share of all chunks and moves
@@ -443,6 +443,14 @@ transport_kernel(TransportParams P) {
     if (trav == 0 || __popcll(__ballot(phase == kParked || phase == kNeed)) >= park) {
       // ================= housekeeping for every parked lane =================
       if (COUNT && lane == 0) ev[kEv_Passes]++;
+      uint64_t clk = COUNT ? __builtin_amdgcn_s_memtime() : 0;
+      auto lap = [&](int slot) {
+        if (COUNT) {
+          const uint64_t now = __builtin_amdgcn_s_memtime();
+          if (lane == 0) ev[slot] += static_cast<uint32_t>(now - clk);
+          clk = now;
+        }
+      };
       if (VOL && phase == kParked && attempts > 0) {
         // ---- a volume-source point was localised: the region on the near
         // side of the first facet along the probe ray (the world if none)
@@ -580,6 +588,7 @@ transport_kernel(TransportParams P) {
         }
       }
 
+      lap(kEv_CycOutcome);
       // ---- new histories for lanes that need one (chunks of the wave's unit)
       const uint64_t need = __ballot(phase == kNeed);
       if (need) {
@@ -756,6 +765,7 @@ transport_kernel(TransportParams P) {
         }
       }
 
+      lap(kEv_CycRefill);
       if (VOL && phase == kSample) {
         // next try of a volume-source point
         ++attempts;
@@ -763,6 +773,7 @@ transport_kernel(TransportParams P) {
         phase = kSetup;
       }
       if (phase == kLaunch) begin_flight();
+      lap(kEv_CycLaunch);
 
       // ---- set up the next segment: attenuation, flight limit, ray
       if (VOL && phase == kSetup && attempts > 0) {
@@ -824,6 +835,7 @@ transport_kernel(TransportParams P) {
         }
         phase = node == kDone ? kParked : kTrav;
       }
+      lap(kEv_CycSetup);
       if (__ballot(phase != kNeed) == 0 && exhausted && pend < 0 && next_h >= end_h && q_n == 0)
         break;
     }
@@ -831,6 +843,7 @@ transport_kernel(TransportParams P) {
     // ================= one traversal step per traversing lane =================
     // the facets of a pending leaf first (one per step), else one node
     bool did_node = false, did_tri = false;
+    const uint64_t clk_trav = COUNT ? __builtin_amdgcn_s_memtime() : 0;
     if (phase == kTrav) {
       if (tri_next >= tri_end && node < 0 && node != kDone) {
         const int code = ~node;  // a leaf taken from the stack
@@ -902,7 +915,9 @@ transport_kernel(TransportParams P) {
     }
     if (COUNT) {
       const bool any_node = __ballot(did_node) != 0, any_tri = __ballot(did_tri) != 0;
+      const uint64_t now = __builtin_amdgcn_s_memtime();
       if (lane == 0) {
+        ev[kEv_CycTrav] += static_cast<uint32_t>(now - clk_trav);
         ev[kEv_Iters]++;
         if (any_node) ev[kEv_ItersNode]++;
         if (any_tri) ev[kEv_ItersTri]++;

@@ -75,7 +75,8 @@ class Counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "segments", "crossings", "node_visits", "tri_tests", "photo", "compton", "coherent",
         "rng_calls", "locates", "emissions", "plane_tests", "iterations", "iterations_node",
-        "iterations_facet", "passes")]
+        "iterations_facet", "passes", "cycles_outcome", "cycles_refill", "cycles_launch",
+        "cycles_setup", "cycles_traversal")]
 
 
 class MeshInfo(C.Structure):
