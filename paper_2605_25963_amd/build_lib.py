@@ -18,7 +18,7 @@ COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off: only scalar/float2 code, compiled plainly
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-Wno-unused-function",
+    "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-Wno-unused-function", "-pthread",
 ]
 
 
@@ -49,7 +49,7 @@ def build(verbose: bool = False, out: str | None = None) -> str:
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
     tmp = lib + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 #include "gadep.h"
@@ -37,6 +38,21 @@ inline D3 cross(D3 a, D3 b) {
 }
 inline double len(D3 a) { return sqrt(dot(a, a)); }
 inline double clamp01(double x) { return x < 0 ? 0 : (x > 1 ? 1 : x); }
+
+// Host threads for the heavy loops of the preparation (up to 16).
+int worker_count(int64_t items) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int64_t by_size = items / 4096 + 1;
+  return static_cast<int>(std::min<int64_t>(std::min<unsigned>(hw, 16u), by_size));
+}
+
+template <class F>
+void run_workers(int n, F&& work) {
+  std::vector<std::thread> th;
+  for (int w = 1; w < n; ++w) th.emplace_back(work, w);
+  work(0);
+  for (auto& t : th) t.join();
+}
 
 struct Box {
   float lo[3], hi[3];
@@ -626,6 +642,9 @@ class SplitBuilder {
     right.assign(s.begin() + mid, s.end());
   }
 
+  static constexpr int64_t kParallelRefs = 65536;  // subtrees this large are built
+  static constexpr int kParallelDepth = 4;          // by a thread of their own
+
   // splits refs (more than kLeafMax, or cheaper split) under node idx
   void build(int32_t idx, std::vector<Ref> refs, const Box& box, int depth, Box& box_out) {
     max_depth_ = std::max(max_depth_, depth);
@@ -634,8 +653,44 @@ class SplitBuilder {
     refs.clear();
     refs.shrink_to_fit();
     Box lb = bounds(left), rb = bounds(right);
-    const int32_t lc = child(std::move(left), lb, depth);
-    const int32_t rc = child(std::move(right), rb, depth);
+    int32_t lc, rc;
+    const int64_t nl = static_cast<int64_t>(left.size()), nr = static_cast<int64_t>(right.size());
+    if (nl + nr >= kParallelRefs && depth <= kParallelDepth) {
+      // the right subtree goes to a builder of its own, in another thread,
+      // with its share of the remaining reference budget (the split of work
+      // depends only on sizes, so the result does not depend on timing)
+      const int64_t spare = std::max<int64_t>(0, max_refs_ - n_refs_);
+      const int64_t spare_r = spare * nr / (nl + nr);
+      SplitBuilder sub(xyz_, tv_, nr + spare_r);
+      sub.root_area_ = root_area_;
+      sub.n_refs_ = nr;
+      n_refs_ -= nr;
+      max_refs_ -= nr + spare_r;
+      int32_t rc_sub = 0;
+      std::thread t([&]() { rc_sub = sub.child(std::move(right), rb, depth); });
+      lc = child(std::move(left), lb, depth);
+      t.join();
+      const int32_t node_off = static_cast<int32_t>(nodes_.size());
+      const int64_t id_off = static_cast<int64_t>(ids_.size());
+      auto relocate = [&](int32_t c) {
+        if (c >= 0) return c + node_off;
+        const int32_t x = ~c;
+        return leaf_code((x >> 3) + id_off, x & 7);
+      };
+      for (BvhNode nd : sub.nodes_) {
+        nd.child[0] = relocate(nd.child[0]);
+        nd.child[1] = relocate(nd.child[1]);
+        nodes_.push_back(nd);
+      }
+      ids_.insert(ids_.end(), sub.ids_.begin(), sub.ids_.end());
+      rc = relocate(rc_sub);
+      n_refs_ += sub.n_refs_;
+      max_refs_ += sub.max_refs_;
+      max_depth_ = std::max(max_depth_, sub.max_depth_);
+    } else {
+      lc = child(std::move(left), lb, depth);
+      rc = child(std::move(right), rb, depth);
+    }
     set_node(idx, lb, lc, rb, rc);
     box_out = lb;
     box_out.grow(rb);
@@ -1056,7 +1111,14 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
   // the smallest distance among them is reported (exact when below reach)
   const double reach = std::max(4.0 * min_gap, 1e-3);
   if (validate && ns > 1) {
-    for (int64_t f = 0; f < nt; ++f) {
+    // facets in contiguous ranges, one per worker thread; the first offending
+    // facet in index order is the one reported
+    const int nth = worker_count(nt);
+    std::vector<double> gap(nth, INFINITY);
+    std::vector<int64_t> bad_f(nth, -1);
+    std::vector<int32_t> bad_g(nth, -1);
+    auto work = [&](int w) {
+    for (int64_t f = nt * w / nth, fe = nt * (w + 1) / nth; f < fe; ++f) {
       Tri3 A = facet(static_cast<int32_t>(f));
       double blo[3], bhi[3];
       const D3 p[3] = {A.a, A.b, A.c};
@@ -1074,15 +1136,27 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
       q.box_all(blo, bhi, [&](int32_t g) {
         if (bad >= 0 || g <= f || shell[g] == shell[f]) return;
         double d = tri_tri_dist(A, facet(g));
-        gap_seen = std::min(gap_seen, d);
+        gap[w] = std::min(gap[w], d);
         if (d < min_gap) bad = g;
       });
-      if (bad >= 0)
+      if (bad >= 0) {
+        bad_f[w] = f;
+        bad_g[w] = bad;
+        return;
+      }
+    }
+    };
+    run_workers(nth, work);
+    for (int w = 0; w < nth; ++w) gap_seen = std::min(gap_seen, gap[w]);
+    for (int w = 0; w < nth; ++w)
+      if (bad_f[w] >= 0) {
+        const int64_t f = bad_f[w];
+        const int32_t bad = bad_g[w];
         return fail(err, GADEP_E_MESH_OVERLAP,
                     "mesh: shells of regions " + std::to_string(tri_region[f]) + " and " +
                         std::to_string(tri_region[bad]) + " intersect or are closer than the "
                         "minimum gap (facets " + std::to_string(f) + ", " + std::to_string(bad) + ")");
-    }
+      }
   }
 
   // ---- topology: region outside each shell by the parity rule
