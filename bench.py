@@ -58,8 +58,8 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNEL_SOURCES = ["paper_2605_25963_amd/csrc/transport.hip",
                   "paper_2605_25963_amd/csrc/device_common.h",
                   "paper_2605_25963_amd/csrc/gadep_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "a8c1d5bebf0308cb86fbdb484e1d58a9530a095c531a15ccff86179565aa35aa",
-                    "bytes_per_launch": 4.41e7}
+MEASURED_TRAFFIC = {"sources_sha256": "cbcb693df6cb21af19cfc74ba01c7e74fb22d889386fa552a0acbebd3c4543f3",
+                    "bytes_per_launch": 9.67e7}
 
 
 def measured_traffic():
