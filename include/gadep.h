@@ -288,6 +288,10 @@ typedef struct {
                              most 32); with a void world, a photon inside it then
                              searches a BVH over the other shells only and leaves
                              the outermost shell's own region through its planes */
+  int32_t region_root[GADEP_MAX_REGIONS + 1]; /* bvh_method 2 only (else -1): root
+                             node of region r's transport BVH (-1: no facets bound
+                             r); entry n_regions: the outer region's without the
+                             outermost shell, when n_exit_planes > 0 */
 } gadep_mesh_info;
 
 /* Validation + topology + BVH on the host, as gadep_load_mesh does, without
@@ -295,9 +299,10 @@ typedef struct {
  * facet, tri_shell[n_tri] (nullable) its shell index.  bvh_method selects the
  * BVH returned in nodes_out / tri_order and described by info: 0 = binned SAH
  * over every facet (the one used for parity counts and geometry queries),
- * 1 = object-median split, 2 = the transport BVH (binned SAH with spatial
- * splits, Stich et al. 2009, over every facet but those of the outermost
- * shell when n_exit_planes > 0; split_budget = extra slots allowed, as a
+ * 1 = object-median split, 2 = the transport BVHs (binned SAH with spatial
+ * splits, Stich et al. 2009), one per region over the facets that bound it
+ * (inside or outside that region), concatenated, with their roots in
+ * info->region_root (split_budget = extra slots each may add, as a
  * fraction of its facets).  nodes_out (nullable, [cap_nodes][16] 32-bit
  * words, the device layout: two child boxes as 12 floats, then two child
  * links as int32 -- >= 0 a node, < 0 a leaf ~(first_slot << 3 | count) --

@@ -235,7 +235,6 @@ __device__ __forceinline__ void load_tri(const TriRec* tris, int i, float4& a, f
   c = gload(p, 2);
 }
 
-constexpr int kDone = INT32_MIN;
 
 // Depth-first traversal of the two-child BVH.  The pending-node stack lives in
 // LDS, one column per thread (stack[i * stride]), so consecutive lanes touch

@@ -22,6 +22,9 @@ constexpr double kEnergyFix = 65536.0;      // keV
 constexpr double kScoreFix = 16777216.0;    // score
 constexpr double kScore2Fix = 65536.0;      // score^2
 
+// node link meaning "no node" (an empty stack, a region without facets)
+constexpr int32_t kDone = INT32_MIN;
+
 // Two children per node, each with its box; 64 bytes, read as four 16-byte loads.
 struct alignas(16) BvhNode {
   float lmin[3], lmax[3];
@@ -53,22 +56,23 @@ struct alignas(16) RegionRec {
 };
 
 // A scene's device tables.  Node 0 is the root of the plain BVH over every
-// facet (one record per facet), used for parity counts and geometry queries;
-// the transport BVH (spatial splits, root trans_root, its records after the
-// plain ones) follows.  When the outermost shell is convex with at most
-// kMaxExitPlanes distinct planes, the transport BVH leaves that shell out,
-// `planes` holds its planes (outward unit normal, offset n . x) and
-// trans_lo/trans_hi bound the transport BVH.  root_all is the BVH a segment
-// that may meet any facet searches: trans_root, or 0 when the transport BVH
-// leaves the outer shell out.
+// facet (one record per facet), used for parity counts, geometry queries and
+// the localisation of volume-source points (root_all); the transport BVHs
+// (spatial splits, one per region, their records after the plain ones)
+// follow.  A photon in region r searches roots[r], whose facets are exactly
+// those that bound r.  When the outermost shell is convex with at most
+// kMaxExitPlanes distinct planes, `planes` holds its planes (outward unit
+// normal, offset n . x), outer_root is the outer region's BVH without that
+// shell and trans_lo/trans_hi bound it.
 struct SceneRec {
   const BvhNode* nodes;
   const TriRec* tris;
   const float* planes;  // 4 floats per plane
+  const int32_t* roots;  // root node of each region's transport BVH (kDone: none)
   int32_t n_regions;
-  int32_t depth;        // deeper of the two BVHs
+  int32_t depth;        // deepest of the BVHs
   int32_t n_planes;     // 0: no exit planes
-  int32_t trans_root;
+  int32_t outer_root;   // outer region's transport BVH without the outermost shell
   int32_t root_all;
   int32_t outer_region;
   float trans_lo[3], trans_hi[3];
@@ -76,9 +80,8 @@ struct SceneRec {
 
 // UnitRec.flags
 constexpr int32_t kUnitExitEscapes = 1;  // entering the (void) world ends the history
-// With kUnitExitEscapes and exit planes: segments inside the outermost shell
-// search only the transport BVH (which leaves that shell out), and the outer
-// shell's own region is left through its planes.
+// With kUnitExitEscapes and exit planes: the outer shell's own region is left
+// through its planes, and its segments search outer_root (the other shells).
 constexpr int32_t kUnitExitPlanes = 2;
 
 enum SourceKind : int32_t { kPoint = 0, kBeam = 1, kCyl = 2 };
@@ -173,14 +176,20 @@ struct PreparedMesh {
   // planes, 4 floats each (outward unit normal, offset n . x).
   std::vector<float> planes;
   int32_t outer_region = 0;
-  // Transport BVH, built with spatial splits (a facet may have several
-  // records): over the facets of every shell but the outermost one when
-  // `planes` is set, else over every facet.  Child indices and record slots
-  // are local to it.
+  // Transport BVHs, built with spatial splits (a facet may have several
+  // records), one per region: region r's lists the facets that bound r (inside
+  // or outside region r), the only ones a photon in r can cross next.  When
+  // `planes` is set, one more (index n_regions) lists those of the outer
+  // region without the outermost shell, which the planes replace.  They are
+  // concatenated: trans_root[r] is the root node of BVH r (-1: r has no
+  // facets); child indices and record slots refer to the concatenation.
   std::vector<BvhNode> trans_nodes;
   std::vector<TriRec> trans_tris;
+  std::vector<int32_t> trans_root;
   int32_t trans_depth = 0;
-  double trans_sah = 0.0;
+  double trans_sah = 0.0;  // sum over the BVHs, each relative to its own root
+  // bounds of the outer region's BVH without the outermost shell (lo > hi:
+  // none, or no facets)
   float trans_lo[3] = {0, 0, 0}, trans_hi[3] = {0, 0, 0};
 };
 

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -1271,22 +1272,90 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
     }
   }
 
-  // ---- transport BVH (spatial splits)
+  // ---- transport BVHs (spatial splits), one per region over the facets
+  // that bound it, plus the outer region's without the outermost shell
   {
-    const bool skip_outer = !out.planes.empty();
-    std::vector<Ref> trefs;
-    for (int64_t f = 0; f < nt; ++f)
-      if (!(skip_outer && shell[f] == top)) trefs.push_back(refs_of[f]);
-    const int64_t budget = static_cast<int64_t>(split_budget * static_cast<double>(trefs.size()));
-    std::vector<int32_t> ids;
-    SplitBuilder sb(xyz, tv.data(), static_cast<int64_t>(trefs.size()) + budget);
-    sb.run(std::move(trefs), out.trans_nodes, ids, out.trans_depth, out.trans_sah);
-    out.trans_tris.resize(ids.size());
-    for (size_t i = 0; i < ids.size(); ++i) out.trans_tris[i].orig = ids[i];
-    const BvhNode& root = out.trans_nodes[0];
+    std::vector<int32_t> own(static_cast<size_t>(nt)), outside_of(static_cast<size_t>(nt));
+    for (int64_t f = 0; f < nt; ++f) {
+      own[f] = tri_region[f];
+      outside_of[f] = container[shell[f]];
+    }
+    const bool with_planes = !out.planes.empty();
+    const int32_t n_bvh = n_regions + (with_planes ? 1 : 0);
+    std::vector<std::vector<Ref>> sets(static_cast<size_t>(n_bvh));
+    for (int64_t f = 0; f < nt; ++f) {
+      sets[own[f]].push_back(refs_of[f]);
+      if (outside_of[f] != own[f]) sets[outside_of[f]].push_back(refs_of[f]);
+      if (with_planes && shell[f] != top &&
+          (own[f] == out.outer_region || outside_of[f] == out.outer_region))
+        sets[n_regions].push_back(refs_of[f]);
+    }
+    struct Built {
+      std::vector<BvhNode> nodes;
+      std::vector<int32_t> ids;
+      int32_t depth = 0;
+      double sah = 0.0;
+    };
+    std::vector<Built> built(static_cast<size_t>(n_bvh));
+    // largest sets first, one at a time per worker thread
+    std::vector<int32_t> todo;
+    for (int32_t b = 0; b < n_bvh; ++b)
+      if (!sets[b].empty()) todo.push_back(b);
+    std::sort(todo.begin(), todo.end(), [&](int32_t x, int32_t y) {
+      return sets[x].size() > sets[y].size() || (sets[x].size() == sets[y].size() && x < y);
+    });
+    std::atomic<size_t> next{0};
+    auto work = [&](int) {
+      for (size_t k = next++; k < todo.size(); k = next++) {
+        const int32_t b = todo[k];
+        const int64_t n = static_cast<int64_t>(sets[b].size());
+        const int64_t budget = static_cast<int64_t>(split_budget * static_cast<double>(n));
+        SplitBuilder sb(xyz, tv.data(), n + budget);
+        Built& o = built[b];
+        sb.run(std::move(sets[b]), o.nodes, o.ids, o.depth, o.sah);
+      }
+    };
+    run_workers(std::min<int>(worker_count(nt), static_cast<int>(todo.size())), work);
+    out.trans_nodes.clear();
+    out.trans_tris.clear();
+    out.trans_root.assign(static_cast<size_t>(n_bvh), -1);
+    out.trans_depth = 0;
+    out.trans_sah = 0.0;
+    for (int32_t b = 0; b < n_bvh; ++b) {
+      const Built& o = built[b];
+      if (o.nodes.empty()) continue;
+      const int32_t node_off = static_cast<int32_t>(out.trans_nodes.size());
+      const int64_t slot_off = static_cast<int64_t>(out.trans_tris.size());
+      out.trans_root[b] = node_off;
+      for (BvhNode nd : o.nodes) {
+        for (int c = 0; c < 2; ++c) {
+          if (nd.child[c] >= 0) {
+            nd.child[c] += node_off;
+          } else {
+            const int32_t x = ~nd.child[c];
+            nd.child[c] = leaf_code((x >> 3) + slot_off, x & 7);
+          }
+        }
+        out.trans_nodes.push_back(nd);
+      }
+      for (int32_t id : o.ids) {
+        TriRec r{};
+        r.orig = id;
+        out.trans_tris.push_back(r);
+      }
+      out.trans_depth = std::max(out.trans_depth, o.depth);
+      out.trans_sah += o.sah;
+    }
     for (int a = 0; a < 3; ++a) {
-      out.trans_lo[a] = std::min(root.lmin[a], root.rmin[a]);
-      out.trans_hi[a] = std::max(root.lmax[a], root.rmax[a]);
+      out.trans_lo[a] = INFINITY;
+      out.trans_hi[a] = -INFINITY;
+    }
+    if (with_planes && out.trans_root[n_regions] >= 0) {
+      const BvhNode& root = out.trans_nodes[out.trans_root[n_regions]];
+      for (int a = 0; a < 3; ++a) {
+        out.trans_lo[a] = std::min(root.lmin[a], root.rmin[a]);
+        out.trans_hi[a] = std::max(root.lmax[a], root.rmax[a]);
+      }
     }
   }
 

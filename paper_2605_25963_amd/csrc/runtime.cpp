@@ -47,13 +47,13 @@ struct Scene {
   int64_t n_nodes = 0;
   bool convex_exit = false;
   int32_t n_planes = 0;
-  int32_t trans_root = 0;
-  int32_t root_all = 0;
+  int32_t outer_root = kDone;
   int32_t outer_region = 0;
   float trans_lo[3] = {0, 0, 0}, trans_hi[3] = {0, 0, 0};
   void* d_nodes = nullptr;
   void* d_tris = nullptr;
   void* d_planes = nullptr;
+  void* d_roots = nullptr;
 };
 
 void fill_scene_rec(const Scene& sc, SceneRec& sr) {
@@ -62,9 +62,10 @@ void fill_scene_rec(const Scene& sc, SceneRec& sr) {
   sr.planes = static_cast<const float*>(sc.d_planes);
   sr.n_regions = sc.n_regions;
   sr.depth = sc.depth;
+  sr.roots = static_cast<const int32_t*>(sc.d_roots);
   sr.n_planes = sc.n_planes;
-  sr.trans_root = sc.trans_root;
-  sr.root_all = sc.root_all;
+  sr.outer_root = sc.outer_root;
+  sr.root_all = 0;
   sr.outer_region = sc.outer_region;
   for (int a = 0; a < 3; ++a) {
     sr.trans_lo[a] = sc.trans_lo[a];
@@ -648,6 +649,7 @@ void gadep_destroy(gadep_ctx* ctx) {
       if (sc->d_nodes) (void)hipFree(sc->d_nodes);
       if (sc->d_tris) (void)hipFree(sc->d_tris);
       if (sc->d_planes) (void)hipFree(sc->d_planes);
+      if (sc->d_roots) (void)hipFree(sc->d_roots);
     }
   for (DevBuf* b : {&ctx->xs, &ctx->units, &ctx->chunk_begin, &ctx->scene_tab, &ctx->sources,
                     &ctx->lines, &ctx->regions, &ctx->tally, &ctx->spectra, &ctx->cursor})
@@ -756,9 +758,10 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   if (sc.d_nodes) (void)hipFree(sc.d_nodes);
   if (sc.d_tris) (void)hipFree(sc.d_tris);
   if (sc.d_planes) (void)hipFree(sc.d_planes);
-  sc.d_nodes = sc.d_tris = sc.d_planes = nullptr;
+  if (sc.d_roots) (void)hipFree(sc.d_roots);
+  sc.d_nodes = sc.d_tris = sc.d_planes = sc.d_roots = nullptr;
   sc.loaded = false;
-  // the transport BVH follows the plain one, its indices shifted to match
+  // the transport BVHs follow the plain one, their indices shifted to match
   std::vector<BvhNode> nodes = pm.nodes;
   std::vector<TriRec> tris = pm.tris;
   const int32_t n_plain = static_cast<int32_t>(pm.nodes.size());
@@ -774,6 +777,9 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
     nodes.push_back(nd);
   }
   tris.insert(tris.end(), pm.trans_tris.begin(), pm.trans_tris.end());
+  std::vector<int32_t> roots(static_cast<size_t>(n_regions), kDone);
+  for (int32_t r = 0; r < n_regions; ++r)
+    if (pm.trans_root[r] >= 0) roots[r] = pm.trans_root[r] + n_plain;
   const int32_t n_planes = static_cast<int32_t>(pm.planes.size() / 4);
   HIP_TRY(hipMalloc(&sc.d_nodes, nodes.size() * sizeof(BvhNode)), "alloc nodes");
   HIP_TRY(hipMalloc(&sc.d_tris, tris.size() * sizeof(TriRec)), "alloc facets");
@@ -781,6 +787,9 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
           "upload nodes");
   HIP_TRY(hipMemcpy(sc.d_tris, tris.data(), tris.size() * sizeof(TriRec), hipMemcpyHostToDevice),
           "upload facets");
+  HIP_TRY(hipMalloc(&sc.d_roots, roots.size() * sizeof(int32_t)), "alloc roots");
+  HIP_TRY(hipMemcpy(sc.d_roots, roots.data(), roots.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+          "upload roots");
   if (n_planes > 0) {
     HIP_TRY(hipMalloc(&sc.d_planes, pm.planes.size() * sizeof(float)), "alloc planes");
     HIP_TRY(hipMemcpy(sc.d_planes, pm.planes.data(), pm.planes.size() * sizeof(float),
@@ -788,8 +797,8 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
             "upload planes");
   }
   sc.n_planes = n_planes;
-  sc.trans_root = n_plain;
-  sc.root_all = n_planes > 0 ? 0 : n_plain;
+  sc.outer_root = n_planes > 0 && pm.trans_root[n_regions] >= 0 ? pm.trans_root[n_regions] + n_plain
+                                                                : kDone;
   sc.outer_region = pm.outer_region;
   for (int a = 0; a < 3; ++a) {
     sc.trans_lo[a] = pm.trans_lo[a];
@@ -1090,6 +1099,9 @@ gadep_status gadep_mesh_prepare(const float* xyz, int64_t nv, const int32_t* tri
     info->min_gap_mm = pm.min_gap;
     info->convex_exit = pm.convex_exit ? 1 : 0;
     info->n_exit_planes = static_cast<int32_t>(pm.planes.size() / 4);
+    for (int32_t r = 0; r <= GADEP_MAX_REGIONS; ++r)
+      info->region_root[r] = trans && r < static_cast<int32_t>(pm.trans_root.size()) ? pm.trans_root[r]
+                                                                                     : -1;
   }
   if (tri_outside) memcpy(tri_outside, pm.outside.data(), pm.outside.size() * 4);
   if (tri_shell) memcpy(tri_shell, pm.shell.data(), pm.shell.size() * 4);

@@ -802,36 +802,36 @@ transport_kernel(TransportParams P) {
         tbest = mu > 0.0f ? tau / mu : INFINITY;
         ray = make_ray(px, py, pz, dx, dy, dz);
         trej = INFINITY;
-        node = S.root_all;
         sp = 0;
         tri_next = tri_end = 0;
         best_id = -1;
-        if ((U.flags & kUnitExitPlanes) && region != 0) {
-          // Inside the convex outermost shell: only the other shells can be
-          // met before its boundary, so the search runs on their BVH; from the
-          // outer shell's own region, the boundary itself is the nearest of
-          // the planes the ray runs towards.
-          node = S.trans_root;
-          if (region == S.outer_region) {
-            float te = INFINITY;
-            for (int i = 0; i < S.n_planes; ++i) {
-              const float4 pl = gload(reinterpret_cast<const float4*>(S.planes), i);
-              const float dn = pl.x * dx + pl.y * dy + pl.z * dz;
-              const float num = pl.w - (pl.x * px + pl.y * py + pl.z * pz);
-              if (dn > 0.0f) te = fminf(te, num * __builtin_amdgcn_rcpf(dn));
-            }
-            if (COUNT) ev[kEv_PlaneTests] += S.n_planes;
-            te = fmaxf(te, 0.0f);
-            if (te <= tbest) {
-              tbest = te;
-              best_id = kExitPlane;
-              best_reg = 0;
-            }
+        // the BVH of the facets that bound this region: no other facet can
+        // be crossed next
+        if ((U.flags & kUnitExitPlanes) && region == S.outer_region) {
+          // the outer shell's own region: its boundary is the nearest of the
+          // planes the ray runs towards, and only the shells inside it are
+          // searched
+          float te = INFINITY;
+          for (int i = 0; i < S.n_planes; ++i) {
+            const float4 pl = gload(reinterpret_cast<const float4*>(S.planes), i);
+            const float dn = pl.x * dx + pl.y * dy + pl.z * dz;
+            const float num = pl.w - (pl.x * px + pl.y * py + pl.z * pz);
+            if (dn > 0.0f) te = fminf(te, num * __builtin_amdgcn_rcpf(dn));
           }
+          if (COUNT) ev[kEv_PlaneTests] += S.n_planes;
+          te = fmaxf(te, 0.0f);
+          if (te <= tbest) {
+            tbest = te;
+            best_id = kExitPlane;
+            best_reg = 0;
+          }
+          node = S.outer_root;
           if (!(S.trans_lo[0] <= S.trans_hi[0]) ||
               slab(ray, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0], S.trans_hi[1],
                    S.trans_hi[2], tbest) == INFINITY)
             node = kDone;  // no inner shell ahead within the flight
+        } else {
+          node = gload(S.roots, region);
         }
         phase = node == kDone ? kParked : kTrav;
       }

@@ -83,7 +83,7 @@ class MeshInfo(C.Structure):
     _fields_ = [("n_shells", C.c_int32), ("genus_max", C.c_int32), ("n_nodes", C.c_int64),
                 ("depth", C.c_int32), ("sah_cost", C.c_double), ("n_slots", C.c_int64),
                 ("min_gap_mm", C.c_double), ("convex_exit", C.c_int32),
-                ("n_exit_planes", C.c_int32)]
+                ("n_exit_planes", C.c_int32), ("region_root", C.c_int32 * (MAX_REGIONS + 1))]
 
 
 EXPORTS = [
@@ -443,7 +443,8 @@ def mesh_prepare(xyz, tri, tri_region, n_regions, min_gap_mm=1e-4, validate=True
     res = dict(outside=outside, shell=shell, order=order, n_shells=info.n_shells,
                genus_max=info.genus_max, n_nodes=info.n_nodes, depth=info.depth,
                sah_cost=info.sah_cost, n_slots=info.n_slots, min_gap_mm=info.min_gap_mm,
-               convex_exit=bool(info.convex_exit), n_exit_planes=info.n_exit_planes)
+               convex_exit=bool(info.convex_exit), n_exit_planes=info.n_exit_planes,
+               region_root=np.array(info.region_root, np.int64))
     if nodes is not None:
         res["nodes"] = nodes
     return res

@@ -247,64 +247,80 @@ def test_exit_planes_of_a_lone_box(G):
     # a single box: planes found, and the BVH of the other shells is empty
     b = mg.SceneBuilder()
     b.add("a", "Ge", 5.32, mg.box((-1, -2, -3), (4, 5, 6)))
-    r = prep(G, b.build())
+    r = prep(G, b.build(), bvh_method=2)
     assert r["convex_exit"] and r["n_exit_planes"] == 6
+    assert r["region_root"][2] == -1 and r["region_root"][0] >= 0 and r["region_root"][1] >= 0
 
 
 @pytest.mark.parametrize("cfg", ["c1", "c2"])
-def test_transport_bvh_covers_every_facet(G, cfg):
-    # Spatial splits clip facet references to boxes; every point of every facet
-    # searched by transport must still lie in the box of a leaf that lists it.
+def test_transport_bvhs_cover_the_facets_of_each_region(G, cfg):
+    # One BVH per region, over exactly the facets that bound it (plus, with
+    # exit planes, the outer region's without the outermost shell).  Spatial
+    # splits clip facet references to boxes; every point of every listed facet
+    # must still lie in the box of a leaf of that BVH that lists it.
     w = C.c1_bare() if cfg == "c1" else C.c2_hpge(n_seg=64, n_phi=8, n_histories=1)
     sc = w.scene
+    nr = sc.n_regions
     r = prep(G, sc, bvh_method=2, want_nodes=True, split_budget=1.0)
     plain = prep(G, sc)
-    nodes, ids = r["nodes"], r["order"]
+    nodes, ids, roots = r["nodes"], r["order"], r["region_root"]
     assert r["n_slots"] == len(ids) >= 1
     boxes = nodes[:, :12].copy().view(np.float32).reshape(-1, 2, 2, 3)
-    # leaf ranges partition the slots; child boxes nest
-    seen = np.zeros(len(ids), int)
-    leaf_box = {}
-    for i, nd in enumerate(nodes):
-        for k, c in enumerate((nd[12], nd[13])):
-            if c < 0:
-                x = ~int(c)
-                f, n = x >> 3, x & 7
-                assert n <= 4
-                seen[f:f + n] += 1
-                for j in range(f, f + n):
-                    leaf_box[j] = boxes[i, k]
-            else:
-                lo, hi = boxes[i, k]
-                clo = boxes[int(c), :, 0].min(0)
-                chi = boxes[int(c), :, 1].max(0)
-                ok = np.isfinite(clo) & np.isfinite(chi)
-                assert (lo[ok] <= clo[ok]).all() and (hi[ok] >= chi[ok]).all()
-    assert (seen == 1).all()
-    # which facets: all, or all but the outer shell's when exit planes exist
+    inside = np.asarray(sc.tri_region)
+    outside = plain["outside"]
     shell = plain["shell"]
+    wants = [set(np.nonzero((inside == reg) | (outside == reg))[0]) for reg in range(nr)]
     if r["n_exit_planes"] > 0:
         outer = shell[sc.shells[0][1]]
-        want = set(np.nonzero(shell != outer)[0])
+        outer_region = inside[sc.shells[0][1]]
+        wants.append(set(np.nonzero(((inside == outer_region) | (outside == outer_region)) &
+                                    (shell != outer))[0]))
     else:
-        want = set(range(len(sc.tri)))
-    assert set(ids.tolist()) == want
-    slots_of = {}
-    for j, f in enumerate(ids):
-        slots_of.setdefault(int(f), []).append(j)
-    rng = np.random.default_rng(7)
+        assert roots[nr] == -1
+    seen = np.zeros(len(ids), int)
     V = sc.xyz.astype(np.float64)
-    for f in sorted(want)[:: max(1, len(want) // 600)]:
-        a, b, c = V[sc.tri[f]]
-        u = rng.random((24, 2))
-        u[u.sum(1) > 1] = 1 - u[u.sum(1) > 1]
-        pts = np.vstack([a, b, c, (a + b) / 2, (b + c) / 2, (a + c) / 2,
-                         a + u[:, :1] * (b - a) + u[:, 1:] * (c - a)])
-        for q in pts:
-            tol = 1e-6 * (1 + np.abs(q))
-            assert any(((leaf_box[j][0] - tol <= q) & (q <= leaf_box[j][1] + tol)).all()
-                       for j in slots_of[f]), (f, q)
+    rng = np.random.default_rng(7)
+    for b, want in enumerate(wants):
+        if not want:
+            assert roots[b] == -1
+            continue
+        # nodes reachable from this root; child boxes nest
+        leaf_box, todo = {}, [int(roots[b])]
+        while todo:
+            i = todo.pop()
+            for k, c in enumerate((nodes[i, 12], nodes[i, 13])):
+                if c < 0:
+                    x = ~int(c)
+                    f, n = x >> 3, x & 7
+                    assert n <= 4
+                    seen[f:f + n] += 1
+                    for j in range(f, f + n):
+                        leaf_box[j] = boxes[i, k]
+                else:
+                    lo, hi = boxes[i, k]
+                    clo = boxes[int(c), :, 0].min(0)
+                    chi = boxes[int(c), :, 1].max(0)
+                    ok = np.isfinite(clo) & np.isfinite(chi)
+                    assert (lo[ok] <= clo[ok]).all() and (hi[ok] >= chi[ok]).all()
+                    todo.append(int(c))
+        listed = {int(ids[j]) for j in leaf_box}
+        assert listed == want, b
+        slots_of = {}
+        for j in leaf_box:
+            slots_of.setdefault(int(ids[j]), []).append(j)
+        for f in sorted(want)[:: max(1, len(want) // 300)]:
+            a, bb, c = V[sc.tri[f]]
+            u = rng.random((24, 2))
+            u[u.sum(1) > 1] = 1 - u[u.sum(1) > 1]
+            pts = np.vstack([a, bb, c, (a + bb) / 2, (bb + c) / 2, (a + c) / 2,
+                             a + u[:, :1] * (bb - a) + u[:, 1:] * (c - a)])
+            for q in pts:
+                tol = 1e-6 * (1 + np.abs(q))
+                assert any(((leaf_box[j][0] - tol <= q) & (q <= leaf_box[j][1] + tol)).all()
+                           for j in slots_of[f]), (b, f, q)
+    # leaf ranges of all the BVHs together partition the slots
+    assert (seen == 1).all()
     assert r["sah_cost"] > 0
     r0 = prep(G, sc, bvh_method=2, split_budget=0.0)
-    assert r0["n_slots"] == len(want)  # no spatial splits: one slot per facet
+    assert r0["n_slots"] == sum(len(x) for x in wants)  # no spatial splits: one slot per listing
     assert r["sah_cost"] <= r0["sah_cost"] * 1.0001
