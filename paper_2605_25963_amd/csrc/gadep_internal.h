@@ -34,7 +34,9 @@ struct alignas(16) BvhNode {
 };
 static_assert(sizeof(BvhNode) == 64, "node layout");
 
-// Facet record in BVH leaf order; 48 bytes, read as three 16-byte loads.
+// Facet record; 48 bytes, read as three 16-byte loads.  Leaves list slots,
+// and each slot names a facet, so a facet that several BVHs (or several
+// leaves of one) list is stored once.
 struct alignas(16) TriRec {
   float v0[3], v1[3], v2[3];
   uint32_t regions;  // inside (low 16 bits) | outside (high 16 bits)
@@ -66,7 +68,8 @@ struct alignas(16) RegionRec {
 // shell and trans_lo/trans_hi bound it.
 struct SceneRec {
   const BvhNode* nodes;
-  const TriRec* tris;
+  const TriRec* tris;     // one record per facet, in the caller's order
+  const int32_t* slots;   // facet of each leaf slot, for every BVH
   const float* planes;  // 4 floats per plane
   const int32_t* roots;  // root node of each region's transport BVH (kDone: none)
   int32_t n_regions;

@@ -329,19 +329,22 @@ class SplitBuilder {
       : xyz_(xyz), tv_(tv), max_refs_(max_refs) {}
 
   // refs: one whole-facet reference per facet.  ids receives the facet of
-  // each reference slot in leaf order.
+  // each reference slot in leaf order.  With a budget for extra references
+  // (max_refs above the facet count), long, thin facets are cut into pieces
+  // first (these do not count against the budget), then spatial splits use it.
   void run(std::vector<Ref> refs, std::vector<BvhNode>& nodes, std::vector<int32_t>& ids,
            int32_t& depth, double& sah) {
     nodes_.clear();
     ids_.clear();
     max_depth_ = 1;
+    if (max_refs_ > static_cast<int64_t>(refs.size())) presplit(refs);
     n_refs_ = static_cast<int64_t>(refs.size());
     Box all;
     all.reset();
     for (const Ref& r : refs) all.grow(r.box);
     root_area_ = all.area();
     nodes_.emplace_back();
-    if (static_cast<int>(refs.size()) <= kLeafMax) {
+    if (static_cast<int>(refs.size()) <= kSplitLeafMax) {
       Box empty;
       empty.reset();
       const int32_t code = emit_leaf(refs);
@@ -369,6 +372,66 @@ class SplitBuilder {
   static constexpr double kCostTrav = 1.2;
   static constexpr double kCostIsect = 1.0;
   static constexpr double kMinOverlap = 1e-5;  // spatial splits only where children overlap
+  static constexpr int kSplitLeafMax = kLeafMax;
+  // early split clipping of long, thin facets (Ernst and Greiner 2007): a
+  // reference is cut in half across its longest box side until that side is
+  // at most kPieceWidths facet widths (twice the area over the longest edge)
+  // or the facet has kMaxPieces pieces.  The fan caps of the detector shells
+  // are the case in point: their wedges' boxes overlap near the centre, and a
+  // segment that starts on one of them would otherwise visit most of them.
+  static constexpr double kPieceWidths = 8.0;
+  static constexpr int kMaxPieces = 32;
+
+  void presplit(std::vector<Ref>& refs) {
+    std::vector<Ref> out;
+    out.reserve(refs.size());
+    std::vector<Ref> st;
+    for (const Ref& r : refs) {
+      const float* v[3] = {xyz_ + 3 * tv_[3 * r.id], xyz_ + 3 * tv_[3 * r.id + 1],
+                           xyz_ + 3 * tv_[3 * r.id + 2]};
+      double e[3][3];
+      double lmax = 0;
+      for (int i = 0; i < 3; ++i) {
+        for (int k = 0; k < 3; ++k) e[i][k] = static_cast<double>(v[(i + 1) % 3][k]) - v[i][k];
+        lmax = std::max(lmax, sqrt(e[i][0] * e[i][0] + e[i][1] * e[i][1] + e[i][2] * e[i][2]));
+      }
+      const double cx = e[0][1] * e[1][2] - e[0][2] * e[1][1];
+      const double cy = e[0][2] * e[1][0] - e[0][0] * e[1][2];
+      const double cz = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+      const double cap = kPieceWidths * sqrt(cx * cx + cy * cy + cz * cz) / std::max(lmax, 1e-30);
+      st.assign(1, r);
+      int pieces = 1;
+      while (!st.empty()) {
+        Ref p = st.back();
+        st.pop_back();
+        int ax = 0;
+        for (int a = 1; a < 3; ++a)
+          if (p.box.hi[a] - p.box.lo[a] > p.box.hi[ax] - p.box.lo[ax]) ax = a;
+        Box L, R;
+        if (p.box.hi[ax] - p.box.lo[ax] > cap && pieces < kMaxPieces)
+          split_ref(p, ax, 0.5f * (p.box.lo[ax] + p.box.hi[ax]), L, R);
+        else
+          L.reset();
+        if (!valid(L) || !valid(R)) {
+          out.push_back(p);
+          continue;
+        }
+        Ref a = p, b = p;
+        a.box = L;
+        b.box = R;
+        for (int k = 0; k < 3; ++k) {
+          a.c[k] = 0.5f * (L.lo[k] + L.hi[k]);
+          b.c[k] = 0.5f * (R.lo[k] + R.hi[k]);
+        }
+        st.push_back(a);
+        st.push_back(b);
+        ++pieces;
+      }
+    }
+    // the pieces do not use up the spatial-split budget
+    max_refs_ += static_cast<int64_t>(out.size()) - static_cast<int64_t>(refs.size());
+    refs.swap(out);
+  }
 
   struct Plan {
     double cost = INFINITY;
@@ -393,9 +456,11 @@ class SplitBuilder {
   }
 
   int32_t emit_leaf(const std::vector<Ref>& refs) {
+    // a facet cut into pieces is listed once per leaf
     const int64_t first = static_cast<int64_t>(ids_.size());
-    for (const Ref& r : refs) ids_.push_back(r.id);
-    return leaf_code(first, static_cast<int32_t>(refs.size()));
+    for (const Ref& r : refs)
+      if (std::find(ids_.begin() + first, ids_.end(), r.id) == ids_.end()) ids_.push_back(r.id);
+    return leaf_code(first, static_cast<int32_t>(static_cast<int64_t>(ids_.size()) - first));
   }
 
   static Box bounds(const std::vector<Ref>& refs) {
@@ -646,7 +711,7 @@ class SplitBuilder {
   static constexpr int64_t kParallelRefs = 65536;  // subtrees this large are built
   static constexpr int kParallelDepth = 4;          // by a thread of their own
 
-  // splits refs (more than kLeafMax, or cheaper split) under node idx
+  // splits refs (more than kSplitLeafMax, or cheaper split) under node idx
   void build(int32_t idx, std::vector<Ref> refs, const Box& box, int depth, Box& box_out) {
     max_depth_ = std::max(max_depth_, depth);
     std::vector<Ref> left, right;
@@ -722,7 +787,7 @@ class SplitBuilder {
 
   int32_t child(std::vector<Ref> refs, const Box& box, int depth) {
     const int64_t n = static_cast<int64_t>(refs.size());
-    if (n <= kLeafMax) {
+    if (n <= kSplitLeafMax) {
       bool leaf = n < 2 || depth >= kMaxDepth - 1;
       if (!leaf) {
         Plan p;

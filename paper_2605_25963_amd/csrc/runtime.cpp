@@ -54,11 +54,13 @@ struct Scene {
   void* d_tris = nullptr;
   void* d_planes = nullptr;
   void* d_roots = nullptr;
+  void* d_slots = nullptr;
 };
 
 void fill_scene_rec(const Scene& sc, SceneRec& sr) {
   sr.nodes = static_cast<const BvhNode*>(sc.d_nodes);
   sr.tris = static_cast<const TriRec*>(sc.d_tris);
+  sr.slots = static_cast<const int32_t*>(sc.d_slots);
   sr.planes = static_cast<const float*>(sc.d_planes);
   sr.n_regions = sc.n_regions;
   sr.depth = sc.depth;
@@ -650,6 +652,7 @@ void gadep_destroy(gadep_ctx* ctx) {
       if (sc->d_tris) (void)hipFree(sc->d_tris);
       if (sc->d_planes) (void)hipFree(sc->d_planes);
       if (sc->d_roots) (void)hipFree(sc->d_roots);
+      if (sc->d_slots) (void)hipFree(sc->d_slots);
     }
   for (DevBuf* b : {&ctx->xs, &ctx->units, &ctx->chunk_begin, &ctx->scene_tab, &ctx->sources,
                     &ctx->lines, &ctx->regions, &ctx->tally, &ctx->spectra, &ctx->cursor})
@@ -759,11 +762,11 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   if (sc.d_tris) (void)hipFree(sc.d_tris);
   if (sc.d_planes) (void)hipFree(sc.d_planes);
   if (sc.d_roots) (void)hipFree(sc.d_roots);
-  sc.d_nodes = sc.d_tris = sc.d_planes = sc.d_roots = nullptr;
+  if (sc.d_slots) (void)hipFree(sc.d_slots);
+  sc.d_nodes = sc.d_tris = sc.d_planes = sc.d_roots = sc.d_slots = nullptr;
   sc.loaded = false;
   // the transport BVHs follow the plain one, their indices shifted to match
   std::vector<BvhNode> nodes = pm.nodes;
-  std::vector<TriRec> tris = pm.tris;
   const int32_t n_plain = static_cast<int32_t>(pm.nodes.size());
   for (BvhNode nd : pm.trans_nodes) {
     for (int c = 0; c < 2; ++c) {
@@ -776,7 +779,11 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
     }
     nodes.push_back(nd);
   }
-  tris.insert(tris.end(), pm.trans_tris.begin(), pm.trans_tris.end());
+  // one record per facet (caller order); the slots of every BVH name them
+  std::vector<TriRec> tris(static_cast<size_t>(nt));
+  for (const TriRec& r : pm.tris) tris[r.orig] = r;
+  std::vector<int32_t> slots(pm.order);
+  for (const TriRec& r : pm.trans_tris) slots.push_back(r.orig);
   std::vector<int32_t> roots(static_cast<size_t>(n_regions), kDone);
   for (int32_t r = 0; r < n_regions; ++r)
     if (pm.trans_root[r] >= 0) roots[r] = pm.trans_root[r] + n_plain;
@@ -787,6 +794,9 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
           "upload nodes");
   HIP_TRY(hipMemcpy(sc.d_tris, tris.data(), tris.size() * sizeof(TriRec), hipMemcpyHostToDevice),
           "upload facets");
+  HIP_TRY(hipMalloc(&sc.d_slots, slots.size() * sizeof(int32_t)), "alloc slots");
+  HIP_TRY(hipMemcpy(sc.d_slots, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+          "upload slots");
   HIP_TRY(hipMalloc(&sc.d_roots, roots.size() * sizeof(int32_t)), "alloc roots");
   HIP_TRY(hipMemcpy(sc.d_roots, roots.data(), roots.size() * sizeof(int32_t), hipMemcpyHostToDevice),
           "upload roots");

@@ -54,7 +54,7 @@ __device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, fl
       if (COUNT) ntri++;
       if (slot == exclude) continue;
       float4 a, b, c;
-      load_tri(tris, slot, a, b, c);
+      load_tri(tris, gload(sc.slots, slot), a, b, c);
       float t;
       bool enter;
       if (wt_test(r, ox, oy, oz, dx, dy, dz, a, b, c, tcur, t, enter) == kWtMiss) continue;
@@ -109,7 +109,7 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
                                                                         float tcur) {
       for (int j = 0; j < count; ++j) {
         float4 a, b, c;
-        load_tri(tris, first + j, a, b, c);
+        load_tri(tris, gload(sc.slots, first + j), a, b, c);
         float t;
         bool enter;
         const int w = wt_test(r, px, py, pz, qx, qy, qz, a, b, c, INFINITY, t, enter);
@@ -129,7 +129,7 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
     v = traverse(sc.nodes, r, tm, stack, stride, sc.depth, [&](int first, int count, float tcur) {
       for (int j = 0; j < count; ++j) {
         float4 a, b, c;
-        load_tri(tris, first + j, a, b, c);
+        load_tri(tris, gload(sc.slots, first + j), a, b, c);
         const int reg = static_cast<int>(__float_as_uint(c.y) & 0xFFFFu);
         if (!((parity >> reg) & 1ull)) continue;
         float t;
@@ -858,7 +858,7 @@ transport_kernel(TransportParams P) {
         if (COUNT) ev[kEv_TriTests]++;
         did_tri = true;
         float4 a, b, c;
-        load_tri(S.tris, slot, a, b, c);
+        load_tri(S.tris, gload(S.slots, slot), a, b, c);
         const int id = __float_as_int(c.z);
         float t;
         bool enter;
@@ -969,7 +969,7 @@ __global__ void raycast_kernel(SceneRec sc, const float* o, const float* d, cons
   if (closest_hit<false>(sc, r, ox, oy, oz, dx, dy, dz, INFINITY, -1, cur, lstack + threadIdx.x,
                          blockDim.x, h, glitch, a, b)) {
     t[i] = h.t;
-    tri[i] = gload(sc.tris, h.slot).orig;
+    tri[i] = gload(sc.slots, h.slot);
     region_after[i] = h.region_after;
   } else {
     t[i] = INFINITY;

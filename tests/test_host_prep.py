@@ -322,5 +322,6 @@ def test_transport_bvhs_cover_the_facets_of_each_region(G, cfg):
     assert (seen == 1).all()
     assert r["sah_cost"] > 0
     r0 = prep(G, sc, bvh_method=2, split_budget=0.0)
-    assert r0["n_slots"] == sum(len(x) for x in wants)  # no spatial splits: one slot per listing
-    assert r["sah_cost"] <= r0["sah_cost"] * 1.0001
+    assert r0["n_slots"] == sum(len(x) for x in wants)  # no splits: one slot per listing
+    # with a budget, the long wedges of the fan caps are cut into pieces
+    assert r["n_slots"] > r0["n_slots"]
