@@ -240,6 +240,10 @@ typedef struct {
    * segments, handing out new histories (with screening), drawing emission
    * directions, segment set-up, traversal steps */
   uint64_t cycles_outcome, cycles_refill, cycles_launch, cycles_setup, cycles_traversal;
+  /* histories that first-flight screening settled with a ray set-up and one
+   * box test: their flight certainly outlasts the outermost shell, so neither
+   * the attenuation nor the exit planes are evaluated (no segment is counted) */
+  uint64_t box_tests;
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 

@@ -115,9 +115,11 @@ __device__ __forceinline__ float pick3(float x, float y, float z, int k) {
   return k == 0 ? x : (k == 1 ? y : z);
 }
 
+// reciprocal of a direction component for the slab tests (hardware rcp, 1
+// ulp; the slab test widens the exit distance by more than that)
 __device__ __forceinline__ float safe_rcp(float d) {
   const float tiny = 7.8886091e-31f;  // 2^-100
-  return 1.0f / (fabsf(d) > tiny ? d : copysignf(tiny, d));
+  return __builtin_amdgcn_rcpf(fabsf(d) > tiny ? d : copysignf(tiny, d));
 }
 
 __device__ __forceinline__ Ray make_ray(float ox, float oy, float oz, float dx, float dy,

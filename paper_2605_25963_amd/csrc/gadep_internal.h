@@ -79,6 +79,7 @@ struct SceneRec {
   int32_t root_all;
   int32_t outer_region;
   float trans_lo[3], trans_hi[3];
+  float outer_lo[3], outer_hi[3];  // box of the outermost shell (with exit planes)
 };
 
 // UnitRec.flags
@@ -118,7 +119,7 @@ enum TallySlot : int {
   kT_Hist = 0, kT_Absorbed, kT_Fep, kT_CollEscape, kT_Lost, kT_Killed, kT_Glitch, kT_SrcFail,
   kT_SpecOvf, kT_EdepAct, kT_EdepTot, kT_EEsc, kT_ESrc,
   kT_Score = 16, kT_FepScore = 24, kT_FepScore2 = 32,
-  kT_Ev = 40,  // event counters, 10 slots
+  kT_Ev = 40,  // event counters, up to 24 slots
   kT_Slots = 64
 };
 enum EventSlot : int {
@@ -128,7 +129,9 @@ enum EventSlot : int {
   // of the batched per-segment work
   kEv_Iters, kEv_ItersNode, kEv_ItersTri, kEv_Passes,
   // wavefront-level shader-clock cycles per section of the loop
-  kEv_CycOutcome, kEv_CycRefill, kEv_CycLaunch, kEv_CycSetup, kEv_CycTrav, kEv_N
+  kEv_CycOutcome, kEv_CycRefill, kEv_CycLaunch, kEv_CycSetup, kEv_CycTrav,
+  // screened histories settled by one box test (no attenuation, no exit planes)
+  kEv_BoxTests, kEv_N
 };
 static_assert(kT_Ev + kEv_N <= kT_Slots, "tally slots");
 
@@ -179,6 +182,7 @@ struct PreparedMesh {
   // planes, 4 floats each (outward unit normal, offset n . x).
   std::vector<float> planes;
   int32_t outer_region = 0;
+  float outer_lo[3] = {0, 0, 0}, outer_hi[3] = {0, 0, 0};  // box of that shell
   // Transport BVHs, built with spatial splits (a facet may have several
   // records), one per region: region r's lists the facets that bound r (inside
   // or outside region r), the only ones a photon in r can cross next.  When

@@ -1328,6 +1328,20 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
     }
     if (few) {
       out.outer_region = tri_region[shell_first[top]];
+      for (int a = 0; a < 3; ++a) {
+        out.outer_lo[a] = INFINITY;
+        out.outer_hi[a] = -INFINITY;
+      }
+      for (int64_t f = 0; f < nt; ++f) {
+        if (shell[f] != top) continue;
+        for (int k = 0; k < 3; ++k) {
+          const float* p = xyz + 3 * tv[3 * f + k];
+          for (int a = 0; a < 3; ++a) {
+            out.outer_lo[a] = std::min(out.outer_lo[a], p[a]);
+            out.outer_hi[a] = std::max(out.outer_hi[a], p[a]);
+          }
+        }
+      }
       for (size_t k = 0; k < pn.size(); ++k) {
         out.planes.push_back(static_cast<float>(pn[k].x));
         out.planes.push_back(static_cast<float>(pn[k].y));

@@ -50,6 +50,7 @@ struct Scene {
   int32_t outer_root = kDone;
   int32_t outer_region = 0;
   float trans_lo[3] = {0, 0, 0}, trans_hi[3] = {0, 0, 0};
+  float outer_lo[3] = {0, 0, 0}, outer_hi[3] = {0, 0, 0};
   void* d_nodes = nullptr;
   void* d_tris = nullptr;
   void* d_planes = nullptr;
@@ -72,6 +73,8 @@ void fill_scene_rec(const Scene& sc, SceneRec& sr) {
   for (int a = 0; a < 3; ++a) {
     sr.trans_lo[a] = sc.trans_lo[a];
     sr.trans_hi[a] = sc.trans_hi[a];
+    sr.outer_lo[a] = sc.outer_lo[a];
+    sr.outer_hi[a] = sc.outer_hi[a];
   }
 }
 
@@ -580,6 +583,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     cnt.cycles_launch += ev[kEv_CycLaunch];
     cnt.cycles_setup += ev[kEv_CycSetup];
     cnt.cycles_traversal += ev[kEv_CycTrav];
+    cnt.box_tests += ev[kEv_BoxTests];
   }
   if (ctx->counters) {
     ctx->last_counters = cnt;
@@ -813,6 +817,8 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   for (int a = 0; a < 3; ++a) {
     sc.trans_lo[a] = pm.trans_lo[a];
     sc.trans_hi[a] = pm.trans_hi[a];
+    sc.outer_lo[a] = pm.outer_lo[a];
+    sc.outer_hi[a] = pm.outer_hi[a];
   }
   sc.regions.assign(regions, regions + n_regions);
   sc.n_regions = n_regions;

@@ -307,6 +307,10 @@ transport_kernel(TransportParams P) {
   // first-flight screening (see the refill below) and its queue
   bool screen = false;
   int q_head = 0, q_n = 0;
+  // a screened history whose first optical depth reaches scr_tau cannot end
+  // its first flight before leaving the outermost shell (INFINITY: always
+  // evaluate the flight; see the unit change below)
+  float scr_tau = INFINITY, scr_far = INFINITY;
 
   // lane state: photon
   int phase = kNeed;
@@ -625,6 +629,23 @@ transport_kernel(TransportParams P) {
               const RegionRec ro = gload(P.regions, U.region_off + S.outer_region);
               screen = P.screen && (U.flags & kUnitExitPlanes) && Src.kind != kCyl &&
                        U.src_region == S.outer_region && (!GRAD || (ro.bits & 0xFF) == 0xFF);
+              scr_tau = scr_far = INFINITY;
+              if (screen && Src.n_lines == 0) {
+                // No point of the outermost shell is farther from the source
+                // than the farthest corner of its box, so a flight longer
+                // than that (plus a margin far above rounding) always ends
+                // at the shell: tau >= mu * far.
+                float d2 = 0.0f;
+                for (int a = 0; a < 3; ++a) {
+                  const float e = fmaxf(fabsf(S.outer_lo[a] - Src.pos[a]), fabsf(S.outer_hi[a] - Src.pos[a]));
+                  d2 = fmaf(e, e, d2);
+                }
+                scr_far = sqrtf(d2) * 1.0001f;
+                float m_p, m_c, m_h;
+                xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, ro,
+                      xs_index(U.energy, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
+                scr_tau = (m_p + m_c + m_h) * scr_far * 1.0001f;
+              }
             }
             next_h = pend_h0;
             end_h = pend_h1;
@@ -670,22 +691,32 @@ transport_kernel(TransportParams P) {
               u0 = u2;
             }
             const float tau0 = -__logf(u0);
-            const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
-            float m_p, m_c, m_h;
-            xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr,
-                  xs_index(e, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
-            const float m = m_p + m_c + m_h;
-            const float tfl = m > 0.0f ? tau0 / m : INFINITY;
             const float ox = Src.pos[0], oy = Src.pos[1], oz = Src.pos[2];
-            float te = INFINITY;
-            for (int i = 0; i < S.n_planes; ++i) {
-              const float4 pl = gload(reinterpret_cast<const float4*>(S.planes), i);
-              const float dn = pl.x * qx + pl.y * qy + pl.z * qz;
-              const float num = pl.w - (pl.x * ox + pl.y * oy + pl.z * oz);
-              if (dn > 0.0f) te = fminf(te, num * __builtin_amdgcn_rcpf(dn));
+            bool escapes;
+            float te;
+            const bool settled = tau0 >= scr_tau;
+            if (settled) {
+              // the flight outlasts the shell (the common case): no need for
+              // the attenuation or the exit distance, only for the box test
+              escapes = true;
+              te = scr_far;
+            } else {
+              const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
+              float m_p, m_c, m_h;
+              xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr,
+                    xs_index(e, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
+              const float m = m_p + m_c + m_h;
+              const float tfl = m > 0.0f ? tau0 / m : INFINITY;
+              te = INFINITY;
+              for (int i = 0; i < S.n_planes; ++i) {
+                const float4 pl = gload(reinterpret_cast<const float4*>(S.planes), i);
+                const float dn = pl.x * qx + pl.y * qy + pl.z * qz;
+                const float num = pl.w - (pl.x * ox + pl.y * oy + pl.z * oz);
+                if (dn > 0.0f) te = fminf(te, num * __builtin_amdgcn_rcpf(dn));
+              }
+              te = fmaxf(te, 0.0f);
+              escapes = te <= tfl;
             }
-            te = fmaxf(te, 0.0f);
-            bool escapes = te <= tfl;
             if (escapes && S.trans_lo[0] <= S.trans_hi[0]) {
               const Ray r0 = make_ray(ox, oy, oz, qx, qy, qz);
               escapes = slab(r0, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0],
@@ -697,10 +728,14 @@ transport_kernel(TransportParams P) {
               acc_eunc += fx_kev(e);
               if (COUNT) {
                 ev[kEv_Emissions]++;
-                ev[kEv_Segments]++;
                 ev[kEv_Crossings]++;
                 ev[kEv_Rng]++;
-                ev[kEv_PlaneTests] += S.n_planes;
+                if (settled) {
+                  ev[kEv_BoxTests]++;
+                } else {
+                  ev[kEv_Segments]++;
+                  ev[kEv_PlaneTests] += S.n_planes;
+                }
               }
             } else {
               survivor = true;

@@ -76,7 +76,7 @@ class Counters(C.Structure):
         "segments", "crossings", "node_visits", "tri_tests", "photo", "compton", "coherent",
         "rng_calls", "locates", "emissions", "plane_tests", "iterations", "iterations_node",
         "iterations_facet", "passes", "cycles_outcome", "cycles_refill", "cycles_launch",
-        "cycles_setup", "cycles_traversal")]
+        "cycles_setup", "cycles_traversal", "box_tests")]
 
 
 class MeshInfo(C.Structure):
