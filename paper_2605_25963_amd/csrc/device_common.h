@@ -30,8 +30,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
                                               uint32_t& c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
-    const uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
+    // full 64-bit products: one v_mad_u64_u32 each instead of a mul_lo / mul_hi pair
+    const uint64_t p0 = static_cast<uint64_t>(c0) * 0xD2511F53u;
+    const uint64_t p1 = static_cast<uint64_t>(c2) * 0xCD9E8D57u;
+    const uint32_t lo0 = static_cast<uint32_t>(p0), hi0 = static_cast<uint32_t>(p0 >> 32);
+    const uint32_t lo1 = static_cast<uint32_t>(p1), hi1 = static_cast<uint32_t>(p1 >> 32);
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -69,6 +72,15 @@ __device__ __noinline__ uint4 philox_block(uint32_t draw, uint32_t h_lo, uint32_
   uint32_t c0 = draw, c1 = h_lo, c2 = h_hi, c3 = stream;
   philox4x32_10(c0, c1, c2, c3, k0, k1);
   return make_uint4(c0, c1, c2, c3);
+}
+
+// Hardware square root and natural logarithm (v_sqrt_f32, v_log_f32; about
+// 1 ulp).  The sampling code takes them on positive, normal arguments only
+// (uniforms in (0, 1), energies in keV, 1 - cos^2), so the IEEE wrappers'
+// range reduction for denormals is not needed.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_log(float x) {
+  return __builtin_amdgcn_logf(x) * 0.693147180559945f;
 }
 
 // Uniform in (0, 1) from one 32-bit output: 23 random bits, (k + 1/2) 2^-23,

@@ -159,7 +159,7 @@ struct Xs {
 };
 
 __device__ __forceinline__ Xs xs_index(float E, float ln_e0, float inv_dlne, int n_e) {
-  const float x = (__logf(E) - ln_e0) * inv_dlne;
+  const float x = (hw_log(E) - ln_e0) * inv_dlne;
   int k = static_cast<int>(floorf(x));
   k = k < 0 ? 0 : (k > n_e - 2 ? n_e - 2 : k);
   float w = x - static_cast<float>(k);
@@ -187,7 +187,7 @@ __device__ __forceinline__ void xs_mu(const float4* __restrict__ xs, int n_e, co
 // 2017).  sin/cos of 2 pi u come from the hardware sine, which takes
 // revolutions.
 __device__ __forceinline__ void turn(float& dx, float& dy, float& dz, float ct, float u) {
-  const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+  const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
   const float cp = __builtin_amdgcn_cosf(u), sp = __builtin_amdgcn_sinf(u);
   const float s = copysignf(1.0f, dz);
   const float a = -1.0f / (s + dz);
@@ -408,7 +408,7 @@ transport_kernel(TransportParams P) {
   // a point of a volume source, uniform in its cylindrical annulus
   auto sample_point = [&]() {
     const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
-    const float rr2 = sqrtf(fmaf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
+    const float rr2 = hw_sqrt(fmaf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), r2hi - r2lo, r2lo));
     const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
     px = Src.pos[0] + rr2 * __builtin_amdgcn_cosf(uphi);
     py = Src.pos[1] + rr2 * __builtin_amdgcn_sinf(uphi);
@@ -424,13 +424,13 @@ transport_kernel(TransportParams P) {
       dz = Src.dir[2];
     } else {
       const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
-      const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+      const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
       const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
       dx = st * __builtin_amdgcn_cosf(uphi);
       dy = st * __builtin_amdgcn_sinf(uphi);
       dz = ct;
     }
-    tau = -__logf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
+    tau = -hw_log(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
     ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
     edep_act = edep_tot = 0.0f;
     clean = true;
@@ -531,7 +531,7 @@ transport_kernel(TransportParams P) {
               const float k = E * (1.0f / kMec2);
               const float e0 = 1.0f / fmaf(2.0f, k, 1.0f);
               const float e02 = e0 * e0;
-              const float a1 = -__logf(e0);
+              const float a1 = -hw_log(e0);
               const float a2 = 0.5f * (1.0f - e02);
               float eps = 1.0f, t = 0.0f;
               for (int it = 0; it < 64; ++it) {
@@ -544,7 +544,7 @@ transport_kernel(TransportParams P) {
                   eps2 = eps * eps;
                 } else {
                   eps2 = fmaf(1.0f - e02, u2, e02);
-                  eps = sqrtf(eps2);
+                  eps = hw_sqrt(eps2);
                 }
                 t = (1.0f - eps) / (k * eps);
                 const float sin2 = t * (2.0f - t);
@@ -580,7 +580,7 @@ transport_kernel(TransportParams P) {
               const float ct = copysignf(c - 1.0f / c, a);
               turn(dx, dy, dz, fminf(1.0f, fmaxf(-1.0f, ct)), rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
             }
-            if (!absorbed) tau = -__logf(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
+            if (!absorbed) tau = -hw_log(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
           }
         } else {
           // vacuum and no facet ahead: escape from the world, otherwise lost
@@ -684,13 +684,13 @@ transport_kernel(TransportParams P) {
             float qx = Src.dir[0], qy = Src.dir[1], qz = Src.dir[2];
             if (Src.kind != kBeam) {
               const float ct = fmaf(2.0f, u0, -1.0f);
-              const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+              const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
               qx = st * __builtin_amdgcn_cosf(u1);
               qy = st * __builtin_amdgcn_sinf(u1);
               qz = ct;
               u0 = u2;
             }
-            const float tau0 = -__logf(u0);
+            const float tau0 = -hw_log(u0);
             const float ox = Src.pos[0], oy = Src.pos[1], oz = Src.pos[2];
             bool escapes;
             float te;
