@@ -86,7 +86,9 @@ __device__ __forceinline__ float hw_log(float x) {
 // Uniform in (0, 1) from one 32-bit output: 23 random bits, (k + 1/2) 2^-23,
 // exact in FP32 so that neither 0 nor 1 can occur.
 __device__ __forceinline__ float unit_float(uint32_t x) {
-  return (static_cast<float>(x >> 9) + 0.5f) * (1.0f / 8388608.0f);
+  // 1 + k 2^-23 (k = the top 23 bits) minus (1 - 2^-24): exact (Sterbenz),
+  // and equal to (k + 1/2) 2^-23
+  return __uint_as_float(0x3F800000u | (x >> 9)) - 0.99999994f;
 }
 
 // The next uniform of a history's stream.
@@ -154,9 +156,11 @@ __device__ __forceinline__ Ray make_ray(float ox, float oy, float oz, float dx, 
     ky = t;
   }
   r.k = kx | (ky << 2) | (kz << 4);
-  r.sx = pick3(dx, dy, dz, kx) / dkz;
-  r.sy = pick3(dx, dy, dz, ky) / dkz;
-  r.sz = 1.0f / dkz;
+  // shear constants: any rounding is the same for every facet the ray meets,
+  // which is all the watertight test needs
+  r.sz = __builtin_amdgcn_rcpf(dkz);
+  r.sx = pick3(dx, dy, dz, kx) * r.sz;
+  r.sy = pick3(dx, dy, dz, ky) * r.sz;
   return r;
 }
 
