@@ -325,19 +325,20 @@ double nodes_sah(const std::vector<BvhNode>& nodes, double root_area) {
 
 class SplitBuilder {
  public:
-  SplitBuilder(const float* xyz, const int32_t* tv, int64_t max_refs)
-      : xyz_(xyz), tv_(tv), max_refs_(max_refs) {}
+  SplitBuilder(const float* xyz, const int32_t* tv, int64_t max_refs, bool cut_pieces = false)
+      : xyz_(xyz), tv_(tv), max_refs_(max_refs), cut_pieces_(cut_pieces) {}
 
   // refs: one whole-facet reference per facet.  ids receives the facet of
   // each reference slot in leaf order.  With a budget for extra references
   // (max_refs above the facet count), long, thin facets are cut into pieces
-  // first (these do not count against the budget), then spatial splits use it.
+  // first when cut_pieces is set (these do not count against the budget),
+  // then spatial splits use it.
   void run(std::vector<Ref> refs, std::vector<BvhNode>& nodes, std::vector<int32_t>& ids,
            int32_t& depth, double& sah) {
     nodes_.clear();
     ids_.clear();
     max_depth_ = 1;
-    if (max_refs_ > static_cast<int64_t>(refs.size())) presplit(refs);
+    if (cut_pieces_ && max_refs_ > static_cast<int64_t>(refs.size())) presplit(refs);
     n_refs_ = static_cast<int64_t>(refs.size());
     Box all;
     all.reset();
@@ -363,6 +364,7 @@ class SplitBuilder {
   const float* xyz_;
   const int32_t* tv_;
   int64_t max_refs_;
+  bool cut_pieces_ = false;
   int64_t n_refs_ = 0;
   double root_area_ = 0.0;
   std::vector<BvhNode> nodes_;
@@ -381,6 +383,14 @@ class SplitBuilder {
   // segment that starts on one of them would otherwise visit most of them.
   static constexpr double kPieceWidths = 8.0;
   static constexpr int kMaxPieces = 32;
+
+ public:
+  // Meshes below this many facets keep whole facets: their BVHs stay small
+  // enough to live in cache, and several of them (one per job of a batch)
+  // may share it, so pieces would cost more in footprint than they save.
+  static constexpr int64_t kPieceMinFacets = 4096;
+
+ private:
 
   void presplit(std::vector<Ref>& refs) {
     std::vector<Ref> out;
@@ -1389,7 +1399,7 @@ int prepare_mesh(const float* xyz, int64_t nv, const int32_t* tri, const int32_t
         const int32_t b = todo[k];
         const int64_t n = static_cast<int64_t>(sets[b].size());
         const int64_t budget = static_cast<int64_t>(split_budget * static_cast<double>(n));
-        SplitBuilder sb(xyz, tv.data(), n + budget);
+        SplitBuilder sb(xyz, tv.data(), n + budget, nt >= SplitBuilder::kPieceMinFacets);
         Built& o = built[b];
         sb.run(std::move(sets[b]), o.nodes, o.ids, o.depth, o.sah);
       }

@@ -812,7 +812,10 @@ transport_kernel(TransportParams P) {
 
       // ---- set up the next segment: attenuation, flight limit, ray
       if (VOL && phase == kSetup && attempts > 0) {
-        // probe ray of a volume-source point: nearest facet of any region
+        // probe ray of a volume-source point.  The point lies in the source
+        // region exactly when the nearest facet along the ray that bounds
+        // that region is met from its inside, so only the region's own BVH
+        // is searched.
         if (COUNT) ev[kEv_Locates]++;
         dx = kLocateDir[0];
         dy = kLocateDir[1];
@@ -823,11 +826,11 @@ transport_kernel(TransportParams P) {
         mu = 0.0f;
         tbest = INFINITY;
         trej = INFINITY;
-        node = S.root_all;
+        node = gload(S.roots, Src.region);
         sp = 0;
         tri_next = tri_end = 0;
         best_id = -1;
-        phase = kTrav;
+        phase = node == kDone ? kParked : kTrav;
       } else if (phase == kSetup) {
         if (COUNT) ev[kEv_Segments]++;
         const RegionRec rr = gload(P.regions, U.region_off + region);

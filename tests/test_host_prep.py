@@ -323,5 +323,9 @@ def test_transport_bvhs_cover_the_facets_of_each_region(G, cfg):
     assert r["sah_cost"] > 0
     r0 = prep(G, sc, bvh_method=2, split_budget=0.0)
     assert r0["n_slots"] == sum(len(x) for x in wants)  # no splits: one slot per listing
-    # with a budget, the long wedges of the fan caps are cut into pieces
-    assert r["n_slots"] > r0["n_slots"]
+    # with a budget, meshes of 4096 facets or more have the long wedges of
+    # their fan caps cut into pieces; smaller ones keep whole facets
+    if len(sc.tri) >= 4096:
+        assert r["n_slots"] > 2 * r0["n_slots"]
+    else:
+        assert r0["n_slots"] <= r["n_slots"] <= 2 * r0["n_slots"]
