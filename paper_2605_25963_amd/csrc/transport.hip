@@ -245,6 +245,7 @@ __device__ __forceinline__ unsigned long long fx(double v, double scale) {
 enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3, kSample = 4, kLaunch = 5 };
 constexpr int kMaxEmitAttempts = 1000;  // volume-source rejection tries per history
 constexpr int kQueue = 128;             // screened histories a wavefront can hold
+constexpr int kXcds = 8;                // accelerator dies (XCDs) of an MI355X, one L2 each
 // probe direction for localising volume-source points (generic: no axis or
 // facet plane of the synthetic meshes is parallel to it)
 __constant__ float kLocateDir[3] = {0.4830462f, 0.3714437f, 0.7929236f};
@@ -283,8 +284,16 @@ transport_kernel(TransportParams P) {
   // drain (let its open histories finish) for a change of unit.
   int claim_unit = 0;
   {
+    // Workgroups are dealt to the chip's kXcds dies in turn (block b runs on
+    // die b % kXcds), and each die has its own L2: number the blocks die by
+    // die, so that the waves of one die start on neighbouring units (for a
+    // batch of jobs, the same few scenes) and keep that part of the geometry
+    // in their L2.
+    int64_t blk = blockIdx.x;
+    if (gridDim.x % kXcds == 0)
+      blk = static_cast<int64_t>(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
     const int64_t n_w = static_cast<int64_t>(gridDim.x) * nwaves;
-    const int64_t gw = static_cast<int64_t>(blockIdx.x) * nwaves + wave;
+    const int64_t gw = blk * nwaves + wave;
     const int64_t x = (gw * total_chunks + total_chunks / 2) / n_w;
     int lo = 0, hi = P.n_units - 1;  // unit u: chunk_begin[u] <= x < chunk_begin[u+1]
     while (lo < hi) {
