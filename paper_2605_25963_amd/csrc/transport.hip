@@ -168,9 +168,13 @@ __device__ __forceinline__ Xs xs_index(float E, float ln_e0, float inv_dlne, int
 }
 
 // partial linear attenuation [1/mm] of a region: log-log interpolation of
-// each partial, mu_i = mult * exp(lerp(ln(mu/rho)_i))
+// each partial, mu_i = mult * exp(lerp(ln(mu/rho)_i)).  The products are kept
+// out of contraction, so that mu = mp + mc + mh comes out the same wherever it
+// is formed (screening decides a flight with a per-unit value that must equal
+// the set-up's).
 __device__ __forceinline__ void xs_mu(const float4* __restrict__ xs, int n_e, const RegionRec& rr,
                                       Xs ix, float& mp, float& mc, float& mh) {
+#pragma clang fp contract(off)
   if (rr.mult > 0.0f) {
     const float4 lo = gload(xs, rr.material * n_e + ix.k);
     const float4 hi = gload(xs, rr.material * n_e + ix.k + 1);
@@ -312,6 +316,7 @@ transport_kernel(TransportParams P) {
   bool exhausted = false;
   UnitRec U{};
   SceneRec S{};
+  int sp_cap = 0;  // stack capacity of this scene's BVHs, times the stride
   SourceRec Src{};
   // first-flight screening (see the refill below) and its queue
   bool screen = false;
@@ -320,6 +325,7 @@ transport_kernel(TransportParams P) {
   // its first flight before leaving the outermost shell (INFINITY: always
   // evaluate the flight; see the unit change below)
   float scr_tau = INFINITY, scr_far = INFINITY;
+  float scr_m = -1.0f;  // attenuation of the outer region at the unit's energy (< 0: per history)
 
   // lane state: photon
   int phase = kNeed;
@@ -334,6 +340,8 @@ transport_kernel(TransportParams P) {
   float mu = 0, mp = 0, mc = 0;
   Ray ray{};
   float tbest = 0, trej = INFINITY;
+  // sp: depth of the LDS stack times the column stride (its entries are
+  // stack[k * stride]), so pushes and pops need no multiply
   int node = kDone, sp = 0, tri_next = 0, tri_end = 0, best_id = -1, best_reg = 0;
   // per-lane accumulators of the per-history (frequent) quantities
   unsigned long long acc_hist = 0, acc_eunc = 0, acc_esrc = 0;
@@ -634,11 +642,13 @@ transport_kernel(TransportParams P) {
               cur = pend;
               U = P.units[cur];
               S = P.scenes[U.scene];
+              sp_cap = S.depth * stride;
               Src = P.sources[U.source];
               const RegionRec ro = gload(P.regions, U.region_off + S.outer_region);
               screen = P.screen && (U.flags & kUnitExitPlanes) && Src.kind != kCyl &&
                        U.src_region == S.outer_region && (!GRAD || (ro.bits & 0xFF) == 0xFF);
               scr_tau = scr_far = INFINITY;
+              scr_m = -1.0f;
               if (screen && Src.n_lines == 0) {
                 // No point of the outermost shell is farther from the source
                 // than the farthest corner of its box, so a flight longer
@@ -653,7 +663,8 @@ transport_kernel(TransportParams P) {
                 float m_p, m_c, m_h;
                 xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, ro,
                       xs_index(U.energy, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
-                scr_tau = (m_p + m_c + m_h) * scr_far * 1.0001f;
+                scr_m = m_p + m_c + m_h;
+                scr_tau = scr_m * scr_far * 1.0001f;
               }
             }
             next_h = pend_h0;
@@ -710,11 +721,14 @@ transport_kernel(TransportParams P) {
               escapes = true;
               te = scr_far;
             } else {
-              const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
-              float m_p, m_c, m_h;
-              xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr,
-                    xs_index(e, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
-              const float m = m_p + m_c + m_h;
+              float m = scr_m;  // the unit's, for a fixed energy
+              if (m < 0.0f) {
+                const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
+                float m_p, m_c, m_h;
+                xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr,
+                      xs_index(e, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
+                m = m_p + m_c + m_h;
+              }
               const float tfl = m > 0.0f ? tau0 / m : INFINITY;
               te = INFINITY;
               for (int i = 0; i < S.n_planes; ++i) {
@@ -896,7 +910,7 @@ transport_kernel(TransportParams P) {
         const int code = ~node;  // a leaf taken from the stack
         tri_next = code >> 3;
         tri_end = tri_next + (code & 7);
-        node = sp > 0 ? stack[(--sp) * stride] : kDone;
+        node = sp > 0 ? stack[sp -= stride] : kDone;
       }
       if (tri_next < tri_end) {
         // one facet test, with the region-consistency filter; the facet just
@@ -943,17 +957,17 @@ transport_kernel(TransportParams P) {
           near = n3.y;
         }
         if (near == kDone) {
-          node = sp > 0 ? stack[(--sp) * stride] : kDone;
+          node = sp > 0 ? stack[sp -= stride] : kDone;
         } else if (near < 0) {
           // nearest child is a leaf: test its facets next, then go to `far`
           const int code = ~near;
           tri_next = code >> 3;
           tri_end = tri_next + (code & 7);
-          node = far != kDone ? far : (sp > 0 ? stack[(--sp) * stride] : kDone);
+          node = far != kDone ? far : (sp > 0 ? stack[sp -= stride] : kDone);
         } else {
-          if (far != kDone && sp < S.depth) {
-            stack[sp * stride] = far;
-            ++sp;
+          if (far != kDone && sp < sp_cap) {
+            stack[sp] = far;
+            sp += stride;
           }
           node = near;
         }
