@@ -131,15 +131,19 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz_mm
 
 /* Partial mass attenuation coefficients mu/rho [cm^2/g] of `material` on the
  * grid ln E_k = lnE0_keV + k dlnE, k = 0..n_E-1 (the same grid for every
- * material).  Interpolation is linear in ln E of ln(mu/rho), per partial.
- * Any partial may be NULL (absent); a present partial must be all-positive or
- * all-zero.  The lowest grid energy is the photon cut-off: below it the
+ * material): photoelectric, incoherent (Klein-Nishina), coherent (Thomson) and
+ * pair production (Sec. 2.4.1).  Interpolation is linear in ln E of ln(mu/rho),
+ * per partial.  Any partial may be NULL (absent); a present partial must be
+ * all-positive or all-zero.  The pair partial counts only above 2 m_e c^2 =
+ * 1021.998 keV (zero at and below it, whatever the table holds there); a pair
+ * event deposits E - 2 m_e c^2 where it happens and starts two 511 keV photons
+ * back to back along a random axis, which the history then follows in turn.  The lowest grid energy is the photon cut-off: below it the
  * remaining energy is deposited locally.  Source energies must lie on the
  * grid and below 65536 keV (energy tallies count 2^-16 keV units).
  * Errors: GADEP_E_ARG, GADEP_E_XS. */
 gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0_keV, double dlnE,
                           int32_t n_E, const float* mu_rho_photo, const float* mu_rho_compton,
-                          const float* mu_rho_coherent);
+                          const float* mu_rho_coherent, const float* mu_rho_pair);
 
 /* Density scales s_g used by gadep_run (default 1).  scales[n_scales]. */
 gadep_status gadep_set_scales(gadep_ctx* ctx, const float* scales, int32_t n_scales);
@@ -244,6 +248,7 @@ typedef struct {
    * box test: their flight certainly outlasts the outermost shell, so neither
    * the attenuation nor the exit planes are evaluated (no segment is counted) */
   uint64_t box_tests;
+  uint64_t pair;        /* pair-production events */
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 

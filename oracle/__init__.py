@@ -32,7 +32,7 @@ class Tally(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "n_histories", "n_absorbed", "n_fep", "n_uncollided", "n_escape", "n_lost", "n_killed",
         "n_source_fail", "n_balance_fail", "n_segments", "n_crossings", "n_photo", "n_compton",
-        "n_coherent", "spectrum_overflow")] + [
+        "n_coherent", "n_pair", "spectrum_overflow")] + [
         ("edep_active", C.c_double), ("edep_total", C.c_double), ("e_escape", C.c_double),
         ("sum_score", C.c_double * MAX_GROUPS), ("sum_fep_score", C.c_double * MAX_GROUPS),
         ("sum_fep_score2", C.c_double * MAX_GROUPS)]
@@ -61,7 +61,8 @@ def lib():
                                        C.POINTER(C.c_int32), C.c_int64, C.c_int32, C.c_int32]
         L.orc_scene_destroy.argtypes = [C.c_void_p]
         L.orc_set_region.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32]
-        L.orc_set_xs.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32, dp, dp, dp]
+        L.orc_set_xs.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32, dp, dp, dp,
+                                 dp]
         L.orc_locate.restype = C.c_int32
         L.orc_locate.argtypes = [C.c_void_p, dp]
         L.orc_closest_hit.restype = C.c_int32
@@ -168,10 +169,10 @@ class Scene:
         if rc:
             raise ValueError(f"oracle: set_region({r}) -> {rc}")
 
-    def set_xs(self, material, grid, photo, compton, coherent):
+    def set_xs(self, material, grid, photo, compton, coherent=None, pair=None):
         lnE0, dlnE, n = grid
         arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
-                for a in (photo, compton, coherent)]
+                for a in (photo, compton, coherent, pair)]
         ptrs = [None if a is None else _dp(a) for a in arrs]
         rc = lib().orc_set_xs(self.h, material, lnE0, dlnE, n, *ptrs)
         if rc:
@@ -190,7 +191,8 @@ class Scene:
         return (t.value, f.value) if ok else (np.inf, -1)
 
     def mu(self, region, E, scales=None):
-        out = np.zeros(3)
+        """(photo, Compton, coherent, pair) linear attenuation [1/mm]."""
+        out = np.zeros(4)
         sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float64)
         lib().orc_mu(self.h, region, E, None if sc is None else _dp(sc),
                      0 if sc is None else len(sc), _dp(out))
@@ -243,6 +245,6 @@ def scene_from_workload(w, use_bvh=True):
     mat, rho, grp, act = w.region_arrays()
     for r in range(sc.n_regions):
         s.set_region(r, int(mat[r]), float(rho[r]), int(grp[r]), bool(act[r]))
-    for m, (pe, c, coh) in w.tables.items():
-        s.set_xs(m, w.grid, pe, c, coh)
+    for m, tab in w.tables.items():
+        s.set_xs(m, w.grid, *tab)
     return s

@@ -97,8 +97,9 @@ typedef struct {
 } onode;
 
 typedef struct {
-  int present[3];
-  double* lnval[3]; /* ln(mu/rho) per grid point, per partial */
+  int present[4];
+  double* lnval[4]; /* ln(mu/rho) per grid point, per partial (photo, Compton,
+                       coherent, pair production) */
 } omat;
 
 struct orc_scene {
@@ -223,7 +224,7 @@ void orc_scene_destroy(orc_scene* s) {
   free(s->nodes);
   free(s->order);
   for (int m = 0; m < MAX_MATERIALS; ++m)
-    for (int i = 0; i < 3; ++i) free(s->mats[m].lnval[i]);
+    for (int i = 0; i < 4; ++i) free(s->mats[m].lnval[i]);
   free(s);
 }
 
@@ -239,15 +240,16 @@ int32_t orc_set_region(orc_scene* s, int32_t r, int32_t material, double density
 }
 
 int32_t orc_set_xs(orc_scene* s, int32_t m, double lnE0, double dlnE, int32_t n,
-                   const double* photo, const double* compton, const double* coherent) {
+                   const double* photo, const double* compton, const double* coherent,
+                   const double* pair) {
   if (m < 0 || m >= MAX_MATERIALS || n < 2 || !(dlnE > 0)) return -1;
   if (s->grid_set && (lnE0 != s->lnE0 || dlnE != s->dlnE || n != s->nE)) return -2;
   s->grid_set = 1;
   s->lnE0 = lnE0;
   s->dlnE = dlnE;
   s->nE = n;
-  const double* src[3] = {photo, compton, coherent};
-  for (int i = 0; i < 3; ++i) {
+  const double* src[4] = {photo, compton, coherent, pair};
+  for (int i = 0; i < 4; ++i) {
     free(s->mats[m].lnval[i]);
     s->mats[m].lnval[i] = NULL;
     s->mats[m].present[i] = 0;
@@ -266,8 +268,10 @@ int32_t orc_set_xs(orc_scene* s, int32_t m, double lnE0, double dlnE, int32_t n,
   return 0;
 }
 
-/* mu/rho interpolated linearly in ln E on ln(mu/rho), per partial. */
-static void mass_atten(const orc_scene* s, int32_t m, double E, double out[3]) {
+/* mu/rho interpolated linearly in ln E on ln(mu/rho), per partial; pair
+ * production exists only above 2 m_e c^2 (Sec. 2.4.1 lists it among the
+ * photon interactions). */
+static void mass_atten(const orc_scene* s, int32_t m, double E, double out[4]) {
   double x = (log(E) - s->lnE0) / s->dlnE;
   int64_t k = (int64_t)floor(x);
   if (k < 0) k = 0;
@@ -275,8 +279,8 @@ static void mass_atten(const orc_scene* s, int32_t m, double E, double out[3]) {
   double w = x - (double)k;
   if (w < 0) w = 0;
   if (w > 1) w = 1;
-  for (int i = 0; i < 3; ++i) {
-    if (!s->mats[m].present[i]) {
+  for (int i = 0; i < 4; ++i) {
+    if (!s->mats[m].present[i] || (i == 3 && E <= 2.0 * MEC2)) {
       out[i] = 0.0;
       continue;
     }
@@ -286,12 +290,12 @@ static void mass_atten(const orc_scene* s, int32_t m, double E, double out[3]) {
 }
 
 void orc_mu(const orc_scene* s, int32_t r, double E, const double* scales, int32_t n_scales,
-            double out[3]) {
-  double mr[3];
+            double out[4]) {
+  double mr[4];
   mass_atten(s, s->mat[r], E, mr);
   double f = 0.1 * s->rho[r];
   if (scales && s->grp[r] >= 0 && s->grp[r] < n_scales) f *= scales[s->grp[r]];
-  for (int i = 0; i < 3; ++i) out[i] = f * mr[i];
+  for (int i = 0; i < 4; ++i) out[i] = f * mr[i];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -644,6 +648,12 @@ static void one_history(worker* w, int64_t h) {
   double tau = -log(rng_uniform(&g));
   double edep_act = 0.0, edep_tot = 0.0;
   int clean = 1, interacted = 0, absorbed = 0, escaped = 0;
+  double e_esc = 0.0; /* energy carried out of the world by this history's photons */
+  /* the second annihilation photon of a pair event waits here until the first
+   * one is done (a 511 keV photon cannot make a pair, so one slot is enough) */
+  int pending = 0, broken = 0; /* broken: lost or killed */
+  double p2[3], d2[3];
+  int32_t region2 = 0;
   double tau0[ORC_MAX_GROUPS] = {0};
   int nint[ORC_MAX_GROUPS] = {0};
   int64_t last = -1;
@@ -658,23 +668,38 @@ static void one_history(worker* w, int64_t h) {
       clean = 0;                 \
   } while (0)
 
+/* the current photon is done (absorbed or escaped): go on with the waiting
+ * annihilation photon, if there is one */
+#define NEXT_PHOTON()                    \
+  if (pending) {                         \
+    memcpy(p, p2, sizeof p);             \
+    memcpy(d, d2, sizeof d);             \
+    region = region2;                    \
+    E = MEC2;                            \
+    last = -1;                           \
+    pending = 0;                         \
+    tau = -log(rng_uniform(&g));         \
+    continue;                            \
+  }
+
   int steps = 0;
   for (;;) {
     if (++steps > w->max_steps) {
       T->n_killed++;
       clean = 0;
+      broken = 1;
       break;
     }
     T->n_segments++;
-    double mu3[3];
-    orc_mu(s, region, E, w->scales, w->ngroups, mu3);
-    double mu = mu3[0] + mu3[1] + mu3[2];
+    double mu4[4];
+    orc_mu(s, region, E, w->scales, w->ngroups, mu4);
+    double mu = mu4[0] + mu4[1] + mu4[2] + mu4[3];
     int32_t gidx = s->grp[region];
     double mu0 = 0.0; /* unscaled total attenuation of the region */
     if (gidx >= 0 && gidx < w->ngroups) {
-      double m0[3];
+      double m0[4];
       orc_mu(s, region, E, NULL, 0, m0);
-      mu0 = m0[0] + m0[1] + m0[2];
+      mu0 = m0[0] + m0[1] + m0[2] + m0[3];
     }
     double th;
     int64_t tri;
@@ -700,6 +725,7 @@ static void one_history(worker* w, int64_t h) {
       if (region < 0) {
         T->n_lost++;
         clean = 0;
+        broken = 1;
         break;
       }
       continue;
@@ -712,12 +738,13 @@ static void one_history(worker* w, int64_t h) {
       interacted = 1;
       if (gidx >= 0 && gidx < w->ngroups) nint[gidx]++;
       double x = rng_uniform(&g) * mu;
-      if (x < mu3[0]) {
+      if (x < mu4[0]) {
         T->n_photo++;
         DEPOSIT(E, region);
-        absorbed = 1;
+        NEXT_PHOTON();
+        absorbed = !escaped;
         break;
-      } else if (x < mu3[0] + mu3[1]) {
+      } else if (x < mu4[0] + mu4[1]) {
         T->n_compton++;
         double k = E / MEC2;
         double eps = orc_kn_sample(k, rng_uniform(&g));
@@ -729,14 +756,31 @@ static void one_history(worker* w, int64_t h) {
         E = Ep;
         if (E < Ecut) {
           DEPOSIT(E, region);
-          absorbed = 1;
+          NEXT_PHOTON();
+          absorbed = !escaped;
           break;
         }
-      } else {
+      } else if (x < mu4[0] + mu4[1] + mu4[2]) {
         T->n_coherent++;
         double ct = orc_thomson_sample(rng_uniform(&g));
         double ph = 2.0 * PI * rng_uniform(&g);
         rotate(d, ct, ph);
+      } else {
+        /* pair production: the photon is gone; the pair's kinetic energy
+         * E - 2 m_e c^2 is deposited here and the positron annihilates at
+         * rest into two 511 keV photons flying apart along a random axis */
+        T->n_pair++;
+        DEPOSIT(E - 2.0 * MEC2, region);
+        double a[3];
+        isotropic(&g, a);
+        memcpy(p2, p, sizeof p2);
+        for (int k = 0; k < 3; ++k) {
+          d[k] = a[k];
+          d2[k] = -a[k];
+        }
+        region2 = region;
+        pending = 1;
+        E = MEC2;
       }
       tau = -log(rng_uniform(&g));
       continue;
@@ -745,24 +789,28 @@ static void one_history(worker* w, int64_t h) {
     if (region == 0) {
       escaped = 1;
       clean = 0;
-      T->n_escape++;
+      e_esc += E;
       T->e_escape += E;
       if (!interacted) T->n_uncollided++;
+      NEXT_PHOTON();
     } else {
       T->n_lost++;
       clean = 0;
+      broken = 1;
     }
     break;
   }
 #undef DEPOSIT
+#undef NEXT_PHOTON
 
+  if (escaped && !broken) T->n_escape++;
   if (absorbed) T->n_absorbed++;
   int fep = absorbed && clean;
   if (fep) T->n_fep++;
   T->edep_active += edep_act;
   T->edep_total += edep_tot;
-  double bal = edep_tot + (escaped ? E : 0.0);
-  if ((absorbed || escaped) && fabs(bal - E0) > 1e-9 * E0) T->n_balance_fail++;
+  double bal = edep_tot + e_esc;
+  if (!broken && fabs(bal - E0) > 1e-9 * E0) T->n_balance_fail++;
   if (edep_act > 0.0 && w->spectrum) {
     double c = floor(edep_act / w->chw);
     if (c < (double)w->nch)
@@ -849,6 +897,7 @@ int32_t orc_run(const orc_scene* s, const orc_source* src, double E0, int64_t n,
     out->n_photo += t->n_photo;
     out->n_compton += t->n_compton;
     out->n_coherent += t->n_coherent;
+    out->n_pair += t->n_pair;
     out->spectrum_overflow += t->spectrum_overflow;
     out->edep_active += t->edep_active;
     out->edep_total += t->edep_total;

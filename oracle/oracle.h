@@ -47,9 +47,12 @@ void orc_scene_destroy(orc_scene* s);
 int32_t orc_set_region(orc_scene* s, int32_t region, int32_t material, double density,
                        int32_t group, int32_t active);
 /* Partial mu/rho [cm^2/g] on the grid ln E_k = lnE0 + k dlnE; any pointer may be
- * NULL (that partial is zero).  A partial must be all-zero or all-positive. */
+ * NULL (that partial is zero).  A partial must be all-zero or all-positive.  The
+ * pair-production partial counts only above its threshold 2 m_e c^2 (zero at and
+ * below it, whatever the table holds there). */
 int32_t orc_set_xs(orc_scene* s, int32_t material, double lnE0, double dlnE, int32_t n,
-                   const double* photo, const double* compton, const double* coherent);
+                   const double* photo, const double* compton, const double* coherent,
+                   const double* pair);
 
 /* Ray-parity localization (Sec. 2.4.2).  Returns region id, or -1 if every
  * probe direction was degenerate. */
@@ -58,10 +61,10 @@ int32_t orc_locate(const orc_scene* s, const double p[3]);
  * Returns 1 and fills t, tri on a hit, else 0. */
 int32_t orc_closest_hit(const orc_scene* s, const double o[3], const double d[3],
                         int64_t exclude, double* t, int64_t* tri);
-/* Linear attenuation coefficients [1/mm] (photo, compton, coherent) of region r at E;
- * scales[n_scales] multiply regions whose group is below n_scales. */
+/* Linear attenuation coefficients [1/mm] (photo, compton, coherent, pair) of
+ * region r at E; scales[n_scales] multiply regions whose group is below n_scales. */
 void orc_mu(const orc_scene* s, int32_t region, double E, const double* scales, int32_t n_scales,
-            double out[3]);
+            double out[4]);
 
 /* Klein-Nishina pieces: k = E / m_e c^2, eps = E'/E. */
 double orc_kn_integral(double k, double eps);    /* antiderivative of the bracket */
@@ -84,7 +87,7 @@ typedef struct {
 typedef struct {
   uint64_t n_histories, n_absorbed, n_fep, n_uncollided, n_escape, n_lost, n_killed,
       n_source_fail, n_balance_fail;
-  uint64_t n_segments, n_crossings, n_photo, n_compton, n_coherent;
+  uint64_t n_segments, n_crossings, n_photo, n_compton, n_coherent, n_pair;
   uint64_t spectrum_overflow;
   double edep_active, edep_total, e_escape;
   double sum_score[ORC_MAX_GROUPS];

@@ -131,7 +131,9 @@ enum EventSlot : int {
   // wavefront-level shader-clock cycles per section of the loop
   kEv_CycOutcome, kEv_CycRefill, kEv_CycLaunch, kEv_CycSetup, kEv_CycTrav,
   // screened histories settled by one box test (no attenuation, no exit planes)
-  kEv_BoxTests, kEv_N
+  kEv_BoxTests,
+  kEv_Pair,  // pair-production events
+  kEv_N
 };
 static_assert(kT_Ev + kEv_N <= kT_Slots, "tally slots");
 
@@ -144,7 +146,7 @@ struct TransportParams {
   const SourceRec* sources;
   const float* lines;          // float2 pairs
   const RegionRec* regions;
-  const float* xs;             // float4 per (material, grid point): ln photo, compton, coherent
+  const float* xs;             // float4 per (material, grid point): ln photo, Compton, coherent, pair
   int32_t n_e;
   float ln_e0;
   float inv_dlne;
@@ -159,6 +161,7 @@ struct TransportParams {
   int32_t stack_depth;
   int32_t period;
   int32_t screen;              // 1: first-flight screening where it applies
+  int32_t pair;                // 1: some material has a pair-production partial
 };
 
 // ---------------------------------------------------------------------------

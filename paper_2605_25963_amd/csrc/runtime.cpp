@@ -15,10 +15,10 @@
 
 namespace gadep {
 // kernels.hip
-size_t transport_smem(int block, int depth, bool grad);
+size_t transport_smem(int block, int depth, bool grad, bool pair);
 hipError_t transport_launch(const TransportParams& P, int variant, int grid, int block,
                             hipStream_t s);
-hipError_t transport_occupancy(int variant, int block, int depth, int* blocks_per_cu);
+hipError_t transport_occupancy(int variant, int block, int depth, int pair, int* blocks_per_cu);
 hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t locate_units(UnitRec* units, int n_units, const SceneRec* scenes,
                         const SourceRec* sources, int depth, hipStream_t s);
@@ -80,7 +80,8 @@ void fill_scene_rec(const Scene& sc, SceneRec& sr) {
 
 struct Material {
   bool set = false;
-  std::vector<float> ln[3];  // ln(mu/rho) per grid point; -200 for an absent partial
+  std::vector<float> ln[4];  // ln(mu/rho) per grid point; -200 for an absent partial
+  bool pair = false;         // has a pair-production partial
 };
 
 }  // namespace
@@ -189,7 +190,7 @@ gadep_status sync_xs(gadep_ctx* ctx) {
   for (size_t m = 0; m < nm; ++m) {
     if (!ctx->mats[m].set) continue;
     for (int32_t k = 0; k < ctx->nE; ++k)
-      for (int i = 0; i < 3; ++i) host[(m * ctx->nE + k) * 4 + i] = ctx->mats[m].ln[i][k];
+      for (int i = 0; i < 4; ++i) host[(m * ctx->nE + k) * 4 + i] = ctx->mats[m].ln[i][k];
   }
   gadep_status s = upload(ctx, ctx->xs, host.data(), host.size() * sizeof(float), "upload xs");
   if (s) return s;
@@ -449,16 +450,20 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   K.stack_depth = P.depth;
   K.period = static_cast<int32_t>(ctx->period);
   K.screen = static_cast<int32_t>(ctx->screen);
+  K.pair = 0;
+  for (const Material& m : ctx->mats)
+    if (m.set && m.pair) K.pair = 1;
 
   bool vol = false;
   for (const SourceRec& sr : P.sources) vol = vol || sr.kind == kCyl;
   const int variant =
-      (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0) | (vol ? 8 : 0);
+      (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0) | (vol ? 8 : 0) |
+      (K.pair ? 16 : 0);
   const int block = static_cast<int>(ctx->block);
   int grid = static_cast<int>(ctx->grid);
   if (grid <= 0) {
     int per_cu = 0;
-    HIP_TRY(transport_occupancy(variant, block, P.depth, &per_cu), "occupancy");
+    HIP_TRY(transport_occupancy(variant, block, P.depth, K.pair, &per_cu), "occupancy");
     if (per_cu < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");
     grid = per_cu * ctx->n_cu;
   }
@@ -584,6 +589,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     cnt.cycles_setup += ev[kEv_CycSetup];
     cnt.cycles_traversal += ev[kEv_CycTrav];
     cnt.box_tests += ev[kEv_BoxTests];
+    cnt.pair += ev[kEv_Pair];
   }
   if (ctx->counters) {
     ctx->last_counters = cnt;
@@ -842,7 +848,8 @@ gadep_status gadep_load_mesh(gadep_ctx* ctx, const float* xyz, int64_t nv, const
 }
 
 gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0, double dlnE, int32_t nE,
-                          const float* photo, const float* compton, const float* coherent) {
+                          const float* photo, const float* compton, const float* coherent,
+                          const float* pair) {
   if (!ctx) return GADEP_E_ARG;
   if (material < 0 || material >= 1024) return set_err(ctx, GADEP_E_ARG, "material id out of range");
   if (nE < 2 || !(dlnE > 0) || !std::isfinite(lnE0) || !std::isfinite(dlnE))
@@ -850,8 +857,8 @@ gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0, double 
   if (ctx->grid_set && (lnE0 != ctx->lnE0 || dlnE != ctx->dlnE || nE != ctx->nE))
     return set_err(ctx, GADEP_E_XS, "every material must use the same energy grid");
   Material m;
-  const float* src[3] = {photo, compton, coherent};
-  for (int i = 0; i < 3; ++i) {
+  const float* src[4] = {photo, compton, coherent, pair};
+  for (int i = 0; i < 4; ++i) {
     m.ln[i].assign(nE, -200.0f);
     if (!src[i]) continue;
     int npos = 0;
@@ -863,6 +870,7 @@ gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0, double 
     if (npos == 0) continue;
     if (npos != nE) return set_err(ctx, GADEP_E_XS, "a partial must be all-positive or all-zero");
     for (int32_t k = 0; k < nE; ++k) m.ln[i][k] = logf(src[i][k]);
+    if (i == 3) m.pair = true;
   }
   m.set = true;
   if (static_cast<int32_t>(ctx->mats.size()) <= material) ctx->mats.resize(material + 1);

@@ -14,6 +14,8 @@
 // slot, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "device_common.h"
 #include "gadep_internal.h"
 
@@ -186,6 +188,17 @@ __device__ __forceinline__ void xs_mu(const float4* __restrict__ xs, int n_e, co
   }
 }
 
+// pair-production partial [1/mm]; zero unless `on` (some material has one)
+// and E lies above the threshold 2 m_e c^2
+__device__ __forceinline__ float xs_pair(const float4* __restrict__ xs, int n_e, const RegionRec& rr,
+                                         Xs ix, float E, bool on) {
+#pragma clang fp contract(off)
+  if (!on || !(E > 2.0f * kMec2) || !(rr.mult > 0.0f)) return 0.0f;
+  const float lo = gload(xs, rr.material * n_e + ix.k).w;
+  const float hi = gload(xs, rr.material * n_e + ix.k + 1).w;
+  return rr.mult * __expf(fmaf(ix.w, hi - lo, lo));
+}
+
 // New direction at polar cosine ct and azimuth 2 pi u about (dx, dy, dz), in an
 // orthonormal basis built branch-free from the direction (Duff et al., JCGT
 // 2017).  sin/cos of 2 pi u come from the hardware sine, which takes
@@ -246,7 +259,9 @@ __device__ __forceinline__ unsigned long long fx(double v, double scale) {
 
 // kSample: draw a volume-source point; kLaunch: emission point settled,
 // draw direction and first flight
-enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3, kSample = 4, kLaunch = 5 };
+// kResume: the photon is done but a pair event left a second one waiting
+enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3, kSample = 4, kLaunch = 5,
+                   kResume = 6 };
 constexpr int kMaxEmitAttempts = 1000;  // volume-source rejection tries per history
 constexpr int kQueue = 128;             // screened histories a wavefront can hold
 constexpr int kXcds = 8;                // accelerator dies (XCDs) of an MI355X, one L2 each
@@ -257,8 +272,9 @@ constexpr int kExitPlane = -2;  // best_id of a crossing through an exit plane
 
 // GRAD: score-function tallies; SPEC: pulse-height spectra; COUNT: event
 // counters; VOL: some unit has a volume source (emission points are
-// localised by probe traversals).
-template <bool GRAD, bool SPEC, bool COUNT, bool VOL>
+// localised by probe traversals); PAIR: some material has a pair-production
+// partial (pair events, waiting annihilation photons).
+template <bool GRAD, bool SPEC, bool COUNT, bool VOL, bool PAIR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 transport_kernel(TransportParams P) {
   extern __shared__ unsigned long long smem[];
@@ -276,6 +292,11 @@ transport_kernel(TransportParams P) {
                        static_cast<size_t>(P.stack_depth) * stride * sizeof(int) +
                        (GRAD ? static_cast<size_t>(kMaxGroups) * stride * sizeof(float) : 0)) +
                    wave * kQueue;
+  // the second annihilation photon of a pair event, waiting for the first to
+  // be done: x, y, z, dx, dy, dz (as bits), region (< 0: none); one LDS
+  // column per thread (only allocated when some material has a pair partial)
+  int* wait = reinterpret_cast<int*>(queue - wave * kQueue + nwaves * kQueue) + threadIdx.x;
+  if (PAIR) wait[6 * stride] = -1;
   for (int i = lane; i < kT_Slots; i += kWave) wt[i] = 0;
 
   const uint32_t k0 = P.seed_lo, k1 = P.seed_hi;
@@ -334,6 +355,7 @@ transport_kernel(TransportParams P) {
   int region = 0, last = -1, steps = 0;
   int attempts = 0;  // > 0: localising a volume-source emission point (try number)
   bool clean = true, interacted = false, touched = false;
+  bool esc_any = false;  // a photon of this history (pair events: not the last) escaped
   Xs ix{0, 0.0f};
   Rng g{};
   // lane state: current segment and its traversal
@@ -381,6 +403,15 @@ transport_kernel(TransportParams P) {
   };
 
   auto end_history = [&](bool absorbed, bool escaped, bool lost, bool killed) {
+    if (PAIR && (absorbed || escaped) && wait[6 * stride] >= 0) {
+      // this photon is done; the history goes on with the waiting one
+      if (escaped) {
+        esc_any = true;
+        atomicAdd(&wt[kT_EEsc], fx_kev(E));
+      }
+      phase = kResume;
+      return;
+    }
     phase = kNeed;
     acc_hist += 1;
     if (escaped) {
@@ -390,7 +421,14 @@ transport_kernel(TransportParams P) {
       } else {
         acc_eunc += fx_kev(E);
       }
+    } else if (esc_any && !lost && !killed) {
+      atomicAdd(&wt[kT_CollEscape], 1ull);  // an earlier photon of the history escaped
     }
+    if (esc_any) {
+      absorbed = false;
+      esc_any = false;
+    }
+    if (PAIR) wait[6 * stride] = -1;
     const bool fep = absorbed && clean;
     if (absorbed) atomicAdd(&wt[kT_Absorbed], 1ull);
     if (fep) atomicAdd(&wt[kT_Fep], 1ull);
@@ -452,6 +490,7 @@ transport_kernel(TransportParams P) {
     edep_act = edep_tot = 0.0f;
     clean = true;
     interacted = touched = false;
+    esc_any = false;
     last = -1;
     steps = 0;
     if (GRAD)
@@ -587,7 +626,8 @@ transport_kernel(TransportParams P) {
               } else {
                 ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
               }
-            } else {
+            } else if (!(PAIR && E > 2.0f * kMec2) ||
+                       x < mu - xs_pair(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ix, E, true)) {
               // coherent: Thomson law 3/8 (1 + mu^2); its CDF (mu^3 + 3 mu + 4)/8
               // inverts in closed form (Cardano): with a = 4u - 2,
               // mu = c - 1/c, c = cbrt(a + sqrt(a^2 + 1)), taken on |a| for accuracy
@@ -596,6 +636,33 @@ transport_kernel(TransportParams P) {
               const float c = cbrtf(fabsf(a) + sqrtf(fmaf(a, a, 1.0f)));
               const float ct = copysignf(c - 1.0f / c, a);
               turn(dx, dy, dz, fminf(1.0f, fmaxf(-1.0f, ct)), rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
+            } else {
+              // pair production: the photon is gone; the pair's kinetic energy
+              // E - 2 m_e c^2 is deposited here and the positron annihilates at
+              // rest into two 511 keV photons flying apart along a random axis.
+              // This lane follows the first; the second waits in LDS.
+              if (COUNT) ev[kEv_Pair]++;
+              const float kin = E - 2.0f * kMec2;
+              edep_tot += kin;
+              if (active)
+                edep_act += kin;
+              else
+                clean = false;
+              const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
+              const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
+              const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+              dx = st * __builtin_amdgcn_cosf(uphi);
+              dy = st * __builtin_amdgcn_sinf(uphi);
+              dz = ct;
+              wait[0] = __float_as_int(px);
+              wait[stride] = __float_as_int(py);
+              wait[2 * stride] = __float_as_int(pz);
+              wait[3 * stride] = __float_as_int(-dx);
+              wait[4 * stride] = __float_as_int(-dy);
+              wait[5 * stride] = __float_as_int(-dz);
+              wait[6 * stride] = region;
+              E = kMec2;
+              ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
             }
             if (!absorbed) tau = -hw_log(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
           }
@@ -609,6 +676,22 @@ transport_kernel(TransportParams P) {
         }
       }
 
+      if (PAIR && phase == kResume) {
+        // the waiting annihilation photon takes over the lane
+        px = __int_as_float(wait[0]);
+        py = __int_as_float(wait[stride]);
+        pz = __int_as_float(wait[2 * stride]);
+        dx = __int_as_float(wait[3 * stride]);
+        dy = __int_as_float(wait[4 * stride]);
+        dz = __int_as_float(wait[5 * stride]);
+        region = wait[6 * stride];
+        wait[6 * stride] = -1;
+        E = kMec2;
+        ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+        last = -1;
+        tau = -hw_log(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
+        phase = kSetup;
+      }
       lap(kEv_CycOutcome);
       // ---- new histories for lanes that need one (chunks of the wave's unit)
       const uint64_t need = __ballot(phase == kNeed);
@@ -661,9 +744,10 @@ transport_kernel(TransportParams P) {
                 }
                 scr_far = sqrtf(d2) * 1.0001f;
                 float m_p, m_c, m_h;
-                xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, ro,
-                      xs_index(U.energy, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
-                scr_m = m_p + m_c + m_h;
+                const Xs ixu = xs_index(U.energy, P.ln_e0, P.inv_dlne, P.n_e);
+                xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, ro, ixu, m_p, m_c, m_h);
+                scr_m = m_p + m_c + m_h +
+                        xs_pair(reinterpret_cast<const float4*>(P.xs), P.n_e, ro, ixu, U.energy, PAIR);
                 scr_tau = scr_m * scr_far * 1.0001f;
               }
             }
@@ -725,9 +809,9 @@ transport_kernel(TransportParams P) {
               if (m < 0.0f) {
                 const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
                 float m_p, m_c, m_h;
-                xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr,
-                      xs_index(e, P.ln_e0, P.inv_dlne, P.n_e), m_p, m_c, m_h);
-                m = m_p + m_c + m_h;
+                const Xs ixe = xs_index(e, P.ln_e0, P.inv_dlne, P.n_e);
+                xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ixe, m_p, m_c, m_h);
+                m = m_p + m_c + m_h + xs_pair(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ixe, e, PAIR);
               }
               const float tfl = m > 0.0f ? tau0 / m : INFINITY;
               te = INFINITY;
@@ -859,7 +943,7 @@ transport_kernel(TransportParams P) {
         const RegionRec rr = gload(P.regions, U.region_off + region);
         float mh;
         xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ix, mp, mc, mh);
-        mu = mp + mc + mh;
+        mu = mp + mc + mh + xs_pair(reinterpret_cast<const float4*>(P.xs), P.n_e, rr, ix, E, PAIR);
         tbest = mu > 0.0f ? tau / mu : INFINITY;
         ray = make_ray(px, py, pz, dx, dy, dz);
         trej = INFINITY;
@@ -1077,46 +1161,40 @@ __global__ void broaden_kernel(const double* in, double* out, int n_spectra, int
 
 using TK = void (*)(TransportParams);
 
-static TK pick(int variant) {
-  switch (variant & 15) {
-    case 0: return transport_kernel<false, false, false, false>;
-    case 1: return transport_kernel<true, false, false, false>;
-    case 2: return transport_kernel<false, true, false, false>;
-    case 3: return transport_kernel<true, true, false, false>;
-    case 4: return transport_kernel<false, false, true, false>;
-    case 5: return transport_kernel<true, false, true, false>;
-    case 6: return transport_kernel<false, true, true, false>;
-    case 7: return transport_kernel<true, true, true, false>;
-    case 8: return transport_kernel<false, false, false, true>;
-    case 9: return transport_kernel<true, false, false, true>;
-    case 10: return transport_kernel<false, true, false, true>;
-    case 11: return transport_kernel<true, true, false, true>;
-    case 12: return transport_kernel<false, false, true, true>;
-    case 13: return transport_kernel<true, false, true, true>;
-    case 14: return transport_kernel<false, true, true, true>;
-    default: return transport_kernel<true, true, true, true>;
-  }
+template <int V>
+constexpr TK variant_kernel() {
+  return transport_kernel<(V & 1) != 0, (V & 2) != 0, (V & 4) != 0, (V & 8) != 0, (V & 16) != 0>;
 }
 
+template <int... V>
+static TK pick_from(int variant, std::integer_sequence<int, V...>) {
+  static const TK table[] = {variant_kernel<V>()...};
+  return table[variant];
+}
+
+// variant bits: 1 GRAD, 2 SPEC, 4 COUNT, 8 VOL, 16 PAIR
+static TK pick(int variant) { return pick_from(variant & 31, std::make_integer_sequence<int, 32>{}); }
+
 // LDS: per-wavefront tallies, the traversal stacks, and (GRAD) the scores
-size_t transport_smem(int block, int depth, bool grad) {
+size_t transport_smem(int block, int depth, bool grad, bool pair) {
   return static_cast<size_t>(block / kWave) * kT_Slots * sizeof(unsigned long long) +
          static_cast<size_t>(depth) * block * sizeof(int) +
          (grad ? static_cast<size_t>(kMaxGroups) * block * sizeof(float) : 0) +
-         static_cast<size_t>(block / kWave) * kQueue * sizeof(int64_t);
+         static_cast<size_t>(block / kWave) * kQueue * sizeof(int64_t) +
+         (pair ? static_cast<size_t>(7) * block * sizeof(int) : 0);
 }
 
 hipError_t transport_launch(const TransportParams& P, int variant, int grid, int block,
                             hipStream_t s) {
-  const size_t smem = transport_smem(block, P.stack_depth, variant & 1);
+  const size_t smem = transport_smem(block, P.stack_depth, variant & 1, (variant & 16) != 0);
   hipLaunchKernelGGL(pick(variant), dim3(grid), dim3(block), smem, s, P);
   return hipGetLastError();
 }
 
-hipError_t transport_occupancy(int variant, int block, int depth, int* blocks_per_cu) {
+hipError_t transport_occupancy(int variant, int block, int depth, int pair, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks_per_cu, reinterpret_cast<const void*>(pick(variant)), block,
-      transport_smem(block, depth, variant & 1));
+      transport_smem(block, depth, variant & 1, (variant & 16) != 0 || pair != 0));
 }
 
 hipError_t fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {

@@ -76,7 +76,7 @@ class Counters(C.Structure):
         "segments", "crossings", "node_visits", "tri_tests", "photo", "compton", "coherent",
         "rng_calls", "locates", "emissions", "plane_tests", "iterations", "iterations_node",
         "iterations_facet", "passes", "cycles_outcome", "cycles_refill", "cycles_launch",
-        "cycles_setup", "cycles_traversal", "box_tests")]
+        "cycles_setup", "cycles_traversal", "box_tests", "pair")]
 
 
 class MeshInfo(C.Structure):
@@ -127,7 +127,7 @@ def lib():
         "gadep_get_option": (i32, [p, i32, C.POINTER(i64)]),
         "gadep_load_mesh": (i32, [p, f32p, i64, i32p, i32p, i64, C.POINTER(Region), i32]),
         "gadep_load_scene": (i32, [p, i32, f32p, i64, i32p, i32p, i64, C.POINTER(Region), i32]),
-        "gadep_set_xs": (i32, [p, i32, C.c_double, C.c_double, i32, f32p, f32p, f32p]),
+        "gadep_set_xs": (i32, [p, i32, C.c_double, C.c_double, i32, f32p, f32p, f32p, f32p]),
         "gadep_set_scales": (i32, [p, f32p, i32]),
         "gadep_run": (i32, [p, C.POINTER(Source), dp, i32, i64, u64, i64, C.POINTER(Tally)]),
         "gadep_run_grad": (i32, [p, C.POINTER(Source), dp, i32, i64, u64, i64, f32p, i32,
@@ -273,9 +273,9 @@ class Context:
     def load_mesh(self, xyz, tri, tri_region, regions):
         self.load_scene(0, xyz, tri, tri_region, regions)
 
-    def set_xs(self, material, grid, photo, compton, coherent=None):
+    def set_xs(self, material, grid, photo, compton, coherent=None, pair=None):
         lnE0, dlnE, n = grid
-        arrs = [None if a is None else _f32(a) for a in (photo, compton, coherent)]
+        arrs = [None if a is None else _f32(a) for a in (photo, compton, coherent, pair)]
         self._check(lib().gadep_set_xs(self.h, int(material), float(lnE0), float(dlnE), int(n),
                                        *[_ptr(a, C.c_float) for a in arrs]))
 
@@ -456,8 +456,8 @@ def load_workload(ctx, w, scene=0):
     regions = [(int(mat[r]), float(rho[r]), int(grp[r]), ACTIVE if act[r] else 0)
                for r in range(len(mat))]
     sc = w.scene
-    for m, (pe, c, coh) in w.tables.items():
-        ctx.set_xs(m, w.grid, pe, c, coh)
+    for m, tab in w.tables.items():
+        ctx.set_xs(m, w.grid, *tab)
     ctx.load_scene(scene, sc.xyz, sc.tri, sc.tri_region, regions)
     return regions
 

@@ -263,12 +263,79 @@ def _slab_scene(orc, T, photo, compton=0.0, coherent=0.0, active=True):
     s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
     s.set_region(0, 0, 0.0)
     s.set_region(1, 1, 1.0, 0, active)
-    for m, (a, b, c) in tabs.items():
-        s.set_xs(m, grid, a, b, c)
+    for m, t in tabs.items():
+        s.set_xs(m, grid, *t)
     return s
 
 
 BEAM = C.Source(C.KIND_BEAM, pos=(0.1234, 0.4321, 10.0), direction=(0.0, 0.0, -1.0))
+
+
+# --------------------------------------------------------------------------
+# pair production (Sec. 2.4.1): closed forms
+
+MEC2 = 510.99895
+
+
+def _pair_slab(orc, T, pair, photo_below=None):
+    """ACTIVE slab with a constant pair partial; photo_below (optional): a
+    photoelectric partial that is large below 1000 keV and negligible above."""
+    scene, mats, tabs, grid = C.slab(T, 0.0, mu_pair=pair)
+    if photo_below is not None:
+        E = xsgen.grid_energies(*grid)
+        t = list(tabs[1])
+        t[0] = np.where(E < 1000.0, photo_below, 1e-30)
+        tabs[1] = tuple(t)
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    s.set_region(0, 0, 0.0)
+    s.set_region(1, 1, 1.0, 0, True)
+    for m, t in tabs.items():
+        s.set_xs(m, grid, *t)
+    return s
+
+
+def test_pair_partial_vanishes_at_threshold(orc):
+    s = _pair_slab(orc, 5.0, 2.0)
+    assert s.mu(1, 2000.0)[3] == pytest.approx(0.2, rel=1e-12)
+    assert s.mu(1, 2 * MEC2)[3] == 0.0 and s.mu(1, MEC2)[3] == 0.0
+    assert s.mu(1, 2 * MEC2 * (1 + 1e-9))[3] == pytest.approx(0.2, rel=1e-12)
+
+
+def test_pair_double_escape_line(orc):
+    # A slab that only makes pairs (mu t = 1 at 2 MeV) and is transparent to
+    # the 511 keV annihilation photons: each interacting history deposits
+    # exactly E0 - 2 m_e c^2 (the double-escape line), the two photons leave,
+    # and the uncollided fraction is exp(-1).  Nothing is a full-energy event.
+    s = _pair_slab(orc, 5.0, 2.0)
+    n, E0 = 200_000, 2000.0
+    r = s.run(BEAM, E0, n, 2301, n_channels=8192, channel_keV=0.25)
+    t = r.tally
+    ex = math.exp(-1.0)
+    assert _sigma_ok(t.n_uncollided / n, ex, math.sqrt(ex * (1 - ex) / n))
+    assert t.n_pair == n - t.n_uncollided
+    assert t.n_fep == 0 and t.n_absorbed == 0 and t.n_escape == n
+    assert t.n_balance_fail == 0 and t.n_lost == 0
+    assert t.edep_active == pytest.approx(t.n_pair * (E0 - 2 * MEC2), rel=1e-12)
+    assert t.e_escape == pytest.approx(t.n_uncollided * E0 + t.n_pair * 2 * MEC2, rel=1e-12)
+    ch = int((E0 - 2 * MEC2) // 0.25)
+    assert r.spectrum[ch] == t.n_pair and r.spectrum.sum() == t.n_pair
+
+
+def test_pair_full_absorption(orc):
+    # The same slab, but the 511 keV photons are photo-absorbed within about a
+    # micrometre: every interacting history deposits all of E0, so the FEPE is
+    # 1 - exp(-1) up to the rare pair event within a micrometre of a face.
+    s = _pair_slab(orc, 5.0, 2.0, photo_below=1e4)
+    n, E0 = 200_000, 2000.0
+    r = s.run(BEAM, E0, n, 2302)
+    t = r.tally
+    ex = 1 - math.exp(-1.0)
+    assert abs(r.fepe() - ex) <= 3 * r.fepe_sigma() + 2e-4
+    assert t.n_fep == t.n_absorbed and t.n_pair >= t.n_fep
+    # both annihilation photons are absorbed unless they leave the slab
+    lost_511 = t.n_escape - t.n_uncollided
+    assert 2 * (t.n_pair - lost_511) <= t.n_photo <= 2 * t.n_pair
+    assert t.n_balance_fail == 0 and t.n_lost == 0
 
 
 def test_slab_photo_only_fepe(orc):

@@ -68,14 +68,14 @@ class Workload:
         return mat, rho, grp, act
 
 
-def _tables_for(materials, coherent=True, overrides=None):
+def _tables_for(materials, coherent=True, overrides=None, pair=False):
     lnE0, dlnE, n = xsgen.grid()
     tabs = {}
     for i, name in enumerate(materials):
         if overrides and name in overrides:
             tabs[i] = overrides[name]
         else:
-            tabs[i] = xsgen.material_table(name, lnE0, dlnE, n, coherent=coherent)
+            tabs[i] = xsgen.material_table(name, lnE0, dlnE, n, coherent=coherent, pair=pair)
     return tabs, (lnE0, dlnE, n)
 
 
@@ -208,11 +208,13 @@ def c5_stress(n_histories=125_000_000, seed=1005, n_seg=1024, n_phi=48, z_slices
 # closed-form fixtures
 
 def slab(thickness, mu_photo, mu_compton=0.0, mu_coherent=0.0, half=50.0, density=1.0,
-         active=True):
+         active=True, mu_pair=None):
     """Box slab z in [-thickness, 0] in vacuum with constant synthetic partials.
 
     The partials are mass attenuation coefficients [cm^2/g]; with density 1
-    the linear coefficient is 0.1 * value [1/mm].
+    the linear coefficient is 0.1 * value [1/mm].  mu_pair (optional) is a
+    constant pair-production partial, which transport applies above 2 m_e c^2
+    only.
     """
     b = mg.SceneBuilder("vacuum", 0.0)
     b.add("slab", "synthetic", density, mg.box((-half, -half, -thickness), (half, half, 0.0)),
@@ -220,7 +222,8 @@ def slab(thickness, mu_photo, mu_compton=0.0, mu_coherent=0.0, half=50.0, densit
     scene = b.build()
     lnE0, dlnE, n = xsgen.grid()
     mats = ["vacuum", "synthetic"]
-    tabs = {0: xsgen.constant_table(n=n), 1: xsgen.constant_table(mu_photo, mu_compton, mu_coherent, n)}
+    tabs = {0: xsgen.constant_table(n=n),
+            1: xsgen.constant_table(mu_photo, mu_compton, mu_coherent, n, pair=mu_pair)}
     return scene, mats, tabs, (lnE0, dlnE, n)
 
 

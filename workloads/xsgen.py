@@ -10,7 +10,11 @@ Per element (Z, A, E_K) and energy E [keV], in cm^2/atom:
   * incoherent: Z * sigma_KN(E), the free-electron Klein-Nishina total cross
     section (textbook closed form);
   * photoelectric: C_pe Z^4 E^-3, divided by 7.5 below the K edge;
-  * coherent: C_coh Z^2 E^-2.
+  * coherent: C_coh Z^2 E^-2;
+  * pair production (optional fourth partial): C_pair Z^2 (1 - 2 m_e c^2 / E)^3
+    above the threshold 2 m_e c^2, a negligible floor below it (the tables keep
+    every partial positive; both transport codes drop the pair partial at or
+    below the threshold).
 A material's mu/rho is sum_i w_i (N_A / A_i) sigma_i.
 """
 from __future__ import annotations
@@ -24,6 +28,8 @@ MEC2_KEV = 510.99895            # electron rest energy [keV]
 N_A = 6.02214076e23
 C_PE = 4.6e-23
 C_COH = 3.5e-23
+C_PAIR = 1.31e-27   # ~1.3e-3 cm^2/g for Ge at 2 MeV
+PAIR_FLOOR = 1e-40  # cm^2/atom below the threshold
 K_EDGE_JUMP = 7.5
 
 # (Z, A, K-edge keV or None)
@@ -86,6 +92,23 @@ def element_sigmas(sym, E_keV):
     return s_pe, s_c, s_coh
 
 
+def element_pair(sym, E_keV):
+    Z, _, _ = ELEMENTS[sym]
+    E = np.asarray(E_keV, dtype=np.float64)
+    x = np.clip(1.0 - 2.0 * MEC2_KEV / E, 0.0, None)
+    return np.where(E > 2.0 * MEC2_KEV, C_PAIR * Z ** 2 * x ** 3, PAIR_FLOOR)
+
+
+def pair_attenuation(composition, E_keV):
+    """Pair-production mu/rho [cm^2/g] for a mass-fraction mix."""
+    E = np.asarray(E_keV, dtype=np.float64)
+    out = np.zeros_like(E)
+    for sym, w in composition.items():
+        _, A, _ = ELEMENTS[sym]
+        out += w * N_A / A * element_pair(sym, E)
+    return out
+
+
 def mass_attenuation(composition, E_keV):
     """(photo, compton, coherent) mu/rho [cm^2/g] for a mass-fraction mix."""
     E = np.asarray(E_keV, dtype=np.float64)
@@ -97,8 +120,8 @@ def mass_attenuation(composition, E_keV):
     return tuple(out)
 
 
-def material_table(name, lnE0=None, dlnE=None, n=None, coherent=True):
-    """Tabulated (photo, compton, coherent) mu/rho on the ln E grid."""
+def material_table(name, lnE0=None, dlnE=None, n=None, coherent=True, pair=False):
+    """Tabulated (photo, compton, coherent[, pair]) mu/rho on the ln E grid."""
     if lnE0 is None:
         lnE0, dlnE, n = grid()
     comp, _ = MATERIALS[name]
@@ -106,9 +129,13 @@ def material_table(name, lnE0=None, dlnE=None, n=None, coherent=True):
     pe, c, coh = mass_attenuation(comp, E)
     if not coherent:
         coh = np.zeros_like(coh)
+    if pair:
+        return pe, c, coh, pair_attenuation(comp, E) if comp else np.zeros_like(pe)
     return pe, c, coh
 
 
-def constant_table(photo=0.0, compton=0.0, coherent=0.0, n=GRID_N):
-    """Energy-independent synthetic partials, for closed-form tests."""
-    return (np.full(n, float(photo)), np.full(n, float(compton)), np.full(n, float(coherent)))
+def constant_table(photo=0.0, compton=0.0, coherent=0.0, n=GRID_N, pair=None):
+    """Energy-independent synthetic partials, for closed-form tests (pair, when
+    given, is a fourth partial; transport drops it at or below 2 m_e c^2)."""
+    t = (np.full(n, float(photo)), np.full(n, float(compton)), np.full(n, float(coherent)))
+    return t if pair is None else t + (np.full(n, float(pair)),)
