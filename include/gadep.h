@@ -326,6 +326,67 @@ gadep_status gadep_mesh_prepare(const float* xyz_mm, int64_t n_vertices,
                                 int64_t cap_nodes, int32_t* tri_order, int64_t cap_slots,
                                 gadep_mesh_info* info, char* err, int32_t err_len);
 
+/* ----------------------------------------------------------------------------
+ * parametric detector meshes (Sec. 2.2, 2.3) */
+
+/* A single-ended coaxial HPGe detector by the Table 2 parameter groups [mm].
+ * Frame: axis z, crystal front face at z = 0 facing +z (toward the source),
+ * crystal z in [-D1, 0].  Readings of the parameters:
+ *   crystal radius D2, length D1, front-edge rounding D3 (Eq. 3-4);
+ *   outer dead layer D4: the active volume has radius D2 - D4, front face at
+ *     -D4, rounding D3 - D4 (Eq. 6); below 4 eps it gets no shell of its own
+ *     (an implanted contact of 0.3 um: the crystal shell is then the active one);
+ *   borehole radius D6, length D5 from the back face, hemispherical tip; the
+ *     contact layer D7 lines it (a shell of its own when >= 4 eps);
+ *   crystal cup: cavity radius D2 + cup_gap_mm, wall d4, floor d10, from
+ *     z = -d8 up to its rim at z = cup_rim_mm (open toward the window);
+ *   vacuum housing: side vacuum d6 outside the cup, wall d3, floor d9 at
+ *     z = -d7; its front wall is the window plane, d5 (top vacuum) above the
+ *     crystal, d2 thick, with the window (radius d1) as a region of its own;
+ *   optional electrode pin in the borehole and cold finger below the cup;
+ *   world_half_mm > 0: an air box of that half-size around the housing.
+ * Nested shells that would touch are separated inside-out by eps_mm (Sec.
+ * 2.4.2).  Discretisation: n_theta angles (Eq. 1-2), n_phi rounding steps
+ * (Eq. 3), z_slices side bands. */
+typedef struct {
+  double d1, d2, d3, d4, d5, d6, d7, d8, d9, d10;
+  double D1, D2, D3, D4, D5, D6, D7;
+  int32_t n_theta, n_phi, z_slices;
+  double eps_mm;
+  double cup_gap_mm, cup_rim_mm;
+  double pin_radius_mm, pin_length_mm;
+  double finger_radius_mm;
+  double world_half_mm;
+} gadep_detector;
+
+/* Region ids of gadep_detmesh (a region may have no facets: no air box, no
+ * separate dead layer, no contact layer, pin or finger). */
+enum {
+  GADEP_DM_WORLD = 0, GADEP_DM_AIR, GADEP_DM_HOUSING, GADEP_DM_WINDOW, GADEP_DM_VACUUM,
+  GADEP_DM_CUP, GADEP_DM_CRYSTAL, GADEP_DM_ACTIVE, GADEP_DM_CONTACT, GADEP_DM_BORE,
+  GADEP_DM_PIN, GADEP_DM_FINGER, GADEP_DM_N
+};
+
+/* Builds the detector's shells (Eq. 5 orientation, CCW seen from outside).
+ * n_vertices / n_facets receive the counts; xyz[3 * n_vertices],
+ * tri_vertices[3 * n_facets] and tri_region[n_facets] (each nullable) receive
+ * the mesh when the capacities suffice (call once with NULL to size);
+ * region_parent[GADEP_DM_N] (nullable) the enclosing region of each region
+ * (-1: the world, or no facets).  The arrays feed gadep_load_mesh /
+ * gadep_load_scene directly (in memory, Sec. 2.4).  Errors: GADEP_E_ARG with
+ * a message for parameters that do not fit together. */
+gadep_status gadep_detmesh(const gadep_detector* params, float* xyz, int64_t cap_vertices,
+                           int32_t* tri_vertices, int32_t* tri_region, int64_t cap_facets,
+                           int64_t* n_vertices, int64_t* n_facets, int32_t* region_parent,
+                           char* err, int32_t err_len);
+
+/* Writes a mesh as VRML 2.0 (Sec. 2.2.3): one Shape with an IndexedFaceSet per
+ * region that has facets, all sharing the vertex list.  GADEP_E_ARG on bad
+ * arrays or an unwritable path. */
+gadep_status gadep_write_vrml(const char* path, const float* xyz, int64_t n_vertices,
+                              const int32_t* tri_vertices, const int32_t* tri_region,
+                              int64_t n_tri, int32_t n_regions);
+
 #ifdef __cplusplus
 }
 #endif

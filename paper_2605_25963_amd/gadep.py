@@ -79,6 +79,20 @@ class Counters(C.Structure):
         "cycles_setup", "cycles_traversal", "box_tests", "pair")]
 
 
+class Detector(C.Structure):
+    """gadep_detector: Table 2 parameter groups [mm] plus discretisation."""
+    _fields_ = ([(n, C.c_double) for n in ("d1", "d2", "d3", "d4", "d5", "d6", "d7", "d8", "d9",
+                                           "d10", "D1", "D2", "D3", "D4", "D5", "D6", "D7")] +
+                [("n_theta", C.c_int32), ("n_phi", C.c_int32), ("z_slices", C.c_int32),
+                 ("eps_mm", C.c_double), ("cup_gap_mm", C.c_double), ("cup_rim_mm", C.c_double),
+                 ("pin_radius_mm", C.c_double), ("pin_length_mm", C.c_double),
+                 ("finger_radius_mm", C.c_double), ("world_half_mm", C.c_double)])
+
+
+DM_REGIONS = ["world", "air", "housing", "window", "vacuum", "cup", "crystal", "active",
+              "contact", "bore", "pin", "finger"]
+
+
 class MeshInfo(C.Structure):
     _fields_ = [("n_shells", C.c_int32), ("genus_max", C.c_int32), ("n_nodes", C.c_int64),
                 ("depth", C.c_int32), ("sah_cost", C.c_double), ("n_slots", C.c_int64),
@@ -91,7 +105,7 @@ EXPORTS = [
     "gadep_load_mesh", "gadep_load_scene", "gadep_set_xs", "gadep_set_scales", "gadep_run",
     "gadep_run_grad", "gadep_run_batch", "gadep_autotune", "gadep_get_counters",
     "gadep_broaden_dev", "gadep_raycast", "gadep_locate", "gadep_mesh_prepare",
-    "gadep_get_last_launch_ms",
+    "gadep_get_last_launch_ms", "gadep_detmesh", "gadep_write_vrml",
 ]
 
 _lib = None
@@ -142,6 +156,9 @@ def lib():
         "gadep_mesh_prepare": (i32, [f32p, i64, i32p, i32p, i64, i32, C.c_double, i32, i32,
                                      C.c_double, i32p, i32p, p, i64, i32p, i64,
                                      C.POINTER(MeshInfo), C.c_char_p, i32]),
+        "gadep_detmesh": (i32, [C.POINTER(Detector), f32p, i64, i32p, i32p, i64,
+                                C.POINTER(C.c_int64), C.POINTER(C.c_int64), i32p, C.c_char_p, i32]),
+        "gadep_write_vrml": (i32, [C.c_char_p, f32p, i64, i32p, i32p, i64, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -448,6 +465,39 @@ def mesh_prepare(xyz, tri, tri_region, n_regions, min_gap_mm=1e-4, validate=True
     if nodes is not None:
         res["nodes"] = nodes
     return res
+
+
+def detmesh(params=None, **kw):
+    """gadep_detmesh: (xyz [nv, 3] float32, tri [nt, 3] int32, tri_region [nt] int32,
+    region_parent [GADEP_DM_N] int32) of a coaxial HPGe detector; params is a
+    Detector or keyword fields of one."""
+    d = params if params is not None else Detector(**kw)
+    L = lib()
+    nv, nt = C.c_int64(), C.c_int64()
+    parent = np.zeros(len(DM_REGIONS), np.int32)
+    err = C.create_string_buffer(512)
+    rc = L.gadep_detmesh(C.byref(d), None, 0, None, None, 0, C.byref(nv), C.byref(nt),
+                         _ptr(parent, C.c_int32), err, 512)
+    if rc:
+        raise GadepError(rc, err.value.decode(errors="replace"))
+    xyz = np.zeros((nv.value, 3), np.float32)
+    tri = np.zeros((nt.value, 3), np.int32)
+    reg = np.zeros(nt.value, np.int32)
+    rc = L.gadep_detmesh(C.byref(d), _ptr(xyz, C.c_float), nv.value, _ptr(tri, C.c_int32),
+                         _ptr(reg, C.c_int32), nt.value, C.byref(nv), C.byref(nt),
+                         _ptr(parent, C.c_int32), err, 512)
+    if rc:
+        raise GadepError(rc, err.value.decode(errors="replace"))
+    return xyz, tri, reg, parent
+
+
+def write_vrml(path, xyz, tri, tri_region, n_regions):
+    """gadep_write_vrml: the mesh as VRML 2.0, one IndexedFaceSet per region."""
+    xyz, tri, reg = _f32(xyz, (-1, 3)), _i32(tri).reshape(-1, 3), _i32(tri_region)
+    rc = lib().gadep_write_vrml(os.fsencode(path), _ptr(xyz, C.c_float), len(xyz),
+                                _ptr(tri, C.c_int32), _ptr(reg, C.c_int32), len(tri), int(n_regions))
+    if rc:
+        raise GadepError(rc, f"write_vrml({path}) failed")
 
 
 def load_workload(ctx, w, scene=0):

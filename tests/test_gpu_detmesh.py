@@ -1,0 +1,62 @@
+"""Transport on the GPU through detectors built by the parametric generator
+(gadep_detmesh, in memory as in Sec. 2.4): Table 1 crystals in the C2
+housing, point source 250 mm above the window, against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from workloads import configs as C
+from workloads import xsgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2605_25963_amd import gadep
+    gadep.lib()
+    return gadep
+
+
+@pytest.fixture(scope="module")
+def ctx(G):
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _density(name):
+    return xsgen.MATERIALS[name][1]
+
+
+@pytest.mark.parametrize("name", ["#3 GEM-C50P4", "#1 GMX45P4-76"])
+def test_table1_detector_matches_oracle(G, ctx, orc, name):
+    p = C.table1_detmesh(name)
+    xyz, tri, reg, parent = G.detmesh(**p)
+    mats = sorted(set(C.DETMESH_MATERIALS))
+    tabs, grid = C._tables_for(mats, coherent=True)
+    for m, t in tabs.items():
+        ctx.set_xs(m, grid, *t)
+    regions = []
+    for r, mname in enumerate(C.DETMESH_MATERIALS):
+        active = r == G.DM_REGIONS.index("active")
+        regions.append((mats.index(mname), _density(mname), -1, G.ACTIVE if active else 0))
+    ctx.load_scene(0, xyz, tri, reg, regions)
+    s = orc.Scene(xyz, tri, reg, len(G.DM_REGIONS))
+    for r, (m, rho, g, fl) in enumerate(regions):
+        s.set_region(r, m, rho, g, bool(fl))
+    for m, t in tabs.items():
+        s.set_xs(m, grid, *t)
+    src = C.Source(C.KIND_POINT, pos=(0.0, 0.0, p["d5"] + p["d2"] + 250.0))
+    for E, seed in ((59.5, 71), (661.7, 72)):
+        n = 40_000_000
+        t = ctx.run(src, [E], n, seed).tallies[0]
+        assert t.n_lost == 0 and t.n_killed == 0
+        assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
+        o = s.run(src, E, 2_000_000, 1000 + seed).tally
+        m = o.n_histories
+        pg, po = t.n_fep / n, o.n_fep / m
+        sg = math.sqrt(max(pg * (1 - pg), 1 / n) / n)
+        so = math.sqrt(max(po * (1 - po), 1 / m) / m)
+        assert po > 0 and abs(pg - po) <= 3 * math.hypot(sg, so), (name, E, pg, po)

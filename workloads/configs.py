@@ -233,3 +233,46 @@ def nested_spheres(radii=(10.0, 20.0, 30.0), n_seg=48, n_rings=24):
     for i, r in enumerate(sorted(radii, reverse=True)):
         b.add(f"shell{i}", "Ge", 5.32, mg.uv_sphere(r, n_seg, n_rings))
     return b.build()
+
+
+# ----------------------------------------------------------------------------
+# parameter sets for the parametric detector generator (gadep_detmesh)
+
+# The C2 detector in Table 2 terms: end-cap r 38 on z in [-100, 5.5] (wall d3,
+# window d2 = 0.5 at d5 = 5 above the crystal), cup wall d4 = 1 with a 0.5 mm
+# gap, crystal r 32 x 60 with R_c 3, 0.7 mm dead layer, 5 mm bore 45 mm deep,
+# pin and cold finger.
+DETMESH_C2 = dict(d1=37.0, d2=0.5, d3=1.0, d4=1.0, d5=5.0, d6=3.5, d7=100.0, d8=62.0, d9=1.0,
+                  d10=1.0, D1=60.0, D2=32.0, D3=3.0, D4=0.7, D5=45.0, D6=5.0, D7=0.0003,
+                  n_theta=128, n_phi=20, z_slices=1, eps_mm=1e-3, cup_gap_mm=0.5,
+                  cup_rim_mm=-1.0, pin_radius_mm=1.0, pin_length_mm=34.0, finger_radius_mm=5.0,
+                  world_half_mm=500.0)
+
+# Table 1 crystals: diameter, length, hole diameter, hole depth, outer / inner
+# dead layer [mm] (the paper's QA numbers)
+TABLE1 = {
+    "#1 GMX45P4-76": (61.8, 61.9, 8.3, 60.0, 0.0003, 0.7),
+    "#2 GEM-C50-LB-C": (68.1, 63.3, 10.1, 50.2, 0.7, 0.0003),
+    "#3 GEM-C50P4": (67.9, 65.6, 8.5, 52.5, 0.7, 0.0003),
+    "#4 GEM-C50P4": (68.7, 65.6, 8.6, 52.0, 0.7, 0.0003),
+    "#5 GEM-C50P4": (68.5, 65.0, 8.7, 52.2, 0.7, 0.0003),
+    "#6 GMX50P4-83": (68.8, 65.8, 8.6, 52.2, 0.0003, 0.7),
+}
+
+# material of each gadep_detmesh region (world, air, housing, window, vacuum,
+# cup, crystal, active, contact, bore, pin, finger)
+DETMESH_MATERIALS = ["vacuum", "air", "Al", "Al", "vacuum", "Al", "Ge", "Ge", "Ge", "vacuum",
+                     "Cu", "Cu"]
+
+
+def table1_detmesh(name, n_theta=64, n_phi=10):
+    """gadep_detmesh parameters for a Table 1 crystal in the C2 housing,
+    widened to fit (the paper gives no housing numbers for these)."""
+    dia, length, hdia, hdepth, outer, inner = TABLE1[name]
+    D2 = dia / 2
+    p = dict(DETMESH_C2)
+    p.update(D1=length, D2=D2, D3=3.0, D4=outer, D5=hdepth, D6=hdia / 2, D7=inner,
+             d1=D2 + 5.0, d6=3.5, d8=length + 2.0, d7=length + 40.0,
+             n_theta=n_theta, n_phi=n_phi, pin_length_mm=hdepth - hdia / 2 - 8.0)
+    return p
+
