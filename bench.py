@@ -124,7 +124,22 @@ def cpu_baseline(w, target_s):
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
             "sample": f"{per_e} histories at each of the {len(w.energies)} energies "
-                      f"({n} total, {dt:.1f} s), same detector and source"}
+                      f"({n} total, {dt:.1f} s), same detector and source",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """Model name of the host CPU and the number of logical CPUs the OS reports."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} logical CPUs"
 
 
 def copy_probe():
@@ -147,8 +162,8 @@ def main():
         copy_probe()
         return
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
-              "the path shards over independent histories, see the design notes", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the transport "
+              "shards over independent histories, see the design notes", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2605_25963_amd import gadep

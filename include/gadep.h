@@ -280,6 +280,14 @@ gadep_status gadep_raycast(gadep_ctx* ctx, int32_t scene, const float* o, const 
 gadep_status gadep_locate(gadep_ctx* ctx, int32_t scene, const float* p, int64_t n,
                           int32_t* region);
 
+/* The transport kernel's random-number generator, Philox4x32-10 (Salmon et
+ * al., SC'11), run on the device for
+ * given counters: counters[n][4] (host, read only), key = k0 | k1 << 32,
+ * out[n][4] (host, written).  The kernel keys each block with the run's
+ * seed and counts (draw, history lo, history hi, unit stream). */
+gadep_status gadep_philox(gadep_ctx* ctx, const uint32_t* counters, uint64_t key, int64_t n,
+                          uint32_t* out);
+
 /* ----------------------------------------------------------------------------
  * host-only mesh preparation (no device needed) */
 

@@ -25,6 +25,8 @@ hipError_t locate_units(UnitRec* units, int n_units, const SceneRec* scenes,
 hipError_t raycast(const SceneRec& sc, const float* o, const float* d, const int32_t* region,
                    int64_t n, float* t, int32_t* tri, int32_t* region_after, hipStream_t s);
 hipError_t locate(const SceneRec& sc, const float* p, int64_t n, int32_t* region, hipStream_t s);
+hipError_t philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
+                  hipStream_t s);
 hipError_t broaden(const double* in, double* out, int n_spectra, int n, double w, double a,
                    double b, hipStream_t s);
 }  // namespace gadep
@@ -1062,6 +1064,27 @@ gadep_status gadep_raycast(gadep_ctx* ctx, int32_t scene, const float* o, const 
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   (void)hipFree(buf);
   if (e != hipSuccess) return hip_err(ctx, e, "raycast");
+  return GADEP_OK;
+}
+
+gadep_status gadep_philox(gadep_ctx* ctx, const uint32_t* counters, uint64_t key, int64_t n,
+                          uint32_t* out) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!counters || !out || n < 0) return set_err(ctx, GADEP_E_ARG, "philox: bad arguments");
+  if (n == 0) return GADEP_OK;
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  void* buf = nullptr;
+  const size_t bytes = static_cast<size_t>(n) * 16;
+  HIP_TRY(hipMalloc(&buf, 2 * bytes), "philox buffers");
+  uint32_t* d_c = static_cast<uint32_t*>(buf);
+  uint32_t* d_o = d_c + 4 * static_cast<size_t>(n);
+  hipError_t e = hipMemcpyAsync(d_c, counters, bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = philox(d_c, static_cast<uint32_t>(key), static_cast<uint32_t>(key >> 32), n, d_o, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_o, bytes, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return hip_err(ctx, e, "philox");
   return GADEP_OK;
 }
 

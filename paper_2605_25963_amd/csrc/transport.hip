@@ -767,8 +767,12 @@ transport_kernel(TransportParams P) {
           bool survivor = false;
           if (h < end_h) {
             const uint64_t hist = static_cast<uint64_t>(U.first + h);
-            const uint4 w = philox_block(0u, static_cast<uint32_t>(hist),
-                                         static_cast<uint32_t>(hist >> 32), U.stream, k0, k1);
+            // the first block of the history's stream, inline: the key and
+            // the stream id are wave-uniform, so the round keys stay scalar
+            uint32_t c0 = 0u, c1 = static_cast<uint32_t>(hist), c2 = static_cast<uint32_t>(hist >> 32),
+                     c3 = U.stream;
+            philox4x32_10(c0, c1, c2, c3, k0, k1);
+            const uint4 w = make_uint4(c0, c1, c2, c3);
             float u0 = unit_float(w.x), u1 = unit_float(w.y), u2 = unit_float(w.z);
             const float u3 = unit_float(w.w);
             float e = U.energy;
@@ -1099,6 +1103,19 @@ __global__ void locate_units_kernel(UnitRec* units, int n_units, const SceneRec*
   (void)stack_depth;
 }
 
+// Philox4x32-10 blocks of the transport kernel's generator for given counters
+__global__ void philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n,
+                              uint32_t* out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c0 = ctr[4 * i], c1 = ctr[4 * i + 1], c2 = ctr[4 * i + 2], c3 = ctr[4 * i + 3];
+  philox4x32_10(c0, c1, c2, c3, k0, k1);
+  out[4 * i] = c0;
+  out[4 * i + 1] = c1;
+  out[4 * i + 2] = c2;
+  out[4 * i + 3] = c3;
+}
+
 __global__ void raycast_kernel(SceneRec sc, const float* o, const float* d, const int32_t* region,
                                int64_t n, float* t, int32_t* tri, int32_t* region_after) {
   extern __shared__ int lstack[];
@@ -1220,6 +1237,15 @@ hipError_t raycast(const SceneRec& sc, const float* o, const float* d, const int
   const int64_t grid = (n + block - 1) / block;
   hipLaunchKernelGGL(raycast_kernel, dim3(static_cast<unsigned>(grid)), dim3(block),
                      sc.depth * block * sizeof(int), s, sc, o, d, region, n, t, tri, region_after);
+  return hipGetLastError();
+}
+
+hipError_t philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
+                  hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (n + block - 1) / block;
+  hipLaunchKernelGGL(philox_kernel, dim3(static_cast<unsigned>(grid)), dim3(block), 0, s, ctr,
+                     k0, k1, n, out);
   return hipGetLastError();
 }
 

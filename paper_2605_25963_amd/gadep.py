@@ -105,7 +105,7 @@ EXPORTS = [
     "gadep_load_mesh", "gadep_load_scene", "gadep_set_xs", "gadep_set_scales", "gadep_run",
     "gadep_run_grad", "gadep_run_batch", "gadep_autotune", "gadep_get_counters",
     "gadep_broaden_dev", "gadep_raycast", "gadep_locate", "gadep_mesh_prepare",
-    "gadep_get_last_launch_ms", "gadep_detmesh", "gadep_write_vrml",
+    "gadep_get_last_launch_ms", "gadep_detmesh", "gadep_write_vrml", "gadep_philox",
 ]
 
 _lib = None
@@ -153,6 +153,7 @@ def lib():
         "gadep_broaden_dev": (i32, [p, p, p, i32, i32, C.c_double, C.c_double, C.c_double]),
         "gadep_raycast": (i32, [p, i32, f32p, f32p, i32p, i64, f32p, i32p, i32p]),
         "gadep_locate": (i32, [p, i32, f32p, i64, i32p]),
+        "gadep_philox": (i32, [p, C.POINTER(C.c_uint32), u64, i64, C.POINTER(C.c_uint32)]),
         "gadep_mesh_prepare": (i32, [f32p, i64, i32p, i32p, i64, i32, C.c_double, i32, i32,
                                      C.c_double, i32p, i32p, p, i64, i32p, i64,
                                      C.POINTER(MeshInfo), C.c_char_p, i32]),
@@ -422,6 +423,14 @@ class Context:
                                        _ptr(out, C.c_int32)))
         return out
 
+    def philox(self, counters, key):
+        """Philox4x32-10 blocks on the device: counters [n][4] uint32, key uint64."""
+        c = np.ascontiguousarray(np.asarray(counters, np.uint32).reshape(-1, 4))
+        out = np.zeros_like(c)
+        self._check(lib().gadep_philox(self.h, _ptr(c, C.c_uint32), C.c_uint64(int(key)), len(c),
+                                       _ptr(out, C.c_uint32)))
+        return out
+
     def broaden_dev(self, in_ptr, out_ptr, n_spectra, n_channels, channel_keV, a, b):
         """in_ptr/out_ptr: device addresses (e.g. torch tensor .data_ptr()) of FP64 arrays."""
         self._check(lib().gadep_broaden_dev(self.h, C.c_void_p(in_ptr), C.c_void_p(out_ptr),
@@ -535,5 +544,6 @@ gadep_get_counters = Context.get_counters
 gadep_get_last_launch_ms = Context.get_last_launch_ms
 gadep_raycast = Context.raycast
 gadep_locate = Context.locate
+gadep_philox = Context.philox
 gadep_broaden_dev = Context.broaden_dev
 gadep_mesh_prepare = mesh_prepare
