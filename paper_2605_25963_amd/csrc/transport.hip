@@ -264,6 +264,7 @@ enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3, kSample = 4, k
                    kResume = 6 };
 constexpr int kMaxEmitAttempts = 1000;  // volume-source rejection tries per history
 constexpr int kQueue = 128;             // screened histories a wavefront can hold
+constexpr int kSlow = 128;              // set-aside short first flights a wavefront can hold
 constexpr int kXcds = 8;                // accelerator dies (XCDs) of an MI355X, one L2 each
 // probe direction for localising volume-source points (generic: no axis or
 // facet plane of the synthetic meshes is parallel to it)
@@ -286,16 +287,18 @@ transport_kernel(TransportParams P) {
   const int stride = static_cast<int>(blockDim.x);
   // per-history scores of the scale groups, one LDS column per thread
   float* sc = reinterpret_cast<float*>(stack) + P.stack_depth * stride;
-  // per-wavefront queue of screened histories that need full transport
-  int64_t* queue = reinterpret_cast<int64_t*>(
-                       reinterpret_cast<char*>(smem + nwaves * kT_Slots) +
-                       static_cast<size_t>(P.stack_depth) * stride * sizeof(int) +
-                       (GRAD ? static_cast<size_t>(kMaxGroups) * stride * sizeof(float) : 0)) +
-                   wave * kQueue;
+  // per-wavefront queues of screened histories: those that need full
+  // transport, and short first flights set aside for the exact exit test
+  int64_t* const qbase = reinterpret_cast<int64_t*>(
+      reinterpret_cast<char*>(smem + nwaves * kT_Slots) +
+      static_cast<size_t>(P.stack_depth) * stride * sizeof(int) +
+      (GRAD ? static_cast<size_t>(kMaxGroups) * stride * sizeof(float) : 0));
+  int64_t* queue = qbase + wave * kQueue;
+  int64_t* slow = qbase + nwaves * kQueue + wave * kSlow;
   // the second annihilation photon of a pair event, waiting for the first to
   // be done: x, y, z, dx, dy, dz (as bits), region (< 0: none); one LDS
   // column per thread (only allocated when some material has a pair partial)
-  int* wait = reinterpret_cast<int*>(queue - wave * kQueue + nwaves * kQueue) + threadIdx.x;
+  int* wait = reinterpret_cast<int*>(qbase + nwaves * (kQueue + kSlow)) + threadIdx.x;
   if (PAIR) wait[6 * stride] = -1;
   for (int i = lane; i < kT_Slots; i += kWave) wt[i] = 0;
 
@@ -342,6 +345,7 @@ transport_kernel(TransportParams P) {
   // first-flight screening (see the refill below) and its queue
   bool screen = false;
   int q_head = 0, q_n = 0;
+  int s_head = 0, s_n = 0;
   // a screened history whose first optical depth reaches scr_tau cannot end
   // its first flight before leaving the outermost shell (INFINITY: always
   // evaluate the flight; see the unit change below)
@@ -719,7 +723,7 @@ transport_kernel(TransportParams P) {
           // a chunk of another unit starts only when no history of this one
           // is open or queued
           if (next_h >= end_h && pend >= 0 &&
-              (pend == cur || (q_n == 0 && __ballot(phase != kNeed) == 0))) {
+              (pend == cur || (q_n == 0 && s_n == 0 && __ballot(phase != kNeed) == 0))) {
             if (pend != cur) {
               flush();
               cur = pend;
@@ -755,26 +759,40 @@ transport_kernel(TransportParams P) {
             end_h = pend_h1;
             pend = -1;
           }
-          if (!(screen && q_n < n_need && next_h < end_h)) break;
+          if (!(screen && q_n < n_need)) break;
           // ---- first-flight screening: every lane takes one of the next 64
           // histories and follows it to the end of its first flight.  Those
           // that leave the outermost shell through its planes without coming
           // near the inner shells (the common case for a distant source) are
           // tallied here; the rest are queued for full transport, which
-          // repeats the same draws and arithmetic.
-          const int64_t h = next_h + lane;
-          next_h = next_h + kWave < end_h ? next_h + kWave : end_h;
-          bool survivor = false;
-          if (h < end_h) {
+          // repeats the same draws and arithmetic.  A flight whose optical
+          // depth is long enough to cross the whole shell (almost all of them)
+          // is settled by one box test; the few shorter ones are set aside in
+          // a second queue and settled exactly, by the exit planes, 64 at a
+          // time, so that their rare branch runs with full wavefronts.
+          const bool exact = s_n >= kWave || (next_h >= end_h && s_n > 0);
+          if (!exact && next_h >= end_h) break;
+          int64_t h = -1;
+          if (exact) {
+            if (lane < s_n) h = slow[(s_head + lane) & (kSlow - 1)];
+            __builtin_amdgcn_wave_barrier();
+            const int taken = s_n < kWave ? s_n : kWave;
+            s_head = (s_head + taken) & (kSlow - 1);
+            s_n -= taken;
+          } else {
+            h = next_h + lane < end_h ? next_h + lane : -1;
+            next_h = next_h + kWave < end_h ? next_h + kWave : end_h;
+          }
+          bool survivor = false, defer = false;
+          if (h >= 0) {
             const uint64_t hist = static_cast<uint64_t>(U.first + h);
             // the first block of the history's stream, inline: the key and
             // the stream id are wave-uniform, so the round keys stay scalar
             uint32_t c0 = 0u, c1 = static_cast<uint32_t>(hist), c2 = static_cast<uint32_t>(hist >> 32),
                      c3 = U.stream;
             philox4x32_10(c0, c1, c2, c3, k0, k1);
-            const uint4 w = make_uint4(c0, c1, c2, c3);
-            float u0 = unit_float(w.x), u1 = unit_float(w.y), u2 = unit_float(w.z);
-            const float u3 = unit_float(w.w);
+            float u0 = unit_float(c0), u1 = unit_float(c1), u2 = unit_float(c2);
+            const float u3 = unit_float(c3);
             float e = U.energy;
             if (Src.n_lines > 0) {
               const float2* L = reinterpret_cast<const float2*>(P.lines) + Src.line_off;
@@ -800,15 +818,15 @@ transport_kernel(TransportParams P) {
             }
             const float tau0 = -hw_log(u0);
             const float ox = Src.pos[0], oy = Src.pos[1], oz = Src.pos[2];
-            bool escapes;
-            float te;
+            bool escapes = false;
+            float te = scr_far;
+            // the flight outlasts the shell (the common case): no need for
+            // the attenuation or the exit distance, only for the box test
             const bool settled = tau0 >= scr_tau;
             if (settled) {
-              // the flight outlasts the shell (the common case): no need for
-              // the attenuation or the exit distance, only for the box test
               escapes = true;
-              te = scr_far;
-            } else {
+            } else if (exact || scr_m < 0.0f) {
+              // (with a line spectrum nothing is settled early: no deferral)
               float m = scr_m;  // the unit's, for a fixed energy
               if (m < 0.0f) {
                 const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
@@ -827,6 +845,8 @@ transport_kernel(TransportParams P) {
               }
               te = fmaxf(te, 0.0f);
               escapes = te <= tfl;
+            } else {
+              defer = true;
             }
             if (escapes && S.trans_lo[0] <= S.trans_hi[0]) {
               const Ray r0 = make_ray(ox, oy, oz, qx, qy, qz);
@@ -848,7 +868,7 @@ transport_kernel(TransportParams P) {
                   ev[kEv_PlaneTests] += S.n_planes;
                 }
               }
-            } else {
+            } else if (!defer) {
               survivor = true;
             }
           }
@@ -857,8 +877,14 @@ transport_kernel(TransportParams P) {
             const int rank = __popcll(surv & ((1ull << lane) - 1ull));
             queue[(q_head + q_n + rank) & (kQueue - 1)] = h;
           }
+          const uint64_t dfr = __ballot(defer);
+          if (defer) {
+            const int rank = __popcll(dfr & ((1ull << lane) - 1ull));
+            slow[(s_head + s_n + rank) & (kSlow - 1)] = h;
+          }
           __builtin_amdgcn_wave_barrier();
           q_n += __popcll(surv);
+          s_n += __popcll(dfr);
         }
         // hand out histories: from the queue when screening, else in order
         const uint64_t below = need & ((1ull << lane) - 1ull);
@@ -985,7 +1011,8 @@ transport_kernel(TransportParams P) {
         phase = node == kDone ? kParked : kTrav;
       }
       lap(kEv_CycSetup);
-      if (__ballot(phase != kNeed) == 0 && exhausted && pend < 0 && next_h >= end_h && q_n == 0)
+      if (__ballot(phase != kNeed) == 0 && exhausted && pend < 0 && next_h >= end_h && q_n == 0 &&
+          s_n == 0)
         break;
     }
 
@@ -1197,7 +1224,7 @@ size_t transport_smem(int block, int depth, bool grad, bool pair) {
   return static_cast<size_t>(block / kWave) * kT_Slots * sizeof(unsigned long long) +
          static_cast<size_t>(depth) * block * sizeof(int) +
          (grad ? static_cast<size_t>(kMaxGroups) * block * sizeof(float) : 0) +
-         static_cast<size_t>(block / kWave) * kQueue * sizeof(int64_t) +
+         static_cast<size_t>(block / kWave) * (kQueue + kSlow) * sizeof(int64_t) +
          (pair ? static_cast<size_t>(7) * block * sizeof(int) : 0);
 }
 
