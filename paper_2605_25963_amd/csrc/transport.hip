@@ -293,8 +293,8 @@ transport_kernel(TransportParams P) {
       reinterpret_cast<char*>(smem + nwaves * kT_Slots) +
       static_cast<size_t>(P.stack_depth) * stride * sizeof(int) +
       (GRAD ? static_cast<size_t>(kMaxGroups) * stride * sizeof(float) : 0));
-  int64_t* queue = qbase + wave * kQueue;
-  int64_t* slow = qbase + nwaves * kQueue + wave * kSlow;
+  int64_t* queue = qbase + wave * (kQueue + kSlow);
+  int64_t* slow = queue + kQueue;  // (a constant offset from queue: no register of its own)
   // the second annihilation photon of a pair event, waiting for the first to
   // be done: x, y, z, dx, dy, dz (as bits), region (< 0: none); one LDS
   // column per thread (only allocated when some material has a pair partial)
