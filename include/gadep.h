@@ -75,7 +75,7 @@ typedef enum {
                                  traversal wait until this many (1..64) have, then the
                                  wavefront runs physics, scoring and new histories for
                                  all of them together; 0 = default (24)                */
-  GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim (8)        */
+  GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim (16)       */
   GADEP_OPT_VALIDATE = 5,     /* 1 = validate meshes at load (default); 0 skips the
                                  closed/orientation/overlap checks (fault-injection
                                  tests only: results are undefined on a bad mesh)      */

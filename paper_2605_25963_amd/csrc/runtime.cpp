@@ -109,7 +109,7 @@ struct gadep_ctx {
   int64_t max_steps = 10000;
   int64_t block = 256;
   int64_t period = 0;
-  int64_t claim = 8;
+  int64_t claim = 16;
   int64_t validate = 1;
   int64_t min_gap_nm = 100;
   int64_t graphs = 1;
@@ -962,7 +962,7 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
   // block size x claim size x park threshold (lanes parked before the wavefront
   // runs the batched physics); tallies do not depend on any of them
   const int64_t blocks[] = {128, 256};
-  const int64_t claims[] = {8, 32};
+  const int64_t claims[] = {16, 64};
   const int64_t periods[] = {16, 24, 32};
   for (int64_t b : blocks)
     for (int64_t c : claims)

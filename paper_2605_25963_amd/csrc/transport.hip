@@ -280,7 +280,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
 transport_kernel(TransportParams P) {
   extern __shared__ unsigned long long smem[];
   const int lane = static_cast<int>(__lane_id());
-  const int wave = static_cast<int>(threadIdx.x) / kWave;
+  // wave-uniform: its LDS areas (tally, queues) are then addressed from scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int nwaves = static_cast<int>(blockDim.x) / kWave;
   unsigned long long* wt = smem + wave * kT_Slots;  // this wavefront's tally
   int* stack = reinterpret_cast<int*>(smem + nwaves * kT_Slots) + threadIdx.x;

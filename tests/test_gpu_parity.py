@@ -268,7 +268,7 @@ def test_tallies_independent_of_launch_shape_and_split(G, ctx):
     ctx.set_option(G.OPT_GRAPHS, 0)
     eager = run()
     ctx.set_option(G.OPT_BLOCK, 256)
-    ctx.set_option(G.OPT_CLAIM, 8)
+    ctx.set_option(G.OPT_CLAIM, 16)
     ctx.set_option(G.OPT_GRAPHS, 1)
     a = run(0, n // 3)
     b = run(n // 3, n - n // 3)

@@ -208,7 +208,7 @@ def test_autotune_and_graph_replay_keep_tallies(G, ctx):
     job = [dict(source=w.source, energies=[80.0, 700.0], n_histories=2_000_000, stream=3)]
     base = ctx.run_batch(job, 71)
     block, period, claim = ctx.autotune(job, 400_000)
-    assert block in (128, 256) and period in (16, 24, 32) and claim in (8, 32)
+    assert block in (128, 256) and period in (16, 24, 32) and claim in (16, 64)
     assert ctx.get_option(G.OPT_BLOCK) == block
     tuned = ctx.run_batch(job, 71)
     replays = [ctx.run_batch(job, 71) for _ in range(3)]
@@ -220,7 +220,7 @@ def test_autotune_and_graph_replay_keep_tallies(G, ctx):
         for f in ("n_histories", "n_fep", "n_absorbed", "n_uncollided", "edep_active_keV"):
             assert np.array_equal(base.field(f), other.field(f)), f
     ctx.set_option(G.OPT_BLOCK, 256)
-    ctx.set_option(G.OPT_CLAIM, 8)
+    ctx.set_option(G.OPT_CLAIM, 16)
     ctx.set_option(G.OPT_PERIOD, 0)
 
 
