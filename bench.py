@@ -60,8 +60,8 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNEL_SOURCES = ["paper_2605_25963_amd/csrc/transport.hip",
                   "paper_2605_25963_amd/csrc/device_common.h",
                   "paper_2605_25963_amd/csrc/gadep_internal.h"]
-MEASURED_TRAFFIC = {"sources_sha256": "0db06790a1af43640f01ee6dbfda92340c2e669e9572ae865099ac92e5ca15e0",
-                    "bytes_per_launch": 1.710e9}
+MEASURED_TRAFFIC = {"sources_sha256": "9b0f7be36402c3d6ca31dab5da8796ecb77f3a2e58abf9416e34d473485a9c3d",
+                    "bytes_per_launch": 9.24e7}
 
 
 def measured_traffic():
