@@ -325,11 +325,15 @@ def test_exit_planes_agree_with_facet_exit(G, ctx, orc, where):
         assert sigma3(pg, math.sqrt(pg * (1 - pg) / n), o.fepe(), o.fepe_sigma()), (e, pg, o.fepe())
 
 
-@pytest.mark.parametrize("case", ["point", "lines", "grad"])
+@pytest.mark.parametrize("case", ["point", "lines", "grad", "set_aside"])
 def test_first_flight_screening_is_exact(G, ctx, case):
     # Screening tallies the histories that leave the air box on their first
     # flight without nearing the detector, and repeats the same draws and
     # arithmetic as full transport: every tally must be identical with it off.
+    # "set_aside": low energies, where air attenuation leaves most first
+    # flights too short to settle by the box test alone (they go through the
+    # set-aside queue), and one-chunk claims, so that the queue is emptied at
+    # many chunk and unit boundaries.
     w = C.c2_hpge(n_histories=1)
     loaded(G, ctx, w)
     src, E = w.source, [60.0, 661.7]
@@ -337,15 +341,22 @@ def test_first_flight_screening_is_exact(G, ctx, case):
         src = C.Source(C.KIND_POINT, pos=w.source.pos, lines_keV=[59.54, 661.66, 1332.5],
                        lines_prob=[0.36, 0.85, 1.0])
         E = None
+    if case == "set_aside":
+        E = [5.0, 12.0, 25.0, 40.0]
     n = 3_000_000
 
     def run(on):
         ctx.set_option(G.OPT_SCREEN, on)
-        if case == "grad":
-            r = ctx.run_grad(src, E, n, 91, scales=[1.0] * len(w.groups))
-        else:
-            r = ctx.run(src, E, n, 91, spectrum=(1024, 2.0))
-        ctx.set_option(G.OPT_SCREEN, 1)
+        if case == "set_aside":
+            ctx.set_option(G.OPT_CLAIM, 1)
+        try:
+            if case == "grad":
+                r = ctx.run_grad(src, E, n, 91, scales=[1.0] * len(w.groups))
+            else:
+                r = ctx.run(src, E, n, 91, spectrum=(1024, 2.0))
+        finally:
+            ctx.set_option(G.OPT_SCREEN, 1)
+            ctx.set_option(G.OPT_CLAIM, 16)
         return r
 
     off, on = run(0), run(1)
