@@ -267,6 +267,12 @@ def main():
                    "max_fepe_rse": float(rse.max())},
         "fwd_grad_over_fwd": fwd_grad_ratio,
         "fepe": [float(x) for x in fepe],
+        # per-event rates of the timed kernel (event counts of the same histories)
+        "rates": {"node_visits_per_s": ev["node_visits"] / (k_ms * 1e-3),
+                  "facet_tests_per_s": ev["tri_tests"] / (k_ms * 1e-3),
+                  "interactions_per_s": (ev["photo"] + ev["compton"] + ev["coherent"] + ev["pair"])
+                  / (k_ms * 1e-3),
+                  "segments_per_s": ev["segments"] / (k_ms * 1e-3)},
         "roofline": roof,
         "cpu_baseline": base,
     }
