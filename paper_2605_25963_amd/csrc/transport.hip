@@ -1018,41 +1018,13 @@ transport_kernel(TransportParams P) {
     }
 
     // ================= one traversal step per traversing lane =================
-    // the facets of a pending leaf first (one per step), else one node
+    // one node when no facet is pending, then one facet of a pending leaf: a
+    // lane whose node step reaches a leaf tests its first facet in the same
+    // iteration (every iteration runs both kinds of step for some lanes)
     bool did_node = false, did_tri = false;
     const uint64_t clk_trav = COUNT ? __builtin_amdgcn_s_memtime() : 0;
     if (phase == kTrav) {
-      if (tri_next >= tri_end && node < 0 && node != kDone) {
-        const int code = ~node;  // a leaf taken from the stack
-        tri_next = code >> 3;
-        tri_end = tri_next + (code & 7);
-        node = sp > 0 ? stack[sp -= stride] : kDone;
-      }
-      if (tri_next < tri_end) {
-        // one facet test, with the region-consistency filter; the facet just
-        // crossed is skipped (by its caller id: it may have several slots)
-        const int slot = tri_next++;
-        if (COUNT) ev[kEv_TriTests]++;
-        did_tri = true;
-        float4 a, b, c;
-        load_tri(S.tris, gload(S.slots, slot), a, b, c);
-        const int id = __float_as_int(c.z);
-        float t;
-        bool enter;
-        if (id != last && wt_test(ray, px, py, pz, dx, dy, dz, a, b, c, tbest, t, enter) != kWtMiss) {
-          const uint32_t regs = __float_as_uint(c.y);
-          const int inside = static_cast<int>(regs & 0xFFFFu);
-          const int outside = static_cast<int>(regs >> 16);
-          const int before = enter ? outside : inside;
-          if (region >= 0 && before != region) {
-            trej = fminf(trej, t);
-          } else {
-            tbest = t;
-            best_id = id;
-            best_reg = (enter ? inside : outside) | (before << 8);  // after | before << 8
-          }
-        }
-      } else if (node >= 0) {
+      if (tri_next >= tri_end && node >= 0) {
         // one node: both child boxes against [0, tbest]
         if (COUNT) ev[kEv_NodeVisits]++;
         did_node = true;
@@ -1086,6 +1058,37 @@ transport_kernel(TransportParams P) {
             sp += stride;
           }
           node = near;
+        }
+      }
+      if (tri_next >= tri_end && node < 0 && node != kDone) {
+        const int code = ~node;  // a leaf taken from the stack
+        tri_next = code >> 3;
+        tri_end = tri_next + (code & 7);
+        node = sp > 0 ? stack[sp -= stride] : kDone;
+      }
+      if (tri_next < tri_end) {
+        // one facet test, with the region-consistency filter; the facet just
+        // crossed is skipped (by its caller id: it may have several slots)
+        const int slot = tri_next++;
+        if (COUNT) ev[kEv_TriTests]++;
+        did_tri = true;
+        float4 a, b, c;
+        load_tri(S.tris, gload(S.slots, slot), a, b, c);
+        const int id = __float_as_int(c.z);
+        float t;
+        bool enter;
+        if (id != last && wt_test(ray, px, py, pz, dx, dy, dz, a, b, c, tbest, t, enter) != kWtMiss) {
+          const uint32_t regs = __float_as_uint(c.y);
+          const int inside = static_cast<int>(regs & 0xFFFFu);
+          const int outside = static_cast<int>(regs >> 16);
+          const int before = enter ? outside : inside;
+          if (region >= 0 && before != region) {
+            trej = fminf(trej, t);
+          } else {
+            tbest = t;
+            best_id = id;
+            best_reg = (enter ? inside : outside) | (before << 8);  // after | before << 8
+          }
         }
       }
       if (tri_next >= tri_end && node == kDone) phase = kParked;
