@@ -354,7 +354,7 @@ def bench_c4(a, torch, gadep, C):
     total = w.n_histories * len(w.energies)
     dt, k_ms = _timed(ctx, torch, lambda: ctx.run_batch(J, 1004), a.steps, a.warmup)
     dtg, kg_ms = _timed(ctx, torch, lambda: ctx.run_batch(JG, 1004, grad=True), a.steps, a.warmup)
-    return _line("histories/s, C2 detector + water sample, volume source, 20 energies",
+    return _line("histories/s, 20236-facet HPGe detector + water sample, volume source, 20 energies",
                  total / dt, "histories/s", a, dt, "c4_hpge_water_sample_volume_source_20_energies",
                  {"histories_per_step": total, "kernel_ms": k_ms, "grad_kernel_ms": kg_ms,
                   "fwd_grad_over_fwd": dtg / dt,

@@ -1,7 +1,7 @@
 """DetMesh-style parametric detector meshes (gadep_detmesh, gadep_write_vrml),
 host only: the Table 2 parameter groups turned into closed shells that the
 validator accepts, nested as declared, with Eq. 1-4 vertices and the Eq. 6
-active volume; the C2 detector's parameters reproduce the independently
+active volume; the 20236-facet coaxial detector's parameters reproduce the independently
 written fixture generator shell for shell; Table 1's crystals; VRML output."""
 import math
 import os

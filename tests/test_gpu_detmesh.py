@@ -1,6 +1,6 @@
 """Transport on the GPU through detectors built by the parametric generator
-(gadep_detmesh, in memory as in Sec. 2.4): Table 1 crystals in the C2
-housing, point source 250 mm above the window, against the oracle."""
+(gadep_detmesh, in memory as in Sec. 2.4): Table 1 crystals in the 20236-facet
+detector's housing, point source 250 mm above the window, against the oracle."""
 import math
 
 import numpy as np

@@ -1,6 +1,6 @@
 """Pair production with annihilation on the GPU (Sec. 2.4.1 lists it among the
 photon interactions), through the C interface: the double-escape line and the
-full-absorption FEPE of a pair-only slab (closed forms), and the C2 detector at
+full-absorption FEPE of a pair-only slab (closed forms), and the 20236-facet HPGe detector at
 2 MeV with synthetic pair partials against the oracle.  Runs without a pair
 partial are covered, unchanged, by the other GPU tests."""
 import math
@@ -87,7 +87,7 @@ def test_pair_full_absorption(G, ctx):
 
 
 def test_c2_detector_with_pairs_matches_oracle(G, ctx, orc):
-    # the C2 detector at 2 MeV and 1.4 MeV with synthetic pair partials in
+    # the 20236-facet HPGe detector at 2 MeV and 1.4 MeV with synthetic pair partials in
     # every material; 100 mm source for more detector events
     w = C.c2_hpge(n_histories=1, distance=100.0)
     w.tables, w.grid = C._tables_for(w.materials, coherent=False, pair=True)

@@ -226,7 +226,7 @@ def test_c1_fepe_and_spectrum_match_oracle(G, ctx, orc):
 
 
 def test_c2_near_source_matches_oracle(G, ctx, orc):
-    # C2 detector, point source 20 mm above the end-cap: many photons enter
+    # 20236-facet HPGe detector, point source 20 mm above the end-cap: many photons enter
     w = C.c2_hpge(n_histories=1, distance=20.0)
     loaded(G, ctx, w)
     s = orc.scene_from_workload(w)

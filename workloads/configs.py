@@ -150,7 +150,7 @@ def c2_hpge(n_histories=100_000_000, seed=1002, n_seg=128, n_phi=20, distance=25
 
 
 def c3_jobs(n_jobs=64, seed=3003):
-    """Per-job bottle geometry, matrix, density and history count (C3)."""
+    """Per-job bottle geometry, matrix, density and history count (64 bottle jobs on the 256-facet crystal)."""
     rng = np.random.default_rng(seed)
     jobs = []
     for j in range(n_jobs):
@@ -238,7 +238,7 @@ def nested_spheres(radii=(10.0, 20.0, 30.0), n_seg=48, n_rings=24):
 # ----------------------------------------------------------------------------
 # parameter sets for the parametric detector generator (gadep_detmesh)
 
-# The C2 detector in Table 2 terms: end-cap r 38 on z in [-100, 5.5] (wall d3,
+# The 20236-facet coaxial HPGe detector in Table 2 terms: end-cap r 38 on z in [-100, 5.5] (wall d3,
 # window d2 = 0.5 at d5 = 5 above the crystal), cup wall d4 = 1 with a 0.5 mm
 # gap, crystal r 32 x 60 with R_c 3, 0.7 mm dead layer, 5 mm bore 45 mm deep,
 # pin and cold finger.
@@ -266,7 +266,7 @@ DETMESH_MATERIALS = ["vacuum", "air", "Al", "Al", "vacuum", "Al", "Ge", "Ge", "G
 
 
 def table1_detmesh(name, n_theta=64, n_phi=10):
-    """gadep_detmesh parameters for a Table 1 crystal in the C2 housing,
+    """gadep_detmesh parameters for a Table 1 crystal in the housing of the 20236-facet detector,
     widened to fit (the paper gives no housing numbers for these)."""
     dia, length, hdia, hdepth, outer, inner = TABLE1[name]
     D2 = dia / 2
