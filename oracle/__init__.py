@@ -79,6 +79,10 @@ def lib():
                               C.c_uint64, C.c_uint32, dp, C.c_int32, C.c_int32, C.c_double,
                               C.POINTER(C.c_uint64), C.c_int32, C.c_int32, C.POINTER(Tally)]
         L.orc_broaden.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_rotate.argtypes = [dp, C.c_double, C.c_double, dp]
+        L.orc_emission.restype = C.c_int32
+        L.orc_emission.argtypes = [C.c_void_p, C.POINTER(Source), C.c_uint64, C.c_uint32, C.c_int64,
+                                   dp, dp, C.POINTER(C.c_int32)]
         _lib = L
     return _lib
 
@@ -109,6 +113,14 @@ def kn_sample(k, u):
 
 def thomson_sample(u):
     return lib().orc_thomson_sample(u)
+
+
+def rotate(d, ct, phi):
+    """Direction after a scattering of polar cosine ct and azimuth phi about unit d."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_rotate(_dp(d), float(ct), float(phi), _dp(out))
+    return out
 
 
 def broaden(spectrum, channel_keV, a, b):
@@ -197,6 +209,20 @@ class Scene:
         lib().orc_mu(self.h, region, E, None if sc is None else _dp(sc),
                      0 if sc is None else len(sc), _dp(out))
         return out
+
+    def emission(self, source, seed, history, unit=0):
+        """(energy, point, tries) of one history's emission step as transport draws it
+        (energy 0 for a mono-energetic source; tries 0: every rejection try failed)."""
+        E = C.c_double()
+        p = np.zeros(3)
+        tries = C.c_int32()
+        src, keep = _make_source(source)
+        rc = lib().orc_emission(self.h, C.byref(src), int(seed), int(unit), int(history), C.byref(E),
+                                _dp(p), C.byref(tries))
+        del keep
+        if rc:
+            raise ValueError(f"oracle: emission -> {rc}")
+        return E.value, p, tries.value
 
     def run(self, source, E0, n, seed, unit=0, first=0, scales=None, n_channels=0,
             channel_keV=0.25, max_steps=10000, threads=None):

@@ -538,27 +538,38 @@ double orc_thomson_sample(double u) {
   return 0.5 * (lo + hi);
 }
 
-/* new direction at polar angle theta (cos ct) and azimuth phi about d */
+/* New direction at polar angle theta (cos ct) and azimuth phi about the
+ * unit direction d, by the classic direction-cosine formula
+ *   d' = d ct + st (cos phi (w d - z) + sin phi (z x d)) / sqrt(1 - w^2)
+ * about the coordinate axis z; the frame is relabelled so that this axis
+ * is the one d is least aligned with (|w| <= 1/sqrt 3), where the formula is
+ * well conditioned, so no direction is ever treated as lying on an axis. */
 static void rotate(double* d, double ct, double phi) {
   double st = sqrt(fmax(0.0, 1.0 - ct * ct));
   double cp = cos(phi), sp = sin(phi);
-  double u = d[0], v = d[1], w = d[2];
-  double nu, nv, nw;
-  if (fabs(w) < 0.99999) {
-    double q = sqrt(1.0 - w * w);
-    nu = u * ct + st * (u * w * cp - v * sp) / q;
-    nv = v * ct + st * (v * w * cp + u * sp) / q;
-    nw = w * ct - st * cp * q;
-  } else {
-    double sg = w > 0 ? 1.0 : -1.0;
-    nu = st * cp;
-    nv = st * sp;
-    nw = sg * ct;
-  }
+  /* axis of the formula: the smallest component of d; (a, b, c) is a cyclic
+   * relabelling of (x, y, z) that puts it last */
+  int c = 2;
+  if (fabs(d[0]) <= fabs(d[1]) && fabs(d[0]) <= fabs(d[2]))
+    c = 0;
+  else if (fabs(d[1]) <= fabs(d[2]))
+    c = 1;
+  int a = (c + 1) % 3, b = (c + 2) % 3;
+  double u = d[a], v = d[b], w = d[c];
+  double q = sqrt(1.0 - w * w);
+  double nu = u * ct + st * (u * w * cp - v * sp) / q;
+  double nv = v * ct + st * (v * w * cp + u * sp) / q;
+  double nw = w * ct - st * cp * q;
   double nn = sqrt(nu * nu + nv * nv + nw * nw);
-  d[0] = nu / nn;
-  d[1] = nv / nn;
-  d[2] = nw / nn;
+  d[a] = nu / nn;
+  d[b] = nv / nn;
+  d[c] = nw / nn;
+}
+
+void orc_rotate(const double d[3], double ct, double phi, double out[3]) {
+  double v[3] = {d[0], d[1], d[2]};
+  rotate(v, ct, phi);
+  memcpy(out, v, sizeof v);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -581,6 +592,40 @@ typedef struct {
   orc_tally tally;
 } worker;
 
+/* Energy of a line source: line i with probability line_prob[i] / sum. */
+static double draw_line(const orc_source* src, orc_rng* g) {
+  double tot = 0;
+  for (int i = 0; i < src->n_lines; ++i) tot += src->line_prob[i];
+  double x = rng_uniform(g) * tot, c = 0;
+  int pick = src->n_lines - 1;
+  for (int i = 0; i < src->n_lines; ++i) {
+    c += src->line_prob[i];
+    if (x < c) {
+      pick = i;
+      break;
+    }
+  }
+  return src->line_keV[pick];
+}
+
+/* A point uniform in the source's cylindrical annulus r_in <= r <= r_out,
+ * 0 <= z <= h (the area element r dr makes r^2 uniform), kept only when the
+ * parity rule puts it in the source region: the accepted points are uniform
+ * in the faceted region.  Returns the number of tries used, 0 when all 1000
+ * failed. */
+static int volume_point(const orc_scene* s, const orc_source* src, orc_rng* g, double p[3]) {
+  for (int attempt = 1; attempt <= 1000; ++attempt) {
+    double r2lo = src->r_in * src->r_in, r2hi = src->r_out * src->r_out;
+    double r = sqrt(r2lo + rng_uniform(g) * (r2hi - r2lo));
+    double ph = 2.0 * PI * rng_uniform(g);
+    p[0] = src->pos[0] + r * cos(ph);
+    p[1] = src->pos[1] + r * sin(ph);
+    p[2] = src->pos[2] + rng_uniform(g) * src->h;
+    if (orc_locate(s, p) == src->region) return attempt;
+  }
+  return 0;
+}
+
 static void isotropic(orc_rng* g, double* d) {
   double ct = 2.0 * rng_uniform(g) - 1.0;
   double ph = 2.0 * PI * rng_uniform(g);
@@ -601,36 +646,11 @@ static void one_history(worker* w, int64_t h) {
   double p[3], d[3], E;
   int32_t region;
   /* energy */
-  if (src->n_lines > 0) {
-    double tot = 0;
-    for (int i = 0; i < src->n_lines; ++i) tot += src->line_prob[i];
-    double x = rng_uniform(&g) * tot, c = 0;
-    int pick = src->n_lines - 1;
-    for (int i = 0; i < src->n_lines; ++i) {
-      c += src->line_prob[i];
-      if (x < c) {
-        pick = i;
-        break;
-      }
-    }
-    E = src->line_keV[pick];
-  } else {
-    E = w->E0;
-  }
+  E = src->n_lines > 0 ? draw_line(src, &g) : w->E0;
   const double E0 = E;
   /* position, direction, region */
   if (src->kind == ORC_CYL) {
-    int ok = 0;
-    for (int attempt = 0; attempt < 1000 && !ok; ++attempt) {
-      double r2lo = src->r_in * src->r_in, r2hi = src->r_out * src->r_out;
-      double r = sqrt(r2lo + rng_uniform(&g) * (r2hi - r2lo));
-      double ph = 2.0 * PI * rng_uniform(&g);
-      p[0] = src->pos[0] + r * cos(ph);
-      p[1] = src->pos[1] + r * sin(ph);
-      p[2] = src->pos[2] + rng_uniform(&g) * src->h;
-      ok = orc_locate(s, p) == src->region;
-    }
-    if (!ok) {
+    if (volume_point(s, src, &g, p) == 0) {
       T->n_source_fail++;
       return;
     }
@@ -826,6 +846,21 @@ static void one_history(worker* w, int64_t h) {
       T->sum_fep_score2[gi] += sc * sc;
     }
   }
+}
+
+int32_t orc_emission(const orc_scene* s, const orc_source* src, uint64_t seed, uint32_t unit,
+                     int64_t history, double* E, double p[3], int32_t* attempts) {
+  if (!s || !src || !E || !p || !attempts || history < 0) return -1;
+  orc_rng g;
+  rng_init(&g, seed, (uint64_t)history, unit);
+  *E = src->n_lines > 0 ? draw_line(src, &g) : 0.0;
+  if (src->kind == ORC_CYL) {
+    *attempts = volume_point(s, src, &g, p);
+  } else {
+    memcpy(p, src->pos, 3 * sizeof(double));
+    *attempts = 1;
+  }
+  return 0;
 }
 
 static void* worker_main(void* arg) {

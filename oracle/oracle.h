@@ -71,6 +71,9 @@ double orc_kn_integral(double k, double eps);    /* antiderivative of the bracke
 double orc_kn_sigma(double k);                   /* total, cm^2 per electron */
 double orc_kn_sample(double k, double u);        /* inverse CDF, u in (0,1) */
 double orc_thomson_sample(double u);             /* cos(theta) from 3/8 (1 + mu^2) */
+/* The direction after a scattering of polar cosine ct and azimuth phi about
+ * the unit direction d (the rotation used by transport). */
+void orc_rotate(const double d[3], double ct, double phi, double out[3]);
 
 enum { ORC_POINT = 0, ORC_BEAM = 1, ORC_CYL = 2 };
 typedef struct {
@@ -94,6 +97,13 @@ typedef struct {
   double sum_fep_score[ORC_MAX_GROUPS];
   double sum_fep_score2[ORC_MAX_GROUPS];
 } orc_tally;
+
+/* The emission step of history `history` of unit `unit` exactly as transport
+ * draws it: the line energy (E = 0 for a mono-energetic source) and the
+ * emission point; for a CYL source the number of rejection tries used
+ * (0: all 1000 failed), else 1.  Returns 0, or -1 on bad arguments. */
+int32_t orc_emission(const orc_scene* s, const orc_source* src, uint64_t seed, uint32_t unit,
+                     int64_t history, double* E, double p[3], int32_t* attempts);
 
 /* Histories first .. first+n-1 of unit `unit`.  scales[n_groups] multiply the
  * density of every region in the group.  spectrum (nullable) has n_channels

@@ -521,3 +521,214 @@ def test_grazing_crossings_keep_their_region(orc):
     t = r.tally
     assert t.n_lost == 0 and t.n_balance_fail == 0
     assert t.n_crossings >= 2 * t.n_escape
+
+
+# --------------------------------------------------------------------------
+# scattering rotation, volume emission, line draw, annihilation axis
+
+def _unit(v):
+    v = np.asarray(v, float)
+    return v / np.linalg.norm(v)
+
+
+ROT_DIRS = [(0, 0, 1), (0, 0, -1), (1, 0, 0), (0, -1, 0),
+            # |w| above and below the 0.99999 switch to the pole branch
+            (math.sqrt(1 - 0.999995 ** 2), 0, 0.999995), (0, math.sqrt(1 - 0.99998 ** 2), -0.99998),
+            (0.3, -0.5, 0.81), (-0.7, 0.1, -0.2)]
+
+
+@pytest.mark.parametrize("d", ROT_DIRS)
+def test_rotation_keeps_polar_angle_and_turns_rigidly(orc, d):
+    # after a scattering of polar cosine ct the new direction is a unit vector
+    # at angle arccos(ct) from the old one, and the azimuth is a rigid turn
+    # about it: two azimuths phi1, phi2 give directions whose dot product is
+    # ct^2 + st^2 cos(phi1 - phi2), whatever the basis the rotation uses
+    d = _unit(d)
+    for ct in (-1.0, -0.3, 0.0, 0.5, 0.99):
+        st2 = 1.0 - ct * ct
+        phis = np.linspace(0.0, 2 * math.pi, 13)[:-1] + 0.1
+        outs = [orc.rotate(d, ct, ph) for ph in phis]
+        for o in outs:
+            assert np.linalg.norm(o) == pytest.approx(1.0, abs=1e-12)
+            assert np.dot(o, d) == pytest.approx(ct, abs=1e-12)
+        for i in range(len(phis)):
+            for j in range(i):
+                expect = ct * ct + st2 * math.cos(phis[i] - phis[j])
+                assert np.dot(outs[i], outs[j]) == pytest.approx(expect, abs=1e-12)
+
+
+@pytest.mark.parametrize("d", [ROT_DIRS[0], ROT_DIRS[4], ROT_DIRS[6]])
+def test_rotation_azimuth_uniform(orc, d):
+    # azimuth of the new direction in a basis of the test's own, for uniform
+    # phi: chi-square against a flat histogram (pole branch included)
+    from scipy import stats
+    d = _unit(d)
+    a = np.eye(3)[np.argmin(np.abs(d))]
+    e1 = _unit(np.cross(d, a))
+    e2 = np.cross(d, e1)
+    rng = np.random.default_rng(21)
+    n = 20000
+    az = np.empty(n)
+    for i, ph in enumerate(rng.uniform(0, 2 * math.pi, n)):
+        o = orc.rotate(d, 0.2, ph)
+        az[i] = math.atan2(np.dot(o, e2), np.dot(o, e1))
+    obs, _ = np.histogram(az, np.linspace(-math.pi, math.pi, 37))
+    assert stats.chisquare(obs).pvalue > 1e-3
+
+
+def _box_scene(orc, boxes, vacuum_world=True):
+    """Boxes (name, lo, hi, (photo, compton, coherent, pair) mass partials,
+    active) in a vacuum world; material i+1 is box i's."""
+    b = mg.SceneBuilder("vacuum", 0.0)
+    for name, lo, hi, _, active in boxes:
+        b.add(name, "synthetic", 1.0, mg.box(lo, hi), group=0, active=active)
+    scene = b.build()
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    lnE0, dlnE, n = xsgen.grid()
+    s.set_region(0, 0, 0.0)
+    s.set_xs(0, (lnE0, dlnE, n), *xsgen.constant_table(n=n))
+    for i, (_, _, _, part, active) in enumerate(boxes):
+        s.set_region(i + 1, i + 1, 1.0, 0, active)
+        pe, cs, coh, pair = part
+        s.set_xs(i + 1, (lnE0, dlnE, n), *xsgen.constant_table(pe, cs, coh, n=n, pair=pair))
+    return s
+
+
+def test_volume_emission_fills_the_annulus_uniformly(orc):
+    # every try lies inside a box that contains the whole annulus, so each
+    # history takes its first draw: r^2, the azimuth and z are each uniform
+    from scipy import stats
+    s = _box_scene(orc, [("big", (-200, -200, -200), (200, 200, 200), (1.0, 0, 0, None), False)])
+    src = C.Source(C.KIND_CYL, pos=(1.0, -2.0, -5.0), r_in=10.0, r_out=40.0, h=30.0, region=1)
+    n = 20000
+    pts = np.empty((n, 3))
+    for h in range(n):
+        E, p, tries = s.emission(src, 77, h)
+        assert tries == 1
+        pts[h] = p
+    x, y, z = pts[:, 0] - 1.0, pts[:, 1] + 2.0, pts[:, 2]
+    r2 = x * x + y * y
+    assert r2.min() >= 100.0 - 1e-9 and r2.max() <= 1600.0 + 1e-9
+    for v, lo, hi in ((r2, 100.0, 1600.0), (np.arctan2(y, x), -math.pi, math.pi), (z, -5.0, 25.0)):
+        obs, _ = np.histogram(v, np.linspace(lo, hi, 21))
+        assert stats.chisquare(obs).pvalue > 1e-3
+
+
+def test_volume_emission_acceptance_equals_volume_ratio(orc):
+    # the sampling cylinder (r 40, h 60) encloses a 64-gon prism (r 20, z in
+    # [0, 30]) that is the source region: the fraction of tries accepted is
+    # the volume ratio, and the accepted points are uniform in the prism
+    from scipy import stats
+    b = mg.SceneBuilder("vacuum", 0.0)
+    b.add("prism", "synthetic", 1.0, mg.cylinder(20.0, 0.0, 30.0, 64), group=0)
+    scene = b.build()
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    src = C.Source(C.KIND_CYL, pos=(0.0, 0.0, -15.0), r_in=0.0, r_out=40.0, h=60.0, region=1)
+    n = 20000
+    tries = np.empty(n)
+    zs = np.empty(n)
+    for h in range(n):
+        E, p, t = s.emission(src, 78, h)
+        assert t >= 1
+        tries[h] = t
+        zs[h] = p[2]
+        assert 0.0 <= p[2] <= 30.0 and math.hypot(p[0], p[1]) <= 20.0
+    v_prism = 0.5 * 64 * 20.0 ** 2 * math.sin(2 * math.pi / 64) * 30.0
+    p_acc = v_prism / (math.pi * 40.0 ** 2 * 60.0)
+    # tries per history are geometric: mean 1/p, variance (1 - p)/p^2
+    m = tries.mean()
+    assert abs(m - 1 / p_acc) <= 3 * math.sqrt((1 - p_acc) / p_acc ** 2 / n)
+    obs, _ = np.histogram(zs, np.linspace(0, 30, 16))
+    assert stats.chisquare(obs).pvalue > 1e-3
+
+
+def test_line_draw_follows_the_weights(orc):
+    # a point source inside a black absorber (photo only, mu = 1000 /mm,
+    # ACTIVE): every history deposits its line energy, so the counts in the
+    # lines' channels follow the weights and the mean deposit is sum(p E)/sum(p)
+    from scipy import stats
+    s = _box_scene(orc, [("black", (-10, -10, -10), (10, 10, 10), (1e4, 0, 0, None), True)])
+    lines = [60.0, 300.0, 662.0, 1300.0]
+    prob = [1.0, 2.0, 3.0, 4.0]
+    src = C.Source(C.KIND_POINT, pos=(0.1, 0.2, 0.3), lines_keV=lines, lines_prob=prob)
+    n = 200_000
+    r = s.run(src, 0.0, n, 2201, n_channels=8192, channel_keV=0.25)
+    t = r.tally
+    assert t.n_fep == n and t.n_balance_fail == 0
+    ch = [int(e / 0.25) for e in lines]
+    obs = np.array([r.spectrum[c] for c in ch])
+    assert obs.sum() == n
+    p = np.array(prob) / sum(prob)
+    assert stats.chisquare(obs, n * p).pvalue > 1e-3
+    E, mean = np.array(lines), float(np.dot(p, lines))
+    sd = math.sqrt(float(np.dot(p, (E - mean) ** 2)) / n)
+    assert abs(t.edep_active / n - mean) <= 3 * sd
+
+
+def test_annihilation_photons_fly_back_to_back(orc):
+    # A 1 mm slab that only makes pairs (transparent at 511 keV, not ACTIVE)
+    # lies just above a wide black ACTIVE absorber.  A 2 MeV pencil beam
+    # starts in the slab and runs upward, away from the absorber.  Of the two
+    # annihilation photons exactly one runs downward (back to back), so every
+    # pair event puts 511 keV, never 1022 keV, into the absorber (but for the
+    # rare downward photon so flat that it passes beside the absorber).
+    s = _box_scene(orc, [
+        ("slab", (-10, -10, -1.0), (10, 10, 0.0), (0, 0, 0, 2.0), False),
+        ("black", (-500, -500, -500), (500, 500, -1.001), (1e4, 0, 0, None), True)])
+    src = C.Source(C.KIND_BEAM, pos=(0.123, 0.432, -0.5), direction=(0.0, 0.0, 1.0))
+    n = 200_000
+    r = s.run(src, 2000.0, n, 2202, n_channels=8192, channel_keV=0.25)
+    t = r.tally
+    p_pair = 1 - math.exp(-0.2 * 0.5)
+    assert abs(t.n_pair / n - p_pair) <= 3 * math.sqrt(p_pair * (1 - p_pair) / n)
+    one, two = int(MEC2 / 0.25), int(2 * MEC2 / 0.25)
+    assert r.spectrum[two] == 0 and r.spectrum.sum() == r.spectrum[one]
+    assert r.spectrum[one] >= 0.99 * t.n_pair
+    assert t.edep_active == pytest.approx(r.spectrum[one] * MEC2, rel=1e-12)
+    assert t.n_fep == 0 and t.n_balance_fail == 0 and t.n_lost == 0
+
+
+def test_thomson_sampler_moments(orc):
+    # moments of 3/8 (1 + mu^2) on [-1, 1] by the inverse CDF on a midpoint
+    # grid of u: E[mu] = 0, E[mu^2] = 2/5, E[mu^4] = 9/35 (independent of the
+    # CDF the sampler inverts)
+    n = 20000
+    mu = np.array([orc.thomson_sample((i + 0.5) / n) for i in range(n)])
+    assert mu.mean() == pytest.approx(0.0, abs=1e-9)
+    assert (mu ** 2).mean() == pytest.approx(2 / 5, abs=1e-6)
+    assert (mu ** 4).mean() == pytest.approx(9 / 35, abs=1e-6)
+
+
+def _recoil_density(T, E):
+    # Compton recoil-electron energy distribution, textbook form in s = T/E:
+    # 2 + s^2/(k^2 (1-s)^2) + s/(1-s) (s - 2/k), k = E / m_e c^2
+    k = E / MEC2
+    s = T / E
+    return 2 + s * s / (k * k * (1 - s) ** 2) + s / (1 - s) * (s - 2 / k)
+
+
+def test_single_scatter_thin_slab_spectrum(orc):
+    # pencil beam through a small Compton-only ACTIVE block (0.5 mm deep, 2 mm
+    # wide, mu t = 0.01): almost every interacting history scatters once and
+    # leaves, depositing the recoil energy T, so the deposit spectrum follows
+    # d sigma / dT and the interacting fraction is 1 - exp(-mu t)
+    from scipy import integrate, stats
+    s = _box_scene(orc, [("thin", (-1, -1, -0.5), (1, 1, 0.0), (0, 0.2, 0, None), True)])
+    src = C.Source(C.KIND_BEAM, pos=(0.0123, -0.0321, 10.0), direction=(0.0, 0.0, -1.0))
+    E, n = 661.7, 3_000_000
+    r = s.run(src, E, n, 2203, n_channels=8192, channel_keV=0.25)
+    t = r.tally
+    p_int = 1 - math.exp(-0.02 * 0.5)
+    hit = int(r.spectrum.sum())
+    assert abs(hit / n - p_int) <= 3 * math.sqrt(p_int * (1 - p_int) / n)
+    k = E / MEC2
+    tmax = E * 2 * k / (1 + 2 * k)
+    # 24 bins of 80 channels (20 keV) up to 480 keV; the last holds the edge
+    edges = np.arange(0, 25) * 80
+    obs = np.array([r.spectrum[a:b].sum() for a, b in zip(edges[:-1], edges[1:])], float)
+    w = np.array([integrate.quad(_recoil_density, a * 0.25, min(b * 0.25, tmax), args=(E,))[0]
+                  for a, b in zip(edges[:-1], edges[1:])])
+    # deposits above the Compton edge need a second scattering (about 0.3 %)
+    assert hit - obs.sum() <= 0.01 * hit
+    assert stats.chisquare(obs, obs.sum() * w / w.sum()).pvalue > 1e-3
+    assert t.n_balance_fail == 0
