@@ -192,6 +192,22 @@ gadep_status gadep_run(gadep_ctx* ctx, const gadep_source* src, const double* en
                        int32_t n_energies, int64_t n_histories, uint64_t seed,
                        int64_t first_history, gadep_tally* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gadep_run on the mesh of
+ * scene 0 at the context's density scales, with the same arguments, results
+ * (bit for bit) and errors, that allocates no device memory.  Its tables,
+ * cursors, tally rows and spectra live in one fixed 4 MiB device array per GPU
+ * (kept until the process ends); the mesh and cross sections must already be
+ * on the device (gadep_load_mesh, gadep_set_xs).  Limits: n_energies <= 256,
+ * n_lines <= 256, n_energies * n_channels <= 505376 spectrum words; larger
+ * inputs return GADEP_E_ARG.  Like gadep_run it returns when the tallies are
+ * in `out`.  Every call on one GPU shares that GPU's array, from any
+ * context: calls that overlap in time on one GPU race and must not be made. */
+gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src,
+                               const double* energies_keV, int32_t n_energies,
+                               int64_t n_histories, uint64_t seed, int64_t first_history,
+                               gadep_tally* out);
+
 /* As gadep_run at density scales `scales[n_scales]`, also returning the
  * score-function derivative of FEPE with respect to each scale,
  * dfepe_ds[n_energies][n_scales] = mean over histories of

@@ -137,6 +137,13 @@ enum EventSlot : int {
 };
 static_assert(kT_Ev + kEv_N <= kT_Slots, "tally slots");
 
+// Fixed device scratch of the no-allocation run (one array per GPU): its size
+// and the number of devices whose addresses are kept.
+constexpr size_t kScratchBytes = size_t(4) << 20;
+constexpr int kScratchDevices = 64;
+constexpr int32_t kScratchUnits = 256;  // energies per no-allocation run
+constexpr int32_t kScratchLines = 256;  // source lines per no-allocation run
+
 struct TransportParams {
   const UnitRec* units;
   const int64_t* chunk_begin;  // [n_units + 1], prefix sums of chunks per unit

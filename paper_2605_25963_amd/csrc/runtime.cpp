@@ -27,6 +27,7 @@ hipError_t raycast(const SceneRec& sc, const float* o, const float* d, const int
 hipError_t locate(const SceneRec& sc, const float* p, int64_t n, int32_t* region, hipStream_t s);
 hipError_t philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
                   hipStream_t s);
+hipError_t scratch_address(int device, void** out);
 hipError_t broaden(const double* in, double* out, int n_spectra, int n, double w, double a,
                    double b, hipStream_t s);
 }  // namespace gadep
@@ -80,6 +81,34 @@ void fill_scene_rec(const Scene& sc, SceneRec& sr) {
   }
 }
 
+// Host side of a no-allocation run: the tables uploaded into the device
+// scratch array, and the tally rows read back from it.
+struct NoAllocHost {
+  UnitRec units[kScratchUnits];
+  int64_t chunk_begin[kScratchUnits + 1];
+  SceneRec scene;
+  SourceRec source;
+  float lines[2 * kScratchLines];
+  RegionRec regions[kMaxRegions];
+  unsigned long long tally[static_cast<size_t>(kScratchUnits) * kT_Slots];
+};
+
+// Byte offsets of those tables in the device scratch array; the spectra take
+// the rest.
+constexpr size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+constexpr size_t kNaUnits = 0;
+constexpr size_t kNaChunks = align256(kNaUnits + kScratchUnits * sizeof(UnitRec));
+constexpr size_t kNaScene = align256(kNaChunks + (kScratchUnits + 1) * sizeof(int64_t));
+constexpr size_t kNaSource = align256(kNaScene + sizeof(SceneRec));
+constexpr size_t kNaLines = align256(kNaSource + sizeof(SourceRec));
+constexpr size_t kNaRegions = align256(kNaLines + 2 * kScratchLines * sizeof(float));
+constexpr size_t kNaCursor = align256(kNaRegions + kMaxRegions * sizeof(RegionRec));
+constexpr size_t kNaTally = align256(kNaCursor + kScratchUnits * sizeof(unsigned long long));
+constexpr size_t kNaSpectra =
+    align256(kNaTally + static_cast<size_t>(kScratchUnits) * kT_Slots * sizeof(unsigned long long));
+constexpr size_t kNaSpectraWords = (kScratchBytes - kNaSpectra) / sizeof(unsigned long long);
+static_assert(kNaSpectra + (size_t(1) << 16) <= kScratchBytes, "scratch layout");
+
 struct Material {
   bool set = false;
   std::vector<float> ln[4];  // ln(mu/rho) per grid point; -200 for an absent partial
@@ -130,6 +159,11 @@ struct gadep_ctx {
   // graph cache
   hipGraphExec_t graph = nullptr;
   std::vector<uint8_t> graph_key;
+
+  // gadep_run_noalloc: the device's fixed scratch array (its address on this
+  // context's device) and host staging of the same tables, set up at create
+  void* scratch = nullptr;
+  std::unique_ptr<NoAllocHost> na;
 };
 
 namespace {
@@ -640,6 +674,10 @@ gadep_status gadep_create(int device, void* hip_stream, gadep_ctx** out) {
     return GADEP_E_HIP;
   }
   ctx->n_cu = prop.multiProcessorCount;
+  // the no-allocation run's scratch: this device's copy of the array (the
+  // device is current), and its host staging
+  if (scratch_address(device, &ctx->scratch) != hipSuccess) ctx->scratch = nullptr;
+  ctx->na = std::make_unique<NoAllocHost>();
   if (hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -882,7 +920,9 @@ gadep_status gadep_set_xs(gadep_ctx* ctx, int32_t material, double lnE0, double 
   ctx->dlnE = dlnE;
   ctx->nE = nE;
   ctx->xs_dirty = true;
-  return GADEP_OK;
+  // uploaded now, so that a run that cannot allocate finds them on the device
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  return sync_xs(ctx);
 }
 
 gadep_status gadep_set_scales(gadep_ctx* ctx, const float* scales, int32_t n) {
@@ -904,6 +944,190 @@ gadep_status gadep_run(gadep_ctx* ctx, const gadep_source* src, const double* en
   gadep_status s = plan_jobs(ctx, &j, 1, out, false, P);
   if (s) return s;
   return execute(ctx, P, seed, out, nullptr, nullptr, 0);
+}
+
+gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const double* energies,
+                               int32_t n_energies, int64_t n, uint64_t seed, int64_t first,
+                               gadep_tally* out) {
+  if (!ctx) return GADEP_E_ARG;
+  if (!src || !out) return set_err(ctx, GADEP_E_ARG, "null source or output");
+  if (!ctx->scratch || !ctx->na) return set_err(ctx, GADEP_E_STATE, "no device scratch on this device");
+  if (!ctx->grid_set || ctx->xs_dirty) return set_err(ctx, GADEP_E_STATE, "run before gadep_set_xs");
+  if (ctx->scenes.empty() || !ctx->scenes[0] || !ctx->scenes[0]->loaded)
+    return set_err(ctx, GADEP_E_STATE, "run before gadep_load_mesh");
+  if (n_energies < 1 || n_energies > kScratchUnits)
+    return set_err(ctx, GADEP_E_ARG, "run_noalloc: n_energies must be in [1, 256]");
+  if (n < 0 || first < 0) return set_err(ctx, GADEP_E_ARG, "negative history count or first history");
+  if (src->n_lines > kScratchLines)
+    return set_err(ctx, GADEP_E_ARG, "run_noalloc: at most 256 source lines");
+  if (src->n_lines == 0 && !energies)
+    return set_err(ctx, GADEP_E_ARG, "energies_keV is NULL for a mono-energetic source");
+  if (src->n_lines > 0 && n_energies != 1)
+    return set_err(ctx, GADEP_E_ARG, "a line source takes n_energies = 1");
+  const Scene& sc = *ctx->scenes[0];
+  gadep_status s = check_source(ctx, *src, sc);
+  if (s) return s;
+  NoAllocHost& H = *ctx->na;
+
+  // spectra: one binning for all units, within the scratch array
+  bool spectrum = false;
+  int32_t n_channels = 0;
+  float channel_keV = 0.0f;
+  for (int32_t u = 0; u < n_energies; ++u) {
+    const gadep_tally& t = out[u];
+    if (!t.spectrum) continue;
+    if (t.n_channels <= 0 || !(t.channel_keV > 0))
+      return set_err(ctx, GADEP_E_ARG, "tally: spectrum needs n_channels > 0 and channel_keV > 0");
+    if (spectrum && (t.n_channels != n_channels || t.channel_keV != channel_keV))
+      return set_err(ctx, GADEP_E_ARG, "tally: all spectra of one run share their binning");
+    spectrum = true;
+    n_channels = t.n_channels;
+    channel_keV = t.channel_keV;
+  }
+  const int64_t spec_words = spectrum ? static_cast<int64_t>(n_energies) * n_channels : 0;
+  if (spec_words > static_cast<int64_t>(kNaSpectraWords))
+    return set_err(ctx, GADEP_E_ARG, "run_noalloc: n_energies * n_channels above the scratch "
+                                     "capacity of " + std::to_string(kNaSpectraWords) +
+                                     " spectrum words");
+
+  // region table at the context's density scales
+  for (int32_t r = 0; r < sc.n_regions; ++r) {
+    const gadep_region& R = sc.regions[r];
+    if (R.material < 0 || R.material >= static_cast<int32_t>(ctx->mats.size()) ||
+        !ctx->mats[R.material].set)
+      return set_err(ctx, GADEP_E_STATE, "a region's material has no cross sections");
+    const float sg = R.scale_group >= 0 ? ctx->scales[R.scale_group] : 1.0f;
+    RegionRec& rr = H.regions[r];
+    rr.mult = static_cast<float>(0.1 * R.density_g_cm3 * sg);
+    rr.inv_scale = 1.0f / sg;
+    rr.material = R.material;
+    rr.bits = (R.scale_group >= 0 ? R.scale_group : 0xFF) | ((R.flags & GADEP_ACTIVE) ? 0x100 : 0);
+  }
+  // source and its lines (cumulative weights, the last one past 1)
+  SourceRec& sr = H.source;
+  sr = SourceRec{};
+  sr.kind = src->kind;
+  for (int a = 0; a < 3; ++a) sr.pos[a] = src->pos_mm[a];
+  if (src->kind == GADEP_SRC_BEAM) {
+    const double nn = sqrt(double(src->dir[0]) * src->dir[0] + double(src->dir[1]) * src->dir[1] +
+                           double(src->dir[2]) * src->dir[2]);
+    for (int a = 0; a < 3; ++a) sr.dir[a] = static_cast<float>(src->dir[a] / nn);
+  }
+  sr.r_in = src->r_in_mm;
+  sr.r_out = src->r_out_mm;
+  sr.h = src->h_mm;
+  sr.region = src->region;
+  sr.n_lines = src->n_lines;
+  sr.line_off = 0;
+  if (src->n_lines > 0) {
+    double tot = 0, cum = 0;
+    for (int i = 0; i < src->n_lines; ++i) tot += src->line_prob[i];
+    for (int i = 0; i < src->n_lines; ++i) {
+      if ((s = check_energy(ctx, src->line_keV[i]))) return s;
+      cum += src->line_prob[i];
+      H.lines[2 * i] = src->line_keV[i];
+      H.lines[2 * i + 1] = static_cast<float>(i == src->n_lines - 1 ? 2.0 : cum / tot);
+    }
+  }
+  // units and their chunks
+  const int64_t chunk = 64 * ctx->claim;
+  int64_t chunks = 0;
+  for (int32_t e = 0; e < n_energies; ++e) {
+    UnitRec& u = H.units[e];
+    u = UnitRec{};
+    u.n = n;
+    u.first = first;
+    const double E = src->n_lines > 0 ? 0.0 : energies[e];
+    if (src->n_lines == 0 && (s = check_energy(ctx, E))) return s;
+    u.energy = static_cast<float>(E);
+    u.source = 0;
+    u.scene = 0;
+    u.region_off = 0;
+    u.stream = static_cast<uint32_t>(e);
+    u.src_region = 0;
+    u.n_groups = 0;
+    u.flags = 0;
+    if (sc.convex_exit && H.regions[0].mult == 0.0f)
+      u.flags = kUnitExitEscapes | (sc.n_planes > 0 && ctx->exit_planes ? kUnitExitPlanes : 0);
+    H.chunk_begin[e] = chunks;
+    chunks += (n + chunk - 1) / chunk;
+  }
+  H.chunk_begin[n_energies] = chunks;
+  fill_scene_rec(sc, H.scene);
+
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  char* base = static_cast<char*>(ctx->scratch);
+  auto up = [&](size_t off, const void* p, size_t bytes) {
+    return hipMemcpyAsync(base + off, p, bytes, hipMemcpyHostToDevice, ctx->stream);
+  };
+  HIP_TRY(up(kNaUnits, H.units, n_energies * sizeof(UnitRec)), "upload units");
+  HIP_TRY(up(kNaChunks, H.chunk_begin, (n_energies + 1) * sizeof(int64_t)), "upload chunks");
+  HIP_TRY(up(kNaScene, &H.scene, sizeof(SceneRec)), "upload scene");
+  HIP_TRY(up(kNaSource, &H.source, sizeof(SourceRec)), "upload source");
+  if (src->n_lines > 0) HIP_TRY(up(kNaLines, H.lines, 2 * src->n_lines * sizeof(float)), "upload lines");
+  HIP_TRY(up(kNaRegions, H.regions, sc.n_regions * sizeof(RegionRec)), "upload regions");
+
+  TransportParams K{};
+  K.units = reinterpret_cast<const UnitRec*>(base + kNaUnits);
+  K.chunk_begin = reinterpret_cast<const int64_t*>(base + kNaChunks);
+  K.n_units = n_energies;
+  K.chunk = static_cast<int32_t>(chunk);
+  K.scenes = reinterpret_cast<const SceneRec*>(base + kNaScene);
+  K.sources = reinterpret_cast<const SourceRec*>(base + kNaSource);
+  K.lines = reinterpret_cast<const float*>(base + kNaLines);
+  K.regions = reinterpret_cast<const RegionRec*>(base + kNaRegions);
+  K.xs = static_cast<const float*>(ctx->xs.p);
+  K.n_e = ctx->nE;
+  K.ln_e0 = static_cast<float>(ctx->lnE0);
+  K.inv_dlne = static_cast<float>(1.0 / ctx->dlnE);
+  K.e_cut = static_cast<float>(exp(ctx->lnE0));
+  K.tally = reinterpret_cast<unsigned long long*>(base + kNaTally);
+  K.spectra = spectrum ? reinterpret_cast<unsigned long long*>(base + kNaSpectra) : nullptr;
+  K.n_channels = n_channels;
+  K.inv_channel_kev = spectrum ? 1.0f / channel_keV : 0.0f;
+  K.cursor = reinterpret_cast<unsigned long long*>(base + kNaCursor);
+  K.seed_lo = static_cast<uint32_t>(seed);
+  K.seed_hi = static_cast<uint32_t>(seed >> 32);
+  K.max_steps = static_cast<int32_t>(ctx->max_steps);
+  K.stack_depth = std::max<int32_t>(1, sc.depth);
+  K.period = static_cast<int32_t>(ctx->period);
+  K.screen = static_cast<int32_t>(ctx->screen);
+  K.pair = 0;
+  for (const Material& m : ctx->mats)
+    if (m.set && m.pair) K.pair = 1;
+  const int variant = (spectrum ? 2 : 0) | (src->kind == GADEP_SRC_CYL ? 8 : 0) | (K.pair ? 16 : 0);
+  const int block = static_cast<int>(ctx->block);
+  int grid = static_cast<int>(ctx->grid);
+  if (grid <= 0) {
+    int per_cu = 0;
+    HIP_TRY(transport_occupancy(variant, block, K.stack_depth, K.pair, &per_cu), "occupancy");
+    if (per_cu < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");
+    grid = per_cu * ctx->n_cu;
+  }
+  // the array keeps the last call's contents: clear the tallies, spectra and
+  // cursors with a fill kernel
+  const int64_t tally_words = static_cast<int64_t>(n_energies) * kT_Slots;
+  HIP_TRY(fill_u64(K.tally, tally_words, 0, ctx->stream), "clear tallies");
+  if (spec_words) HIP_TRY(fill_u64(K.spectra, spec_words, 0, ctx->stream), "clear spectra");
+  HIP_TRY(fill_u64(K.cursor, n_energies, 0, ctx->stream), "clear cursors");
+  HIP_TRY(locate_units(reinterpret_cast<UnitRec*>(base + kNaUnits), n_energies,
+                       reinterpret_cast<const SceneRec*>(base + kNaScene),
+                       reinterpret_cast<const SourceRec*>(base + kNaSource), K.stack_depth,
+                       ctx->stream),
+          "locate units");
+  HIP_TRY(transport_launch(K, variant, grid, block, ctx->stream), "transport launch");
+  HIP_TRY(hipMemcpyAsync(H.tally, K.tally, tally_words * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, ctx->stream),
+          "tally D2H");
+  for (int32_t u = 0; u < n_energies && spec_words; ++u)
+    if (out[u].spectrum)
+      HIP_TRY(hipMemcpyAsync(out[u].spectrum, K.spectra + static_cast<int64_t>(u) * n_channels,
+                             n_channels * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             ctx->stream),
+              "spectra D2H");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "transport");
+  for (int32_t u = 0; u < n_energies; ++u) to_tally(H.tally + static_cast<int64_t>(u) * kT_Slots, out[u]);
+  return GADEP_OK;
 }
 
 gadep_status gadep_run_grad(gadep_ctx* ctx, const gadep_source* src, const double* energies,

@@ -14,6 +14,7 @@
 // slot, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <utility>
 
 #include "device_common.h"
@@ -1202,6 +1203,35 @@ __global__ void broaden_kernel(const double* in, double* out, int n_spectra, int
     acc += x * 0.5 * (erfc(-((c + 1) * w - Ec) * r) - erfc(-(c * w - Ec) * r));
   }
   out[i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch for callers that cannot allocate (gadep_run_noalloc):
+// the run's unit, chunk, scene, source, line and region tables, the chunk
+// cursors, the tally rows and the spectra live in this one array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name
+// (a host-side stand-in): it takes the address that hipGetSymbolAddress
+// returns for the current device, once per device.
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex m;
+  static void* addr[kScratchDevices] = {};
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(m);
+  if (!addr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

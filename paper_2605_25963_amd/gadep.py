@@ -106,6 +106,7 @@ EXPORTS = [
     "gadep_run_grad", "gadep_run_batch", "gadep_autotune", "gadep_get_counters",
     "gadep_broaden_dev", "gadep_raycast", "gadep_locate", "gadep_mesh_prepare",
     "gadep_get_last_launch_ms", "gadep_detmesh", "gadep_write_vrml", "gadep_philox",
+    "gadep_run_noalloc",
 ]
 
 _lib = None
@@ -144,6 +145,8 @@ def lib():
         "gadep_set_xs": (i32, [p, i32, C.c_double, C.c_double, i32, f32p, f32p, f32p, f32p]),
         "gadep_set_scales": (i32, [p, f32p, i32]),
         "gadep_run": (i32, [p, C.POINTER(Source), dp, i32, i64, u64, i64, C.POINTER(Tally)]),
+        "gadep_run_noalloc": (i32, [p, C.POINTER(Source), dp, i32, i64, u64, i64,
+                                    C.POINTER(Tally)]),
         "gadep_run_grad": (i32, [p, C.POINTER(Source), dp, i32, i64, u64, i64, f32p, i32,
                                  C.POINTER(Tally), dp, dp]),
         "gadep_run_batch": (i32, [p, C.POINTER(Job), i32, u64, C.POINTER(Tally), dp, dp]),
@@ -322,6 +325,17 @@ class Context:
         out, spec = self._tallies(nu, spectrum)
         self._check(lib().gadep_run(self.h, C.byref(src), None if src.n_lines else _ptr(e, C.c_double),
                                     nu, int(n_histories), int(seed), int(first_history), out))
+        return Result(list(out), spec)
+
+    def run_noalloc(self, source, energies, n_histories, seed, first_history=0, spectrum=None):
+        """gadep_run_noalloc: gadep_run without device allocations (fixed scratch)."""
+        src = source if isinstance(source, Source) else source_from(source)
+        e = np.ascontiguousarray(energies if energies is not None else [0.0], dtype=np.float64)
+        nu = len(e)
+        out, spec = self._tallies(nu, spectrum)
+        self._check(lib().gadep_run_noalloc(self.h, C.byref(src),
+                                            None if src.n_lines else _ptr(e, C.c_double), nu,
+                                            int(n_histories), int(seed), int(first_history), out))
         return Result(list(out), spec)
 
     def run_grad(self, source, energies, n_histories, seed, scales, first_history=0,
@@ -537,6 +551,7 @@ gadep_load_scene = Context.load_scene
 gadep_set_xs = Context.set_xs
 gadep_set_scales = Context.set_scales
 gadep_run = Context.run
+gadep_run_noalloc = Context.run_noalloc
 gadep_run_grad = Context.run_grad
 gadep_run_batch = Context.run_batch
 gadep_autotune = Context.autotune
