@@ -180,9 +180,13 @@ typedef struct {
 } gadep_tally;
 
 /* ----------------------------------------------------------------------------
- * transport */
+ * transport (Sec. 2.4: the host prepares geometry and tables and scores, the
+ * device transports; Sec. 2.4.1: photon physics and the free path by partial
+ * cross sections; Sec. 2.4.2: region at each crossing; Sec. 2.4.3: BVH) */
 
-/* n_histories histories (numbers first_history..) at each of the energies,
+/* FEPE calibration run (Sec. 3.2: an on-axis point source and FEPE per
+ * energy; Table 4 counts particles per energy).
+ * n_histories histories (numbers first_history..) at each of the energies,
  * point/beam/volume source, seed for the counter-based generator
  * (Philox4x32-10 keyed by seed, counter = (draw, history, unit)).  Results are
  * a pure function of (inputs, seed, history numbers): disjoint history ranges
@@ -199,7 +203,7 @@ gadep_status gadep_run(gadep_ctx* ctx, const gadep_source* src, const double* en
  * cursors, tally rows and spectra live in one fixed 4 MiB device array per GPU
  * (kept until the process ends); the mesh and cross sections must already be
  * on the device (gadep_load_mesh, gadep_set_xs).  Limits: n_energies <= 256,
- * n_lines <= 256, n_energies * n_channels <= 505376 spectrum words; larger
+ * n_lines <= 256, n_energies * n_channels <= 503328 spectrum words; larger
  * inputs return GADEP_E_ARG.  Like gadep_run it returns when the tallies are
  * in `out`.  Every call on one GPU shares that GPU's array, from any
  * context: calls that overlap in time on one GPU race and must not be made. */
@@ -208,7 +212,10 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src,
                                int64_t n_histories, uint64_t seed, int64_t first_history,
                                gadep_tally* out);
 
-/* As gadep_run at density scales `scales[n_scales]`, also returning the
+/* Not a step of the paper: FEPE is most sensitive to the dead layer and the
+ * crystal at low energies (Sec. 1, Sec. 4), and this gives the derivative a
+ * fit of those densities needs.
+ * As gadep_run at density scales `scales[n_scales]`, also returning the
  * score-function derivative of FEPE with respect to each scale,
  * dfepe_ds[n_energies][n_scales] = mean over histories of
  * 1_FEP * (n_g / s_g - sum over path segments in group g of mu0 * l),
@@ -218,7 +225,9 @@ gadep_status gadep_run_grad(gadep_ctx* ctx, const gadep_source* src, const doubl
                             int64_t first_history, const float* scales, int32_t n_scales,
                             gadep_tally* out, double* dfepe_ds, double* dfepe_ds_var);
 
-/* Many calibration jobs of uneven size in one persistent launch. */
+/* Many calibration jobs of uneven size in one persistent launch: sourceless
+ * calibration evaluates many energies, source geometries and matrices for
+ * one detector (Sec. 1, Sec. 3.2). */
 typedef struct {
   gadep_source src;
   const double* energies_keV;  /* [n_energies]; NULL for a line source (n_energies 1) */
@@ -239,7 +248,9 @@ typedef struct {
 gadep_status gadep_run_batch(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
                              uint64_t seed, gadep_tally* out, double* grads, double* grads_var);
 
-/* Times short pilot launches of `jobs` (scaled down to about pilot_histories
+/* Launch tuning (no counterpart in the paper, whose kernel runs on one
+ * RTX 4090 configuration, Sec. 3.3).
+ * Times short pilot launches of `jobs` (scaled down to about pilot_histories
  * in total) over block sizes, park thresholds (GADEP_OPT_PERIOD) and claim
  * sizes, keeps the fastest in the context and returns it (any output pointer
  * may be NULL).  Tallies never depend on these settings. */
@@ -247,7 +258,8 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
                             int64_t pilot_histories, int32_t* block, int32_t* period,
                             int32_t* claim);
 
-/* Event counts of the last run with GADEP_OPT_COUNTERS = 1. */
+/* Event counts of the last run with GADEP_OPT_COUNTERS = 1 (the work the
+ * performance comparison of Sec. 3.3 / Table 4 rests on, per event). */
 typedef struct {
   uint64_t segments, crossings, node_visits, tri_tests, photo, compton, coherent, rng_calls,
       locates, emissions;
@@ -268,12 +280,15 @@ typedef struct {
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 
-/* Duration of the last transport launch, from HIP events recorded on the
+/* Timing as in Sec. 3.3 (kernel time per run).
+ * Duration of the last transport launch, from HIP events recorded on the
  * context's stream right before and after it (the graph replay, when graphs
  * are on, which adds two tiny set-up kernels to the transport kernel). */
 gadep_status gadep_get_last_launch_ms(const gadep_ctx* ctx, double* ms);
 
-/* Gaussian broadening of spectra on the device: FWHM(E)^2 = a + b E (keV^2,
+/* Pulse-height spectrum post-processing (the detector resolution the paper
+ * leaves to the analysis after transport, Sec. 2.4 scoring on the host side).
+ * Gaussian broadening of spectra on the device: FWHM(E)^2 = a + b E (keV^2,
  * E = channel centre), counts spread over the channels within 5 sigma,
  * each receiving channel taking the integral of the normal law over its
  * width.  in_dev / out_dev: device arrays [n_spectra][n_channels], FP64. */
@@ -284,7 +299,9 @@ gadep_status gadep_broaden_dev(gadep_ctx* ctx, const double* in_dev, double* out
 /* ----------------------------------------------------------------------------
  * geometry queries on the device (checks of the boundary handling) */
 
-/* Closest facet hit for rays o[n][3] + t d[n][3], t > 0, from region
+/* Nearest-hit query of Sec. 2.4.2 (the facet ahead and the material behind
+ * it) on the BVH of Sec. 2.4.3.
+ * Closest facet hit for rays o[n][3] + t d[n][3], t > 0, from region
  * region[n] (nullable: no region-consistency filter).  Returns t[n]
  * (INFINITY on a miss), tri[n] (caller's facet index, -1 on a miss) and
  * region_after[n] (region entered across the hit facet). */

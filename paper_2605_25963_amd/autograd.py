@@ -27,9 +27,7 @@ class GadepFEPE(torch.autograd.Function):
                             first_history=job.get("first_history", 0))
         fepe = torch.as_tensor(np.asarray(r.fepe()), dtype=torch.float64, device=scales.device)
         jac = torch.as_tensor(r.grad, dtype=torch.float64, device=scales.device)
-        var = torch.as_tensor(r.grad_var, dtype=torch.float64, device=scales.device)
         ctx.save_for_backward(jac)
-        ctx.mark_non_differentiable(var)
         ctx.in_dtype = scales.dtype
         return fepe
 

@@ -20,7 +20,12 @@ constexpr float kMec2 = 510.99895f;  // electron rest energy [keV]
 // Fixed-point scales of the 64-bit tally accumulators (exact, order-free sums).
 constexpr double kEnergyFix = 65536.0;      // keV
 constexpr double kScoreFix = 16777216.0;    // score
-constexpr double kScore2Fix = 65536.0;      // score^2
+// score^2 of a history, x = score^2 * 2^16, is kept in two slots: floor(x)
+// and the rest of x rounded in units of 2^-24, so that the squares of tiny
+// scores (a layer of a few micrometres, such as a separation gap) are not lost
+// while the range stays that of floor(x).
+constexpr double kScore2Fix = 65536.0;  // score^2, integer part
+constexpr int kScore2LoBits = 24;       // fraction bits of the second slot
 
 // node link meaning "no node" (an empty stack, a region without facets)
 constexpr int32_t kDone = INT32_MIN;
@@ -120,7 +125,8 @@ enum TallySlot : int {
   kT_SpecOvf, kT_EdepAct, kT_EdepTot, kT_EEsc, kT_ESrc,
   kT_Score = 16, kT_FepScore = 24, kT_FepScore2 = 32,
   kT_Ev = 40,  // event counters, up to 24 slots
-  kT_Slots = 64
+  kT_FepScore2Lo = 64,  // fractions of the FEP score^2 sums (see kScore2Fix)
+  kT_Slots = 72
 };
 enum EventSlot : int {
   kEv_Segments = 0, kEv_Crossings, kEv_NodeVisits, kEv_TriTests, kEv_Photo, kEv_Compton,
@@ -135,7 +141,7 @@ enum EventSlot : int {
   kEv_Pair,  // pair-production events
   kEv_N
 };
-static_assert(kT_Ev + kEv_N <= kT_Slots, "tally slots");
+static_assert(kT_Ev + kEv_N <= kT_FepScore2Lo, "tally slots");
 
 // Fixed device scratch of the no-allocation run (one array per GPU): its size
 // and the number of devices whose addresses are kept.

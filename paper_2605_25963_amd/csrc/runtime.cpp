@@ -598,7 +598,9 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
       const double n = static_cast<double>(Tu[kT_Hist]);
       for (int32_t g = 0; g < n_grad_cols; ++g) {
         const double m1 = n > 0 ? static_cast<double>(static_cast<int64_t>(Tu[kT_FepScore + g])) / kScoreFix / n : 0.0;
-        const double m2 = n > 0 ? static_cast<double>(Tu[kT_FepScore2 + g]) / kScore2Fix / n : 0.0;
+        const double q = static_cast<double>(Tu[kT_FepScore2 + g]) +
+                         static_cast<double>(Tu[kT_FepScore2Lo + g]) / (1 << kScore2LoBits);
+        const double m2 = n > 0 ? q / kScore2Fix / n : 0.0;
         if (grads) grads[static_cast<int64_t>(u) * n_grad_cols + g] = m1;
         if (grads_var) grads_var[static_cast<int64_t>(u) * n_grad_cols + g] = n > 1 ? std::max(0.0, m2 - m1 * m1) / n : 0.0;
       }
@@ -1331,62 +1333,6 @@ gadep_status gadep_locate(gadep_ctx* ctx, int32_t scene, const float* p, int64_t
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   (void)hipFree(buf);
   if (e != hipSuccess) return hip_err(ctx, e, "locate");
-  return GADEP_OK;
-}
-
-gadep_status gadep_mesh_prepare(const float* xyz, int64_t nv, const int32_t* tri,
-                                const int32_t* tri_region, int64_t nt, int32_t n_regions,
-                                double min_gap_mm, int32_t validate, int32_t bvh_method,
-                                double split_budget, int32_t* tri_outside, int32_t* tri_shell,
-                                void* nodes_out, int64_t cap_nodes, int32_t* tri_order,
-                                int64_t cap_slots, gadep_mesh_info* info, char* err,
-                                int32_t err_len) {
-  if (bvh_method < 0 || bvh_method > 2 || !(split_budget >= 0) || split_budget > 16) {
-    if (err && err_len > 0) {
-      strncpy(err, "mesh: bvh_method or split_budget out of range", static_cast<size_t>(err_len) - 1);
-      err[err_len - 1] = 0;
-    }
-    return GADEP_E_ARG;
-  }
-  PreparedMesh pm;
-  std::string e;
-  int rc = prepare_mesh(xyz, nv, tri, tri_region, nt, n_regions, min_gap_mm, validate != 0,
-                        bvh_method == 1 ? 1 : 0, split_budget, pm, e);
-  if (err && err_len > 0) {
-    strncpy(err, e.c_str(), static_cast<size_t>(err_len) - 1);
-    err[err_len - 1] = 0;
-  }
-  if (rc != GADEP_OK) return static_cast<gadep_status>(rc);
-  const bool trans = bvh_method == 2;
-  const std::vector<BvhNode>& nodes = trans ? pm.trans_nodes : pm.nodes;
-  const int64_t n_slots = trans ? static_cast<int64_t>(pm.trans_tris.size()) : nt;
-  if (info) {
-    info->n_shells = pm.n_shells;
-    info->genus_max = pm.genus_max;
-    info->n_nodes = static_cast<int64_t>(nodes.size());
-    info->depth = trans ? pm.trans_depth : pm.depth;
-    info->sah_cost = trans ? pm.trans_sah : pm.sah;
-    info->n_slots = n_slots;
-    info->min_gap_mm = pm.min_gap;
-    info->convex_exit = pm.convex_exit ? 1 : 0;
-    info->n_exit_planes = static_cast<int32_t>(pm.planes.size() / 4);
-    for (int32_t r = 0; r <= GADEP_MAX_REGIONS; ++r)
-      info->region_root[r] = trans && r < static_cast<int32_t>(pm.trans_root.size()) ? pm.trans_root[r]
-                                                                                     : -1;
-  }
-  if (tri_outside) memcpy(tri_outside, pm.outside.data(), pm.outside.size() * 4);
-  if (tri_shell) memcpy(tri_shell, pm.shell.data(), pm.shell.size() * 4);
-  if (tri_order) {
-    if (cap_slots < n_slots) return GADEP_E_ARG;
-    if (trans)
-      for (int64_t i = 0; i < n_slots; ++i) tri_order[i] = pm.trans_tris[i].orig;
-    else
-      memcpy(tri_order, pm.order.data(), pm.order.size() * 4);
-  }
-  if (nodes_out) {
-    if (cap_nodes < static_cast<int64_t>(nodes.size())) return GADEP_E_ARG;
-    memcpy(nodes_out, nodes.data(), nodes.size() * sizeof(BvhNode));
-  }
   return GADEP_OK;
 }
 

@@ -460,7 +460,10 @@ transport_kernel(TransportParams P) {
         atomicAdd(&wt[kT_Score + i], fx(s, kScoreFix));
         if (fep) {
           atomicAdd(&wt[kT_FepScore + i], fx(s, kScoreFix));
-          atomicAdd(&wt[kT_FepScore2 + i], fx(s * s, kScore2Fix));
+          const double x = s * s * kScore2Fix;
+          const double xi = floor(x);
+          atomicAdd(&wt[kT_FepScore2 + i], static_cast<unsigned long long>(xi));
+          atomicAdd(&wt[kT_FepScore2Lo + i], fx(x - xi, static_cast<double>(1 << kScore2LoBits)));
         }
       }
     }

@@ -15,8 +15,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# GADEP_LIBRARY selects another build of the library (for A/B timing)
-LIB_PATH = os.environ.get("GADEP_LIBRARY") or os.path.join(HERE, "libgadep.so")
+LIB_PATH = os.path.join(HERE, "libgadep.so")
 
 MAX_REGIONS = 64
 MAX_GROUPS = 8

@@ -98,25 +98,53 @@ def test_detector_gradients_match_oracle_and_crn_fd(G, ctx, orc):
         og, os_ = o.grad(6), o.grad_sigma(6)
         for gi in range(6):
             assert close3(gg[gi], gs[gi], og[gi], os_[gi]), (e, w.groups[gi], gg[gi], og[gi])
-    # common-random-number finite differences at +-1 % for three groups; the
-    # FD's own error comes from 10 independent batches (disjoint history ranges)
-    h, nb = 0.01, 10
-    for gi in (0, 1, 5):  # dead layer, crystal, matrix
-        up = list(scales)
-        dn = list(scales)
-        up[gi] += h
-        dn[gi] -= h
-        fds = []
-        for b in range(nb):
-            fu = ctx.run_grad(w.source, E, ng // nb, 41, up, first_history=b * (ng // nb)).fepe()
-            fl = ctx.run_grad(w.source, E, ng // nb, 41, dn, first_history=b * (ng // nb)).fepe()
-            fds.append((fu - fl) / (2 * h))
-        fds = np.array(fds)
-        fd, fd_sig = fds.mean(0), fds.std(0, ddof=1) / math.sqrt(nb)
-        for k in range(len(E)):
-            g, gs = r.grad[k, gi], math.sqrt(r.grad_var[k, gi])
-            tol = max(0.02 * abs(fd[k]), 3 * math.hypot(gs, fd_sig[k]))
-            assert abs(g - fd[k]) <= tol, (w.groups[gi], E[k], g, fd[k], fd_sig[k])
+    # Common-random-number finite differences at +-1 % for all six groups, on
+    # the same histories as the score-function estimate; the FD's own error
+    # comes from nb batches of disjoint history ranges.  N is sized so that
+    # 3 combined sigma lie below 2 % of the derivative for the dead layer at
+    # 100 keV and the crystal and the matrix at both energies: there the 2 %
+    # bar is asserted on its own.  The dead layer at 661.7 keV, the window,
+    # the end-cap and the cup change FEPE by too few histories
+    # for a CRN difference to resolve 2 % at a test's size (the end-cap and the
+    # cup enter mostly through the micrometre separation gaps); they are held
+    # to 3 combined sigma, and every case is printed.
+    n_fd, nb, h = 1_600_000_000, 8, 0.01
+    rg = ctx.run_grad(w.source, E, n_fd, 41, scales)
+    strict = {("dead", 100.0), ("crystal", 100.0), ("crystal", 661.7), ("matrix", 100.0),
+              ("matrix", 661.7)}
+    seen = set()
+    try:
+        for gi in range(6):
+            up = list(scales)
+            dn = list(scales)
+            up[gi] += h
+            dn[gi] -= h
+            fds = []
+            for b in range(nb):
+                m = n_fd // nb
+                ctx.set_scales(up)
+                fu = ctx.run(w.source, E, m, 41, first_history=b * m).fepe()
+                ctx.set_scales(dn)
+                fl = ctx.run(w.source, E, m, 41, first_history=b * m).fepe()
+                fds.append((fu - fl) / (2 * h))
+            fds = np.array(fds)
+            fd, fd_sig = fds.mean(0), fds.std(0, ddof=1) / math.sqrt(nb)
+            for k in range(len(E)):
+                g, gs = rg.grad[k, gi], math.sqrt(rg.grad_var[k, gi])
+                comb = math.hypot(gs, fd_sig[k])
+                rel = abs(g - fd[k]) / abs(fd[k]) if fd[k] else math.inf
+                name = w.groups[gi]
+                print(f"grad {name:8s} E {E[k]:6.1f}: sf {g:+.4e} (sd {gs:.1e})  fd {fd[k]:+.4e} "
+                      f"(sd {fd_sig[k]:.1e})  rel diff {rel:.2%}  3 sigma {3 * comb / abs(fd[k]):.2%}",
+                      flush=True)
+                if 3 * comb <= 0.02 * abs(fd[k]):
+                    assert abs(g - fd[k]) <= 0.02 * abs(fd[k]), (name, E[k], g, fd[k])
+                    seen.add((name, E[k]))
+                else:
+                    assert abs(g - fd[k]) <= 3 * comb, (name, E[k], g, fd[k], comb)
+    finally:
+        ctx.set_scales(scales)
+    assert strict <= seen, strict - seen
 
 
 # --------------------------------------------------------------------------
@@ -305,8 +333,11 @@ def test_full_size_hpge_properties_and_oracle_sample(G, ctx, orc):
     # front disk (r 31.3 at z = -0.7, source at z = 255.5)
     d = 255.5 + 0.7
     bound = 0.5 * (1 - d / math.hypot(d, 31.3))
-    no = 1_000_000
+    # the oracle takes 3e7 histories at the lowest, the peak and the highest
+    # energy (a 3-sigma band of about 3 % of FEPE), 1e6 at the others
+    no_big = {0: 30_000_000, 3: 30_000_000, 11: 30_000_000}
     for k, E in enumerate(w.energies):
+        no = no_big.get(k, 1_000_000)
         t = r.tallies[k]
         assert t.n_histories == n and t.n_lost == 0 and t.n_killed == 0
         assert t.n_glitch <= 1e-6 * n
@@ -315,6 +346,9 @@ def test_full_size_hpge_properties_and_oracle_sample(G, ctx, orc):
         assert math.sqrt((1 - p) / (n * p)) < 0.0065
         assert t.edep_total_keV + t.e_escape_keV == pytest.approx(t.e_source_keV, rel=1e-6)
         o = s.run(w.source, E, no, 3002 + k)
+        band = 3 * math.hypot(binom_sigma(t.n_fep, n), o.fepe_sigma())
+        print(f"C2 250 mm E {E:8.3f}: FEPE gpu {p:.6e} (N {n})  oracle {o.fepe():.6e} (N {no})  "
+              f"diff {abs(p - o.fepe()) / band * 3:.2f} sigma, 3 sigma = {band / p:.2%}", flush=True)
         assert close3(p, binom_sigma(t.n_fep, n), o.fepe(), o.fepe_sigma()), (E, p, o.fepe())
 
 
