@@ -52,7 +52,8 @@ OPS_PER_EVENT = {
     "pair": 40,          # pair event: deposit, annihilation axis (sqrt, sin, cos), LDS store
 }
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz one-lane-op slots per second
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_SCLK_MHZ = 2400.0
+PEAK_LANE_OPS = 256 * 4 * 16 * PEAK_SCLK_MHZ * 1e6
 
 # HBM bytes per timed launch of this workload, from FETCH_SIZE / WRITE_SIZE counter
 # runs scaled by a copy probe (profiles/transport_hpge20k_counters.md), valid only
@@ -86,7 +87,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--min-histories", type=float, default=1e8, help="per energy")
     ap.add_argument("--pilot", type=float, default=1e7)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=60.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--quick", action="store_true",
@@ -173,9 +174,53 @@ def main():
         print(json.dumps(OTHER[a.workload](a, torch, gadep, C)), flush=True)
         return
     distance = 250.0 if a.workload == "c2" else 100.0
-    w = C.c2_hpge(n_histories=0, distance=distance)
     stream = torch.cuda.current_stream()
     ctx = gadep.Context(0, stream if stream.cuda_stream else None)
+    m = measure(a, torch, gadep, C, ctx, distance, a.steps, a.warmup, full=True)
+    near = None
+    if a.workload == "c2" and not a.quick:
+        # the same detector with the source at 100 mm, where more histories enter it
+        mn = measure(a, torch, gadep, C, ctx, 100.0, min(a.steps, 5), 1, full=False)
+        near = {"value": mn["total"] / mn["dt"], "unit": "histories/s", "ms_per_step": mn["dt"] * 1e3,
+                "histories_per_step": mn["total"], "max_fepe_rse": float(mn["rse"].max()),
+                "frac": mn["roof"]["frac"], "kernel_ms": mn["roof"]["kernel_ms"],
+                "active_lanes": mn["roof"]["active_lanes"]}
+    w = m["w"]
+    base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
+    line = {
+        "metric": "histories/s on 20k-tri HPGe mesh at <=0.5% FEPE RSE; fwd+grad/fwd cost",
+        "value": m["total"] / m["dt"],
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": m["dt"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"hpge_coaxial_20236_facets_point_{distance:.0f}mm_12_energies",
+                   "n_facets": int(len(w.scene.tri)), "energies_keV": [round(e, 3) for e in w.energies],
+                   "histories_per_energy": [int(x) for x in m["n_e"]], "histories_per_step": m["total"],
+                   "max_fepe_rse": float(m["rse"].max())},
+        "fwd_grad_over_fwd": m["fwd_grad_ratio"],
+        "batched_grad_vs_single_job": m["batched_vs_single"],
+        "fepe": [float(x) for x in m["fepe"]],
+        "rates": m["rates"],
+        "roofline": m["roof"],
+        "c2_source_100mm": near,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def measure(a, torch, gadep, C, ctx, distance, steps, warmup, full):
+    """One distance of the metric's detector: pilot-sized N_e, timed steps, event
+    counts and roofline; with full=True also the gradient run and the batched+grad
+    against single-job comparison."""
+    w = C.c2_hpge(n_histories=0, distance=distance)
     gadep.load_workload(ctx, w)
     n_groups = len(w.groups)
 
@@ -194,35 +239,63 @@ def main():
            np.full(len(p), a.min_histories)).astype(np.int64)
     total = int(n_e.sum())
     J = jobs(n_e)
+    JG = jobs(n_e, True)
 
     def step(grad=False, seed=1002):
         if grad:
-            return ctx.run_batch(jobs(n_e, True), seed, grad=True)
+            return ctx.run_batch(JG, seed, grad=True)
         return ctx.run_batch(J, seed)
 
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     kernel_ms = []
+    sclks = []
     res = None
-    for _ in range(a.steps):
+    t0 = time.perf_counter()
+    for _ in range(steps):
         res = step()
         kernel_ms.append(ctx.get_last_launch_ms())
+        sclks.append(ctx.get_last_clock_mhz())
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / a.steps
+    dt = (time.perf_counter() - t0) / steps
+    # the shader clock the timed launches ran at (in-kernel clock counters)
+    sclk = float(np.mean(sclks))
     fepe = res.fepe()
     rse = np.sqrt((1 - fepe) / (n_e * np.maximum(fepe, 1e-300)))
 
     fwd_grad_ratio = None
-    if not a.no_grad:
+    batched_vs_single = None
+    if full and not a.no_grad:
         step(grad=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for _ in range(a.steps):
-            step(grad=True)
+        for _ in range(steps):
+            rg = step(grad=True)
         torch.cuda.synchronize()
-        fwd_grad_ratio = (time.perf_counter() - t1) / a.steps / dt
+        dtg = (time.perf_counter() - t1) / steps
+        fwd_grad_ratio = dtg / dt
+        # the plain single-job kernel: one forward gadep_run launch per energy,
+        # the same histories (each meets the same RSE)
+        for k, E in enumerate(w.energies):
+            ctx.run(w.source, [E], int(n_e[k]), 1002)
+        torch.cuda.synchronize()
+        reps = max(1, min(steps, 3))
+        t2 = time.perf_counter()
+        for _ in range(reps):
+            for k, E in enumerate(w.energies):
+                ctx.run(w.source, [E], int(n_e[k]), 1002)
+        torch.cuda.synchronize()
+        dts = (time.perf_counter() - t2) / reps
+        gf = rg.fepe()
+        batched_vs_single = {
+            "batched_grad_histories_per_s": total / dtg,
+            "single_job_histories_per_s": total / dts,
+            "batched_grad_over_single_job": dts / dtg,
+            "max_fepe_rse": float(np.sqrt((1 - gf) / (n_e * np.maximum(gf, 1e-300))).max()),
+            "batched_grad": f"one gadep_run_batch launch over the {len(w.energies)} energies with "
+                            f"dFEPE/ds for {n_groups} density groups",
+            "single_job": f"{len(w.energies)} gadep_run launches, one per energy, no gradients"}
 
     # event counts of the same histories (deterministic) for the op model
     ctx.set_option(gadep.OPT_COUNTERS, 1)
@@ -241,43 +314,20 @@ def main():
     lanes["time_share"] = {k: v / cyc_total for k, v in cyc.items()}
     k_ms = float(np.mean(kernel_ms))
     achieved = ops / (k_ms * 1e-3)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "T lane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": measured_traffic(),
-            "kernel_ms": k_ms, "ops_per_history": ops / total,
+    peak = PEAK_LANE_OPS * (sclk / PEAK_SCLK_MHZ if sclk else 1.0)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "T lane-op/s", "frac": achieved / peak,
+            "traffic": measured_traffic() if distance == 250.0 else None,
+            "kernel_ms": k_ms, "measured_sclk_mhz": sclk,
+            "peak_at_2400_mhz": PEAK_LANE_OPS / 1e12, "ops_per_history": ops / total,
             "events_per_history": {k: ev[k] / total for k in ev if not k.startswith("cycles_")},
             "active_lanes": lanes}
-
-    base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
-    line = {
-        "metric": "histories/s on 20k-tri HPGe mesh at <=0.5% FEPE RSE; fwd+grad/fwd cost",
-        "value": total / dt,
-        "unit": "histories/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": dt * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"hpge_coaxial_20236_facets_point_{distance:.0f}mm_12_energies",
-                   "n_facets": int(len(w.scene.tri)), "energies_keV": [round(e, 3) for e in w.energies],
-                   "histories_per_energy": [int(x) for x in n_e], "histories_per_step": total,
-                   "max_fepe_rse": float(rse.max())},
-        "fwd_grad_over_fwd": fwd_grad_ratio,
-        "fepe": [float(x) for x in fepe],
-        # per-event rates of the timed kernel (event counts of the same histories)
-        "rates": {"node_visits_per_s": ev["node_visits"] / (k_ms * 1e-3),
-                  "facet_tests_per_s": ev["tri_tests"] / (k_ms * 1e-3),
-                  "interactions_per_s": (ev["photo"] + ev["compton"] + ev["coherent"] + ev["pair"])
-                  / (k_ms * 1e-3),
-                  "segments_per_s": ev["segments"] / (k_ms * 1e-3)},
-        "roofline": roof,
-        "cpu_baseline": base,
-    }
-    print(json.dumps(line), flush=True)
-    ctx.close()
+    s = k_ms * 1e-3
+    rates = {"node_visits_per_s": ev["node_visits"] / s, "facet_tests_per_s": ev["tri_tests"] / s,
+             "interactions_per_s": (ev["photo"] + ev["compton"] + ev["coherent"] + ev["pair"]) / s,
+             "segments_per_s": ev["segments"] / s}
+    return {"w": w, "n_e": n_e, "total": total, "dt": dt, "fepe": fepe, "rse": rse, "roof": roof,
+            "rates": rates, "fwd_grad_ratio": fwd_grad_ratio, "batched_vs_single": batched_vs_single}
 
 
 # ---------------------------------------------------------------------------

@@ -88,13 +88,22 @@ typedef enum {
   GADEP_OPT_SPLIT_PCT = 11,   /* extra facet slots the transport BVH may add by spatial
                                  splits, % of its facets (100); 0 = no spatial splits;
                                  applies to meshes loaded afterwards                  */
-  GADEP_OPT_SCREEN = 12       /* 1 = first-flight screening (1): with exit planes and a
+  GADEP_OPT_SCREEN = 12,      /* 1 = first-flight screening (1): with exit planes and a
                                  point or beam source in the outermost shell's region,
                                  each wavefront follows 64 new histories at a time to
                                  the end of their first flight, tallies those that
                                  leave through the planes without nearing the inner
                                  shells, and transports the rest in full.  Tallies
                                  are identical either way                             */
+  GADEP_OPT_POOL = 13         /* 1 = pooled transport kernel: each wavefront keeps 96
+                                 photons in LDS for its 64 lanes, steps rays with full
+                                 lanes while set-up rays last, and runs outcomes, new
+                                 histories and set-up 64 photons at a time
+                                 (GADEP_OPT_PERIOD: lanes still traversing when such a
+                                 round starts, default 32; GADEP_OPT_BLOCK is unused);
+                                 0 = per-lane kernel (0; the faster one on MI355X: the
+                                 pooled kernel's LDS and registers allow 2 wavefronts
+                                 per SIMD against 3).  Tallies are the same either way */
 } gadep_option;
 gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t value);
 gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* value);
@@ -285,6 +294,13 @@ gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
  * context's stream right before and after it (the graph replay, when graphs
  * are on, which adds two tiny set-up kernels to the transport kernel). */
 gadep_status gadep_get_last_launch_ms(const gadep_ctx* ctx, double* ms);
+
+/* Shader clock [MHz] the last transport launch ran at: each wavefront reads
+ * the shader-clock counter (s_memtime) and the constant-rate counter
+ * (s_memrealtime) when it starts and when it ends; the ratio of the summed
+ * differences times the constant counter's rate.  For scaling the ALU peak
+ * of the roofline to the clock actually sustained. */
+gadep_status gadep_get_last_clock_mhz(const gadep_ctx* ctx, double* mhz);
 
 /* Pulse-height spectrum post-processing (the detector resolution the paper
  * leaves to the analysis after transport, Sec. 2.4 scoring on the host side).

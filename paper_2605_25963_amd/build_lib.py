@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgadep.so")
-SOURCES = ["transport.hip", "runtime.cpp", "mesh_prep.cpp", "detmesh.cpp"]
+SOURCES = ["transport.hip", "transport_pool.hip", "runtime.cpp", "mesh_prep.cpp", "detmesh.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -123,6 +123,10 @@ struct UnitRec {
 enum TallySlot : int {
   kT_Hist = 0, kT_Absorbed, kT_Fep, kT_CollEscape, kT_Lost, kT_Killed, kT_Glitch, kT_SrcFail,
   kT_SpecOvf, kT_EdepAct, kT_EdepTot, kT_EEsc, kT_ESrc,
+  // per wavefront, over its lifetime: shader-clock cycles (s_memtime) and
+  // ticks of the constant-rate clock (s_memrealtime); their ratio is the
+  // shader clock the launch ran at
+  kT_ClkCore, kT_ClkRef,
   kT_Score = 16, kT_FepScore = 24, kT_FepScore2 = 32,
   kT_Ev = 40,  // event counters, up to 24 slots
   kT_FepScore2Lo = 64,  // fractions of the FEP score^2 sums (see kScore2Fix)

@@ -28,6 +28,8 @@ hipError_t locate(const SceneRec& sc, const float* p, int64_t n, int32_t* region
 hipError_t philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, int64_t n, uint32_t* out,
                   hipStream_t s);
 hipError_t scratch_address(int device, void** out);
+hipError_t pool_launch(const TransportParams& P, int variant, int grid, hipStream_t s);
+hipError_t pool_occupancy(int variant, int depth, int pair, int* blocks_per_cu);
 hipError_t broaden(const double* in, double* out, int n_spectra, int n, double w, double a,
                    double b, hipStream_t s);
 }  // namespace gadep
@@ -147,6 +149,7 @@ struct gadep_ctx {
   int64_t exit_planes = 1;
   int64_t split_pct = 100;
   int64_t screen = 1;
+  int64_t pool = 0;
 
   DevBuf units, chunk_begin, scene_tab, sources, lines, regions, tally, spectra, cursor;
   void* h_tally = nullptr;  // pinned
@@ -154,6 +157,8 @@ struct gadep_ctx {
   gadep_counters last_counters{};
   bool have_counters = false;
   double last_ms = -1.0;
+  double last_sclk_mhz = -1.0;  // shader clock of the last transport launch
+  double ref_clock_khz = 100000.0;  // rate of the constant clock the kernels read
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   // graph cache
@@ -436,6 +441,39 @@ void to_tally(const unsigned long long* T, gadep_tally& t) {
   t.spectrum_overflow = T[kT_SpecOvf];
 }
 
+// The transport kernel the context's options select: the pooled kernel (one
+// wavefront per block) or the per-lane one (ctx->block threads).  grid <= 0:
+// from the occupancy of the kernel on every compute unit.
+hipError_t pick_grid(const gadep_ctx* ctx, int variant, int depth, int pair, int* grid) {
+  if (ctx->grid > 0) {
+    *grid = static_cast<int>(ctx->grid);
+    return hipSuccess;
+  }
+  int per_cu = 0;
+  hipError_t e = ctx->pool ? pool_occupancy(variant, depth, pair, &per_cu)
+                           : transport_occupancy(variant, static_cast<int>(ctx->block), depth, pair,
+                                                 &per_cu);
+  if (e != hipSuccess) return e;
+  *grid = per_cu * ctx->n_cu;
+  return hipSuccess;
+}
+
+hipError_t launch_transport(const gadep_ctx* ctx, const TransportParams& K, int variant, int grid,
+                            hipStream_t s) {
+  return ctx->pool ? pool_launch(K, variant, grid, s)
+                   : transport_launch(K, variant, grid, static_cast<int>(ctx->block), s);
+}
+
+// shader clock of the launch whose tally rows are T[n_units][kT_Slots]
+void note_clock(gadep_ctx* ctx, const unsigned long long* T, int32_t n_units) {
+  double core = 0, ref = 0;
+  for (int32_t u = 0; u < n_units; ++u) {
+    core += static_cast<double>(T[static_cast<int64_t>(u) * kT_Slots + kT_ClkCore]);
+    ref += static_cast<double>(T[static_cast<int64_t>(u) * kT_Slots + kT_ClkRef]);
+  }
+  ctx->last_sclk_mhz = ref > 0 ? core / ref * ctx->ref_clock_khz * 1e-3 : -1.0;
+}
+
 gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, double* grads,
                      double* grads_var, int32_t n_grad_cols, float* elapsed_ms = nullptr) {
   gadep_status s = sync_xs(ctx);
@@ -495,19 +533,15 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   const int variant =
       (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0) | (vol ? 8 : 0) |
       (K.pair ? 16 : 0);
-  const int block = static_cast<int>(ctx->block);
-  int grid = static_cast<int>(ctx->grid);
-  if (grid <= 0) {
-    int per_cu = 0;
-    HIP_TRY(transport_occupancy(variant, block, P.depth, K.pair, &per_cu), "occupancy");
-    if (per_cu < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");
-    grid = per_cu * ctx->n_cu;
-  }
+  const int block = ctx->pool ? 64 : static_cast<int>(ctx->block);
+  int grid = 0;
+  HIP_TRY(pick_grid(ctx, variant, P.depth, K.pair, &grid), "occupancy");
+  if (grid < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");
 
   // graph key: everything baked into the captured launches
-  std::vector<uint8_t> key(sizeof(TransportParams) + 4 * sizeof(int64_t));
+  std::vector<uint8_t> key(sizeof(TransportParams) + 5 * sizeof(int64_t));
   memcpy(key.data(), &K, sizeof K);
-  int64_t extra[4] = {variant, grid, block, static_cast<int64_t>(tally_words + spec_words)};
+  int64_t extra[5] = {variant, grid, block, static_cast<int64_t>(tally_words + spec_words), ctx->pool};
   memcpy(key.data() + sizeof K, extra, sizeof extra);
 
   if (!ctx->ev0) HIP_TRY(hipEventCreate(&ctx->ev0), "event");
@@ -520,7 +554,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
       e = locate_units(static_cast<UnitRec*>(ctx->units.p), nu,
                        static_cast<const SceneRec*>(ctx->scene_tab.p),
                        static_cast<const SourceRec*>(ctx->sources.p), P.depth, ctx->stream);
-    if (e == hipSuccess) e = transport_launch(K, variant, grid, block, ctx->stream);
+    if (e == hipSuccess) e = launch_transport(ctx, K, variant, grid, ctx->stream);
     return e;
   };
   // the enqueue below is wrapped by two events: the launch duration
@@ -557,7 +591,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     }
     HIP_TRY(hipGraphLaunch(ctx->graph, ctx->stream), "graph launch");
   } else {
-    HIP_TRY(transport_launch(K, variant, grid, block, ctx->stream), "transport launch");
+    HIP_TRY(launch_transport(ctx, K, variant, grid, ctx->stream), "transport launch");
   }
   HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream), "event");
 
@@ -585,6 +619,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   }
 
   const unsigned long long* T = static_cast<const unsigned long long*>(ctx->h_tally);
+  note_clock(ctx, T, nu);
   gadep_counters cnt{};
   for (int32_t u = 0; u < nu; ++u) {
     const unsigned long long* Tu = T + static_cast<int64_t>(u) * kT_Slots;
@@ -676,6 +711,11 @@ gadep_status gadep_create(int device, void* hip_stream, gadep_ctx** out) {
     return GADEP_E_HIP;
   }
   ctx->n_cu = prop.multiProcessorCount;
+  {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+      ctx->ref_clock_khz = khz;
+  }
   // the no-allocation run's scratch: this device's copy of the array (the
   // device is current), and its host staging
   if (scratch_address(device, &ctx->scratch) != hipSuccess) ctx->scratch = nullptr;
@@ -764,6 +804,9 @@ gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t v) {
     case GADEP_OPT_SCREEN:
       ctx->screen = v ? 1 : 0;
       return GADEP_OK;
+    case GADEP_OPT_POOL:
+      ctx->pool = v ? 1 : 0;
+      return GADEP_OK;
     default:
       return set_err(ctx, GADEP_E_ARG, "unknown option");
   }
@@ -784,6 +827,7 @@ gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* v) 
     case GADEP_OPT_EXIT_PLANES: *v = ctx->exit_planes; return GADEP_OK;
     case GADEP_OPT_SPLIT_PCT: *v = ctx->split_pct; return GADEP_OK;
     case GADEP_OPT_SCREEN: *v = ctx->screen; return GADEP_OK;
+    case GADEP_OPT_POOL: *v = ctx->pool; return GADEP_OK;
     default: return GADEP_E_ARG;
   }
 }
@@ -1098,14 +1142,9 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
   for (const Material& m : ctx->mats)
     if (m.set && m.pair) K.pair = 1;
   const int variant = (spectrum ? 2 : 0) | (src->kind == GADEP_SRC_CYL ? 8 : 0) | (K.pair ? 16 : 0);
-  const int block = static_cast<int>(ctx->block);
-  int grid = static_cast<int>(ctx->grid);
-  if (grid <= 0) {
-    int per_cu = 0;
-    HIP_TRY(transport_occupancy(variant, block, K.stack_depth, K.pair, &per_cu), "occupancy");
-    if (per_cu < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");
-    grid = per_cu * ctx->n_cu;
-  }
+  int grid = 0;
+  HIP_TRY(pick_grid(ctx, variant, K.stack_depth, K.pair, &grid), "occupancy");
+  if (grid < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");
   // the array keeps the last call's contents: clear the tallies, spectra and
   // cursors with a fill kernel
   const int64_t tally_words = static_cast<int64_t>(n_energies) * kT_Slots;
@@ -1117,7 +1156,7 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
                        reinterpret_cast<const SourceRec*>(base + kNaSource), K.stack_depth,
                        ctx->stream),
           "locate units");
-  HIP_TRY(transport_launch(K, variant, grid, block, ctx->stream), "transport launch");
+  HIP_TRY(launch_transport(ctx, K, variant, grid, ctx->stream), "transport launch");
   HIP_TRY(hipMemcpyAsync(H.tally, K.tally, tally_words * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, ctx->stream),
           "tally D2H");
@@ -1128,6 +1167,7 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
                              ctx->stream),
               "spectra D2H");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "transport");
+  note_clock(ctx, H.tally, n_energies);
   for (int32_t u = 0; u < n_energies; ++u) to_tally(H.tally + static_cast<int64_t>(u) * kT_Slots, out[u]);
   return GADEP_OK;
 }
@@ -1185,15 +1225,18 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
   ctx->graphs = 0;
   float best = INFINITY;
   int64_t best_block = saved_block, best_claim = saved_claim, best_period = saved_period;
-  // block size x claim size x park threshold (lanes parked before the wavefront
-  // runs the batched physics); tallies do not depend on any of them
-  const int64_t blocks[] = {128, 256};
+  // block size x claim size x threshold (per-lane kernel: lanes parked before
+  // the wavefront runs the batched physics; pooled kernel: lanes still
+  // traversing when a housekeeping round starts); tallies depend on none of
+  // them.  The pooled kernel always runs one wavefront per block.
+  const std::vector<int64_t> blocks = ctx->pool ? std::vector<int64_t>{64} : std::vector<int64_t>{128, 256};
   const int64_t claims[] = {16, 64};
-  const int64_t periods[] = {16, 24, 32};
+  const std::vector<int64_t> periods =
+      ctx->pool ? std::vector<int64_t>{16, 24, 32, 40, 48} : std::vector<int64_t>{16, 24, 32};
   for (int64_t b : blocks)
     for (int64_t c : claims)
       for (int64_t q : periods) {
-        ctx->block = b;
+        if (!ctx->pool) ctx->block = b;
         ctx->claim = c;
         ctx->period = q;
         Plan P;
@@ -1216,7 +1259,7 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
           best_period = q;
         }
       }
-  ctx->block = best_block;
+  if (!ctx->pool) ctx->block = best_block;
   ctx->claim = best_claim;
   ctx->period = best_period;
   ctx->graphs = saved_graphs;
@@ -1230,6 +1273,13 @@ gadep_status gadep_get_last_launch_ms(const gadep_ctx* ctx, double* ms) {
   if (!ctx || !ms) return GADEP_E_ARG;
   if (ctx->last_ms < 0) return GADEP_E_STATE;
   *ms = ctx->last_ms;
+  return GADEP_OK;
+}
+
+gadep_status gadep_get_last_clock_mhz(const gadep_ctx* ctx, double* mhz) {
+  if (!ctx || !mhz) return GADEP_E_ARG;
+  if (ctx->last_sclk_mhz < 0) return GADEP_E_STATE;
+  *mhz = ctx->last_sclk_mhz;
   return GADEP_OK;
 }
 

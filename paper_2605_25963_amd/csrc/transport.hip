@@ -19,10 +19,9 @@
 
 #include "device_common.h"
 #include "gadep_internal.h"
+#include "transport_common.h"
 
 namespace gadep {
-
-constexpr int kWave = 64;
 
 // ---------------------------------------------------------------------------
 // closest hit with the region-consistency filter
@@ -154,100 +153,6 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
 }
 
 // ---------------------------------------------------------------------------
-// physics helpers
-
-struct Xs {
-  int k;
-  float w;
-};
-
-__device__ __forceinline__ Xs xs_index(float E, float ln_e0, float inv_dlne, int n_e) {
-  const float x = (hw_log(E) - ln_e0) * inv_dlne;
-  int k = static_cast<int>(floorf(x));
-  k = k < 0 ? 0 : (k > n_e - 2 ? n_e - 2 : k);
-  float w = x - static_cast<float>(k);
-  w = fminf(fmaxf(w, 0.0f), 1.0f);
-  return {k, w};
-}
-
-// partial linear attenuation [1/mm] of a region: log-log interpolation of
-// each partial, mu_i = mult * exp(lerp(ln(mu/rho)_i)).  The products are kept
-// out of contraction, so that mu = mp + mc + mh comes out the same wherever it
-// is formed (screening decides a flight with a per-unit value that must equal
-// the set-up's).
-__device__ __forceinline__ void xs_mu(const float4* __restrict__ xs, int n_e, const RegionRec& rr,
-                                      Xs ix, float& mp, float& mc, float& mh) {
-#pragma clang fp contract(off)
-  if (rr.mult > 0.0f) {
-    const float4 lo = gload(xs, rr.material * n_e + ix.k);
-    const float4 hi = gload(xs, rr.material * n_e + ix.k + 1);
-    mp = rr.mult * __expf(fmaf(ix.w, hi.x - lo.x, lo.x));
-    mc = rr.mult * __expf(fmaf(ix.w, hi.y - lo.y, lo.y));
-    mh = rr.mult * __expf(fmaf(ix.w, hi.z - lo.z, lo.z));
-  } else {
-    mp = mc = mh = 0.0f;
-  }
-}
-
-// pair-production partial [1/mm]; zero unless `on` (some material has one)
-// and E lies above the threshold 2 m_e c^2
-__device__ __forceinline__ float xs_pair(const float4* __restrict__ xs, int n_e, const RegionRec& rr,
-                                         Xs ix, float E, bool on) {
-#pragma clang fp contract(off)
-  if (!on || !(E > 2.0f * kMec2) || !(rr.mult > 0.0f)) return 0.0f;
-  const float lo = gload(xs, rr.material * n_e + ix.k).w;
-  const float hi = gload(xs, rr.material * n_e + ix.k + 1).w;
-  return rr.mult * __expf(fmaf(ix.w, hi - lo, lo));
-}
-
-// New direction at polar cosine ct and azimuth 2 pi u about (dx, dy, dz), in an
-// orthonormal basis built branch-free from the direction (Duff et al., JCGT
-// 2017).  sin/cos of 2 pi u come from the hardware sine, which takes
-// revolutions.
-__device__ __forceinline__ void turn(float& dx, float& dy, float& dz, float ct, float u) {
-  const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
-  const float cp = __builtin_amdgcn_cosf(u), sp = __builtin_amdgcn_sinf(u);
-  const float s = copysignf(1.0f, dz);
-  const float a = -1.0f / (s + dz);
-  const float b = dx * dy * a;
-  const float b1x = 1.0f + s * dx * dx * a, b1y = s * b, b1z = -s * dx;
-  const float b2x = b, b2y = s + dy * dy * a, b2z = -dy;
-  const float ux = st * cp, uy = st * sp;
-  float nx = ct * dx + ux * b1x + uy * b2x;
-  float ny = ct * dy + ux * b1y + uy * b2y;
-  float nz = ct * dz + ux * b1z + uy * b2z;
-  const float inv = rsqrtf(nx * nx + ny * ny + nz * nz);
-  dx = nx * inv;
-  dy = ny * inv;
-  dz = nz * inv;
-}
-
-// ---------------------------------------------------------------------------
-// wavefront helpers
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) x += __shfl_xor(x, m, kWave);
-  return x;
-}
-
-__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
-  return (static_cast<unsigned long long>(hi) << 32) | lo;
-}
-
-// Energies in keV (0 <= E < 65536) in units of 2^-16 keV: E * 2^16 is exact in
-// FP32, so rounding it to an integer in FP32 gives the same value as FP64.
-__device__ __forceinline__ unsigned long long fx_kev(float e) {
-  return static_cast<unsigned long long>(__float2uint_rn(e * 65536.0f));
-}
-
-__device__ __forceinline__ unsigned long long fx(double v, double scale) {
-  return static_cast<unsigned long long>(__double2ll_rn(v * scale));
-}
-
-// ---------------------------------------------------------------------------
 // transport kernel
 //
 // Persistent state machine.  Every iteration each lane with an open
@@ -258,19 +163,6 @@ __device__ __forceinline__ unsigned long long fx(double v, double scale) {
 // crossing, interaction, escape, scoring), takes new histories for lanes that
 // need one and sets up the next traversals, for all parked lanes at once.
 
-// kSample: draw a volume-source point; kLaunch: emission point settled,
-// draw direction and first flight
-// kResume: the photon is done but a pair event left a second one waiting
-enum Phase : int { kNeed = 0, kTrav = 1, kParked = 2, kSetup = 3, kSample = 4, kLaunch = 5,
-                   kResume = 6 };
-constexpr int kMaxEmitAttempts = 1000;  // volume-source rejection tries per history
-constexpr int kQueue = 128;             // screened histories a wavefront can hold
-constexpr int kSlow = 128;              // set-aside short first flights a wavefront can hold
-constexpr int kXcds = 8;                // accelerator dies (XCDs) of an MI355X, one L2 each
-// probe direction for localising volume-source points (generic: no axis or
-// facet plane of the synthetic meshes is parallel to it)
-__constant__ float kLocateDir[3] = {0.4830462f, 0.3714437f, 0.7929236f};
-constexpr int kExitPlane = -2;  // best_id of a crossing through an exit plane
 
 // GRAD: score-function tallies; SPEC: pulse-height spectra; COUNT: event
 // counters; VOL: some unit has a volume source (emission points are
@@ -304,6 +196,8 @@ transport_kernel(TransportParams P) {
   if (PAIR) wait[6 * stride] = -1;
   for (int i = lane; i < kT_Slots; i += kWave) wt[i] = 0;
 
+  const uint64_t clk_core0 = __builtin_amdgcn_s_memtime();
+  const uint64_t clk_ref0 = __builtin_amdgcn_s_memrealtime();
   const uint32_t k0 = P.seed_lo, k1 = P.seed_hi;
   const int64_t total_chunks = P.chunk_begin[P.n_units];
   const int park = P.period > 0 ? (P.period > kWave ? kWave : P.period) : 24;
@@ -371,6 +265,8 @@ transport_kernel(TransportParams P) {
   // sp: depth of the LDS stack times the column stride (its entries are
   // stack[k * stride]), so pushes and pops need no multiply
   int node = kDone, sp = 0, tri_next = 0, tri_end = 0, best_id = -1, best_reg = 0;
+  // a leaf met while facets of an earlier one were still pending (kDone: none)
+  int leaf2 = kDone;
   // per-lane accumulators of the per-history (frequent) quantities
   unsigned long long acc_hist = 0, acc_eunc = 0, acc_esrc = 0;
   uint32_t ev[kEv_N];
@@ -971,6 +867,7 @@ transport_kernel(TransportParams P) {
         node = gload(S.roots, Src.region);
         sp = 0;
         tri_next = tri_end = 0;
+        leaf2 = kDone;
         best_id = -1;
         phase = node == kDone ? kParked : kTrav;
       } else if (phase == kSetup) {
@@ -984,6 +881,7 @@ transport_kernel(TransportParams P) {
         trej = INFINITY;
         sp = 0;
         tri_next = tri_end = 0;
+        leaf2 = kDone;
         best_id = -1;
         // the BVH of the facets that bound this region: no other facet can
         // be crossed next
@@ -1022,13 +920,27 @@ transport_kernel(TransportParams P) {
     }
 
     // ================= one traversal step per traversing lane =================
-    // one node when no facet is pending, then one facet of a pending leaf: a
-    // lane whose node step reaches a leaf tests its first facet in the same
-    // iteration (every iteration runs both kinds of step for some lanes)
+    // One node and one facet per lane and iteration.  A lane keeps walking the
+    // tree while facets of a leaf are still pending (speculative traversal,
+    // Aila and Laine 2009): a second leaf it meets waits in `leaf2`, so that
+    // node and facet steps overlap instead of alternating.  Nodes are culled
+    // with the nearest hit found so far, which can only keep more of them.
     bool did_node = false, did_tri = false;
     const uint64_t clk_trav = COUNT ? __builtin_amdgcn_s_memtime() : 0;
     if (phase == kTrav) {
-      if (tri_next >= tri_end && node >= 0) {
+      const bool busy = tri_next < tri_end;
+      if (node < 0 && node != kDone && (!busy || leaf2 == kDone)) {
+        // a leaf taken from the stack (or a far child): test it now, or
+        // postpone it and keep walking
+        const int code = ~node;
+        if (!busy) {
+          tri_next = code >> 3;
+          tri_end = tri_next + (code & 7);
+        } else {
+          leaf2 = node;
+        }
+        node = sp > 0 ? stack[sp -= stride] : kDone;
+      } else if (node >= 0 && (!busy || leaf2 == kDone)) {
         // one node: both child boxes against [0, tbest]
         if (COUNT) ev[kEv_NodeVisits]++;
         did_node = true;
@@ -1051,10 +963,15 @@ transport_kernel(TransportParams P) {
         if (near == kDone) {
           node = sp > 0 ? stack[sp -= stride] : kDone;
         } else if (near < 0) {
-          // nearest child is a leaf: test its facets next, then go to `far`
-          const int code = ~near;
-          tri_next = code >> 3;
-          tri_end = tri_next + (code & 7);
+          // nearest child is a leaf: test its facets next (or after the
+          // pending ones), then go to `far`
+          if (!busy) {
+            const int code = ~near;
+            tri_next = code >> 3;
+            tri_end = tri_next + (code & 7);
+          } else {
+            leaf2 = near;
+          }
           node = far != kDone ? far : (sp > 0 ? stack[sp -= stride] : kDone);
         } else {
           if (far != kDone && sp < sp_cap) {
@@ -1064,11 +981,11 @@ transport_kernel(TransportParams P) {
           node = near;
         }
       }
-      if (tri_next >= tri_end && node < 0 && node != kDone) {
-        const int code = ~node;  // a leaf taken from the stack
+      if (tri_next >= tri_end && leaf2 != kDone) {
+        const int code = ~leaf2;
         tri_next = code >> 3;
         tri_end = tri_next + (code & 7);
-        node = sp > 0 ? stack[sp -= stride] : kDone;
+        leaf2 = kDone;
       }
       if (tri_next < tri_end) {
         // one facet test, with the region-consistency filter; the facet just
@@ -1095,7 +1012,7 @@ transport_kernel(TransportParams P) {
           }
         }
       }
-      if (tri_next >= tri_end && node == kDone) phase = kParked;
+      if (tri_next >= tri_end && node == kDone && leaf2 == kDone) phase = kParked;
     }
     if (COUNT) {
       const bool any_node = __ballot(did_node) != 0, any_tri = __ballot(did_tri) != 0;
@@ -1108,6 +1025,11 @@ transport_kernel(TransportParams P) {
       }
     }
   }
+  if (lane == 0) {
+    wt[kT_ClkCore] += __builtin_amdgcn_s_memtime() - clk_core0;
+    wt[kT_ClkRef] += __builtin_amdgcn_s_memrealtime() - clk_ref0;
+  }
+  __builtin_amdgcn_wave_barrier();
   flush();
 }
 

@@ -23,7 +23,7 @@ ACTIVE = 1
 SRC_POINT, SRC_BEAM, SRC_CYL = 0, 1, 2
 
 OPT_MAX_STEPS, OPT_BLOCK, OPT_PERIOD, OPT_CLAIM, OPT_VALIDATE, OPT_MIN_GAP_NM, OPT_GRAPHS, \
-    OPT_COUNTERS, OPT_GRID, OPT_EXIT_PLANES, OPT_SPLIT_PCT, OPT_SCREEN = range(1, 13)
+    OPT_COUNTERS, OPT_GRID, OPT_EXIT_PLANES, OPT_SPLIT_PCT, OPT_SCREEN, OPT_POOL = range(1, 14)
 
 STATUS = {
     0: "GADEP_OK", -1: "GADEP_E_ARG", -2: "GADEP_E_MESH_OPEN", -3: "GADEP_E_MESH_ORIENT",
@@ -105,7 +105,7 @@ EXPORTS = [
     "gadep_run_grad", "gadep_run_batch", "gadep_autotune", "gadep_get_counters",
     "gadep_broaden_dev", "gadep_raycast", "gadep_locate", "gadep_mesh_prepare",
     "gadep_get_last_launch_ms", "gadep_detmesh", "gadep_write_vrml", "gadep_philox",
-    "gadep_run_noalloc",
+    "gadep_run_noalloc", "gadep_get_last_clock_mhz",
 ]
 
 _lib = None
@@ -152,6 +152,7 @@ def lib():
         "gadep_autotune": (i32, [p, C.POINTER(Job), i32, i64, i32p, i32p, i32p]),
         "gadep_get_counters": (i32, [p, C.POINTER(Counters)]),
         "gadep_get_last_launch_ms": (i32, [p, C.POINTER(C.c_double)]),
+        "gadep_get_last_clock_mhz": (i32, [p, C.POINTER(C.c_double)]),
         "gadep_broaden_dev": (i32, [p, p, p, i32, i32, C.c_double, C.c_double, C.c_double]),
         "gadep_raycast": (i32, [p, i32, f32p, f32p, i32p, i64, f32p, i32p, i32p]),
         "gadep_locate": (i32, [p, i32, f32p, i64, i32p]),
@@ -411,6 +412,11 @@ class Context:
         self._check(lib().gadep_get_last_launch_ms(self.h, C.byref(v)))
         return v.value
 
+    def get_last_clock_mhz(self):
+        v = C.c_double()
+        self._check(lib().gadep_get_last_clock_mhz(self.h, C.byref(v)))
+        return v.value
+
     def get_counters(self):
         c = Counters()
         self._check(lib().gadep_get_counters(self.h, C.byref(c)))
@@ -556,6 +562,7 @@ gadep_run_batch = Context.run_batch
 gadep_autotune = Context.autotune
 gadep_get_counters = Context.get_counters
 gadep_get_last_launch_ms = Context.get_last_launch_ms
+gadep_get_last_clock_mhz = Context.get_last_clock_mhz
 gadep_raycast = Context.raycast
 gadep_locate = Context.locate
 gadep_philox = Context.philox

@@ -103,18 +103,23 @@ def test_detector_gradients_match_oracle_and_crn_fd(G, ctx, orc):
     # comes from nb batches of disjoint history ranges.  N is sized so that
     # 3 combined sigma lie below 2 % of the derivative for the dead layer at
     # 100 keV and the crystal and the matrix at both energies: there the 2 %
-    # bar is asserted on its own.  The dead layer at 661.7 keV, the window,
-    # the end-cap and the cup change FEPE by too few histories
-    # for a CRN difference to resolve 2 % at a test's size (the end-cap and the
-    # cup enter mostly through the micrometre separation gaps); they are held
-    # to 3 combined sigma, and every case is printed.
-    n_fd, nb, h = 1_600_000_000, 8, 0.01
+    # bar is asserted on its own.  The dead layer at 661.7 keV, the window, the
+    # end-cap and the cup change FEPE by too few histories for a +-1 % CRN
+    # difference to resolve 2 % at a test's size (the end-cap and the cup
+    # enter mostly through the micrometre separation gaps); they are held to
+    # 3 combined sigma.  The thin Al and Ge layers are checked again at
+    # +-20 %: FEPE depends on their density as exp(-s a) with a ~ 0.01-0.1, so
+    # the central difference's own error, a^2 h^2 / 6 relative, stays below
+    # 1e-3 there, and the 2 % bar holds on its own.  Every case is printed.
+    n_fd, nb = 1_600_000_000, 32
     rg = ctx.run_grad(w.source, E, n_fd, 41, scales)
-    strict = {("dead", 100.0), ("crystal", 100.0), ("crystal", 661.7), ("matrix", 100.0),
-              ("matrix", 661.7)}
+    strict = {(0.01, "dead", 100.0), (0.01, "crystal", 100.0), (0.01, "crystal", 661.7),
+              (0.01, "matrix", 100.0), (0.01, "matrix", 661.7), (0.2, "dead", 661.7),
+              (0.2, "window", 100.0), (0.2, "window", 661.7)}
     seen = set()
+    cases = [(0.01, gi) for gi in range(6)] + [(0.2, 0), (0.2, 2)]
     try:
-        for gi in range(6):
+        for h, gi in cases:
             up = list(scales)
             dn = list(scales)
             up[gi] += h
@@ -134,14 +139,14 @@ def test_detector_gradients_match_oracle_and_crn_fd(G, ctx, orc):
                 comb = math.hypot(gs, fd_sig[k])
                 rel = abs(g - fd[k]) / abs(fd[k]) if fd[k] else math.inf
                 name = w.groups[gi]
-                print(f"grad {name:8s} E {E[k]:6.1f}: sf {g:+.4e} (sd {gs:.1e})  fd {fd[k]:+.4e} "
+                print(f"grad {name:8s} E {E[k]:6.1f} h {h:4.2f}: sf {g:+.4e} (sd {gs:.1e})  fd {fd[k]:+.4e} "
                       f"(sd {fd_sig[k]:.1e})  rel diff {rel:.2%}  3 sigma {3 * comb / abs(fd[k]):.2%}",
                       flush=True)
                 if 3 * comb <= 0.02 * abs(fd[k]):
-                    assert abs(g - fd[k]) <= 0.02 * abs(fd[k]), (name, E[k], g, fd[k])
-                    seen.add((name, E[k]))
+                    assert abs(g - fd[k]) <= 0.02 * abs(fd[k]), (name, h, E[k], g, fd[k])
+                    seen.add((h, name, E[k]))
                 else:
-                    assert abs(g - fd[k]) <= 3 * comb, (name, E[k], g, fd[k], comb)
+                    assert abs(g - fd[k]) <= 3 * comb, (name, h, E[k], g, fd[k], comb)
     finally:
         ctx.set_scales(scales)
     assert strict <= seen, strict - seen
