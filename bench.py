@@ -192,6 +192,9 @@ def main():
                 "histories_per_step": mn["total"], "max_fepe_rse": float(mn["rse"].max()),
                 "frac": mn["roof"]["frac"], "kernel_ms": mn["roof"]["kernel_ms"],
                 "active_lanes": mn["roof"]["active_lanes"]}
+    cone = None
+    if a.workload == "c2" and not a.quick:
+        cone = measure_cone(a, torch, gadep, C, ctx, min(a.steps, 5))
     w = m["w"]
     base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
     line = {
@@ -217,10 +220,47 @@ def main():
         "rates": m["rates"],
         "roofline": m["roof"],
         "c2_source_100mm": near,
+        "cone_emission": cone,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def measure_cone(a, torch, gadep, C, ctx, steps):
+    """The metric's detector and source with cone emission (variance reduction,
+    not the metric): histories start only towards the detector and carry the
+    weight Omega/4pi.  N per energy is sized for the same 0.5 % FEPE RSE; the
+    analog-equivalent rate counts the analog histories that RSE would take."""
+    w = C.c2_hpge(n_histories=0)
+    gadep.load_workload(ctx, w)
+    src = C.Source(C.KIND_CONE, pos=w.source.pos)
+
+    def jobs(n_per_e):
+        return [dict(source=src, energies=[E], n_histories=int(n_per_e[k]), stream=k)
+                for k, E in enumerate(w.energies)]
+
+    pilot = ctx.run_batch(jobs([1e6] * len(w.energies)), 998)
+    wt = pilot.weights()
+    q0 = np.maximum(pilot.fepe() / wt, 1e-12)  # FEP probability per cone history
+    q = np.maximum(q0 - 3.0 * np.sqrt(q0 * (1 - q0) / 1e6), 0.5 * q0)
+    n_c = np.maximum(1e6, np.ceil((1 - q) / (q * 0.005 ** 2))).astype(np.int64)
+    J = jobs(n_c)
+    ctx.run_batch(J, 1002)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = ctx.run_batch(J, 1002)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    p = r.fepe()
+    rse = r.fepe_sigma() / np.maximum(p, 1e-300)
+    n_analog = np.sum((1 - p) / (np.maximum(p, 1e-300) * rse ** 2))
+    return {"value": float(n_c.sum()) / dt, "unit": "histories/s", "weight": float(wt[0]),
+            "histories_per_energy": [int(x) for x in n_c], "ms_per_step": dt * 1e3,
+            "max_fepe_rse": float(rse.max()),
+            "analog_equivalent_histories_per_s": float(n_analog) / dt,
+            "fepe": [float(x) for x in p]}
 
 
 def measure(a, torch, gadep, C, ctx, distance, steps, warmup, full):

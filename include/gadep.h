@@ -160,10 +160,25 @@ gadep_status gadep_set_scales(gadep_ctx* ctx, const float* scales, int32_t n_sca
 /* ----------------------------------------------------------------------------
  * sources and tallies */
 
-typedef enum { GADEP_SRC_POINT = 0, GADEP_SRC_BEAM = 1, GADEP_SRC_CYL = 2 } gadep_source_kind;
+/* GADEP_SRC_CONE: an isotropic point source of which only the directions that
+ * can meet the inner shells are followed (variance reduction for distant
+ * sources; not a step of the paper): every history starts in the cone that
+ * subtends the bounding sphere of the shells inside the outermost one (of all
+ * shells when the outermost is not a convex exit shell) and stands for the
+ * weight w = (1 - cos theta_c) / 2 = Omega / 4 pi of the emitted photons,
+ * reported in gadep_tally.weight (FEPE = weight * n_fep / n_histories).  The
+ * photons it leaves out cross only the region around the source, so FEPE is
+ * unchanged as long as that region has no coherent partial (an elastic
+ * scatter there could send such a photon into the detector with its full
+ * energy): a source in a region whose material has one is rejected
+ * (GADEP_E_ARG).  Spectra and efficiencies other than FEPE lose the photons
+ * scattered into the detector from outside the cone.  A source inside that
+ * sphere emits into 4 pi (weight 1). */
+typedef enum { GADEP_SRC_POINT = 0, GADEP_SRC_BEAM = 1, GADEP_SRC_CYL = 2,
+               GADEP_SRC_CONE = 3 } gadep_source_kind;
 typedef struct {
   int32_t kind;          /* gadep_source_kind                                      */
-  float pos_mm[3];       /* POINT/BEAM: origin.  CYL: centre of the base face      */
+  float pos_mm[3];       /* POINT/BEAM/CONE: origin.  CYL: centre of the base face */
   float dir[3];          /* BEAM: direction (normalised here)                      */
   float r_in_mm, r_out_mm, h_mm; /* CYL: uniform in r_in <= r <= r_out, 0 <= z <= h
                                     (axis +z); points outside `region` rejected    */
@@ -186,6 +201,8 @@ typedef struct {
   int32_t n_channels;        /* in */
   float channel_keV;         /* in */
   uint64_t spectrum_overflow;/* out: histories with E_dep >= n_channels*channel_keV */
+  double weight;             /* out: emitted photons each history stands for (1, or
+                                Omega / 4 pi for GADEP_SRC_CONE)                   */
 } gadep_tally;
 
 /* ----------------------------------------------------------------------------

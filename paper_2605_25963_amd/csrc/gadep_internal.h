@@ -93,7 +93,7 @@ constexpr int32_t kUnitExitEscapes = 1;  // entering the (void) world ends the h
 // through its planes, and its segments search outer_root (the other shells).
 constexpr int32_t kUnitExitPlanes = 2;
 
-enum SourceKind : int32_t { kPoint = 0, kBeam = 1, kCyl = 2 };
+enum SourceKind : int32_t { kPoint = 0, kBeam = 1, kCyl = 2, kCone = 3 };
 
 struct SourceRec {
   int32_t kind;
@@ -103,7 +103,7 @@ struct SourceRec {
   int32_t region;
   int32_t n_lines;
   int32_t line_off;  // into the line table (float2: keV, cumulative probability)
-  int32_t pad;
+  float cone_cos;    // kCone: directions uniform in the cone of this half-angle cosine about dir
 };
 
 struct UnitRec {

@@ -56,6 +56,9 @@ struct Scene {
   int32_t outer_region = 0;
   float trans_lo[3] = {0, 0, 0}, trans_hi[3] = {0, 0, 0};
   float outer_lo[3] = {0, 0, 0}, outer_hi[3] = {0, 0, 0};
+  // box of the shells inside a convex exit shell (of all shells without one):
+  // the target of cone emission
+  double inner_lo[3] = {0, 0, 0}, inner_hi[3] = {0, 0, 0};
   void* d_nodes = nullptr;
   void* d_tris = nullptr;
   void* d_planes = nullptr;
@@ -250,6 +253,7 @@ struct Plan {
   std::vector<float> lines;
   std::vector<RegionRec> regions;
   std::vector<double> unit_energy;  // for reporting
+  std::vector<double> unit_weight;  // photons each history stands for (cone emission)
   bool spectrum = false;
   int32_t n_channels = 0;
   float channel_keV = 0;
@@ -258,7 +262,7 @@ struct Plan {
 };
 
 gadep_status check_source(gadep_ctx* ctx, const gadep_source& s, const Scene& sc) {
-  if (s.kind < GADEP_SRC_POINT || s.kind > GADEP_SRC_CYL)
+  if (s.kind < GADEP_SRC_POINT || s.kind > GADEP_SRC_CONE)
     return set_err(ctx, GADEP_E_ARG, "source: unknown kind");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(s.pos_mm[a])) return set_err(ctx, GADEP_E_ARG, "source: non-finite position");
@@ -292,6 +296,41 @@ gadep_status check_energy(gadep_ctx* ctx, double E) {
     return set_err(ctx, GADEP_E_XS, "energy " + std::to_string(E) + " keV outside the table grid");
   if (!(E < 65536.0))  // energy tallies count 2^-16 keV units in 32 bits per history
     return set_err(ctx, GADEP_E_ARG, "energy " + std::to_string(E) + " keV: at most 65536 keV");
+  return GADEP_OK;
+}
+
+// Cone emission of a GADEP_SRC_CONE source towards the scene's inner box:
+// axis (unit, from the source to the centre of the box's bounding sphere),
+// cosine of the half-angle (-1: the whole sphere) and the weight Omega/4pi.
+// The sphere's radius is raised by 1e-4 relative so that rounding of the
+// sampled directions can never exclude one that meets the box.
+gadep_status cone_setup(gadep_ctx* ctx, const Scene& sc, const gadep_source& src,
+                        const RegionRec* regions, SourceRec& sr, double& weight) {
+  weight = 1.0;
+  sr.cone_cos = -1.0f;
+  if (src.kind != GADEP_SRC_CONE) return GADEP_OK;
+  double c[3], r2 = 0, d2 = 0;
+  for (int a = 0; a < 3; ++a) {
+    c[a] = 0.5 * (sc.inner_lo[a] + sc.inner_hi[a]);
+    const double h = 0.5 * (sc.inner_hi[a] - sc.inner_lo[a]);
+    r2 += h * h;
+    d2 += (src.pos_mm[a] - c[a]) * (src.pos_mm[a] - c[a]);
+  }
+  const double R = sqrt(r2) * (1.0 + 1e-4), D = sqrt(d2);
+  // the region around the source must not scatter elastically (see gadep.h)
+  for (int32_t r = 0; r < sc.n_regions; ++r) {
+    if (r != 0 && r != sc.outer_region) continue;
+    const RegionRec& rr = regions[r];
+    if (rr.mult > 0.0f && ctx->mats[rr.material].ln[2][0] > -200.0f)
+      return set_err(ctx, GADEP_E_ARG, "cone source: the region around it has a coherent partial");
+  }
+  if (!(D > R)) return GADEP_OK;  // inside the sphere: the whole sphere
+  for (int a = 0; a < 3; ++a) sr.dir[a] = static_cast<float>((c[a] - src.pos_mm[a]) / D);
+  const double cc = sqrt(1.0 - (R / D) * (R / D));
+  sr.cone_cos = static_cast<float>(cc);
+  // the weight of the directions the kernel samples: those with cos >= the
+  // FP32 cosine it is given
+  weight = 0.5 * (1.0 - static_cast<double>(sr.cone_cos));
   return GADEP_OK;
 }
 
@@ -379,6 +418,8 @@ gadep_status plan_jobs(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
         P.lines.push_back(static_cast<float>(i == J.src.n_lines - 1 ? 2.0 : cum / tot));
       }
     }
+    double weight = 1.0;
+    if ((s = cone_setup(ctx, sc, J.src, P.regions.data() + roff, sr, weight))) return s;
     const int32_t src_idx = static_cast<int32_t>(P.sources.size());
     P.sources.push_back(sr);
     P.depth = std::max(P.depth, sc.depth);
@@ -403,6 +444,7 @@ gadep_status plan_jobs(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
         u.flags = kUnitExitEscapes | (sc.n_planes > 0 && ctx->exit_planes ? kUnitExitPlanes : 0);
       P.units.push_back(u);
       P.unit_energy.push_back(E);
+      P.unit_weight.push_back(weight);
       P.chunk_begin.push_back(chunks);
       chunks += (u.n + chunk - 1) / chunk;
       if (out) {
@@ -626,6 +668,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     if (out) {
       gadep_tally& t = out[u];
       to_tally(Tu, t);
+      t.weight = P.unit_weight[u];
       if (t.spectrum && spec_words)
         memcpy(t.spectrum, spec.data() + static_cast<int64_t>(u) * P.n_channels, P.n_channels * 8);
     }
@@ -912,6 +955,24 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
     sc.outer_lo[a] = pm.outer_lo[a];
     sc.outer_hi[a] = pm.outer_hi[a];
   }
+  if (n_planes > 0 && pm.trans_lo[0] <= pm.trans_hi[0]) {
+    for (int a = 0; a < 3; ++a) {
+      sc.inner_lo[a] = pm.trans_lo[a];
+      sc.inner_hi[a] = pm.trans_hi[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      sc.inner_lo[a] = INFINITY;
+      sc.inner_hi[a] = -INFINITY;
+    }
+    for (int64_t f = 0; f < 3 * nt; ++f) {
+      const float* v = xyz + 3 * static_cast<int64_t>(tri[f]);
+      for (int a = 0; a < 3; ++a) {
+        sc.inner_lo[a] = std::min<double>(sc.inner_lo[a], v[a]);
+        sc.inner_hi[a] = std::max<double>(sc.inner_hi[a], v[a]);
+      }
+    }
+  }
   sc.regions.assign(regions, regions + n_regions);
   sc.n_regions = n_regions;
   sc.depth = std::max(pm.depth, pm.trans_depth);
@@ -1065,6 +1126,8 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
   sr.region = src->region;
   sr.n_lines = src->n_lines;
   sr.line_off = 0;
+  double weight = 1.0;
+  if ((s = cone_setup(ctx, sc, *src, H.regions, sr, weight))) return s;
   if (src->n_lines > 0) {
     double tot = 0, cum = 0;
     for (int i = 0; i < src->n_lines; ++i) tot += src->line_prob[i];
@@ -1168,7 +1231,10 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
               "spectra D2H");
   HIP_TRY(hipStreamSynchronize(ctx->stream), "transport");
   note_clock(ctx, H.tally, n_energies);
-  for (int32_t u = 0; u < n_energies; ++u) to_tally(H.tally + static_cast<int64_t>(u) * kT_Slots, out[u]);
+  for (int32_t u = 0; u < n_energies; ++u) {
+    to_tally(H.tally + static_cast<int64_t>(u) * kT_Slots, out[u]);
+    out[u].weight = weight;
+  }
   return GADEP_OK;
 }
 

@@ -375,6 +375,13 @@ pool_kernel(TransportParams P) {
       dx = Src.dir[0];
       dy = Src.dir[1];
       dz = Src.dir[2];
+    } else if (Src.kind == kCone && Src.cone_cos > -1.0f) {
+      // uniform in the cone about the axis: cos theta uniform in [cone_cos, 1]
+      const float ct = fmaf(-rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), 1.0f - Src.cone_cos, 1.0f);
+      dx = Src.dir[0];
+      dy = Src.dir[1];
+      dz = Src.dir[2];
+      turn(dx, dy, dz, ct, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
     } else {
       const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
       const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
@@ -856,7 +863,11 @@ pool_kernel(TransportParams P) {
               u2 = u3;
             }
             float qx = Src.dir[0], qy = Src.dir[1], qz = Src.dir[2];
-            if (Src.kind != kBeam) {
+            if (Src.kind == kCone && Src.cone_cos > -1.0f) {
+              // the same draws as begin_flight's cone branch
+              turn(qx, qy, qz, fmaf(-u0, 1.0f - Src.cone_cos, 1.0f), u1);
+              u0 = u2;
+            } else if (Src.kind != kBeam) {
               const float ct = fmaf(2.0f, u0, -1.0f);
               const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
               qx = st * __builtin_amdgcn_cosf(u1);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libgadep.so")
 MAX_REGIONS = 64
 MAX_GROUPS = 8
 ACTIVE = 1
-SRC_POINT, SRC_BEAM, SRC_CYL = 0, 1, 2
+SRC_POINT, SRC_BEAM, SRC_CYL, SRC_CONE = 0, 1, 2, 3
 
 OPT_MAX_STEPS, OPT_BLOCK, OPT_PERIOD, OPT_CLAIM, OPT_VALIDATE, OPT_MIN_GAP_NM, OPT_GRAPHS, \
     OPT_COUNTERS, OPT_GRID, OPT_EXIT_PLANES, OPT_SPLIT_PCT, OPT_SCREEN, OPT_POOL = range(1, 14)
@@ -58,7 +58,7 @@ class Tally(C.Structure):
         ("edep_active_keV", C.c_double), ("edep_total_keV", C.c_double),
         ("e_escape_keV", C.c_double), ("e_source_keV", C.c_double),
         ("spectrum", C.POINTER(C.c_uint64)), ("n_channels", C.c_int32),
-        ("channel_keV", C.c_float), ("spectrum_overflow", C.c_uint64)]
+        ("channel_keV", C.c_float), ("spectrum_overflow", C.c_uint64), ("weight", C.c_double)]
 
 
 class Job(C.Structure):
@@ -222,13 +222,18 @@ class Result:
     grad_var: np.ndarray | None = None
     _keep: list = field(default_factory=list)
 
+    def weights(self):
+        """Photons each history stands for (1, or Omega/4pi for a cone source)."""
+        return np.array([t.weight for t in self.tallies])
+
     def fepe(self):
-        return np.array([t.n_fep / max(1, t.n_histories) for t in self.tallies])
+        return np.array([t.weight * t.n_fep / max(1, t.n_histories) for t in self.tallies])
 
     def fepe_sigma(self):
-        p = self.fepe()
+        w = self.weights()
+        q = np.array([t.n_fep / max(1, t.n_histories) for t in self.tallies])
         n = np.array([max(1, t.n_histories) for t in self.tallies], dtype=np.float64)
-        return np.sqrt(p * (1 - p) / n)
+        return w * np.sqrt(q * (1 - q) / n)
 
     def field(self, name):
         return np.array([getattr(t, name) for t in self.tallies])

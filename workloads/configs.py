@@ -25,7 +25,7 @@ EPS = 1.0e-3  # inside-out separation of otherwise coincident faces [mm]
 TABLE3_LINES_KEV = [59.54, 81.00, 121.78, 244.70, 344.28, 356.02, 411.13,
                     443.97, 778.90, 964.06, 1112.09, 1332.49, 1408.02]
 
-KIND_POINT, KIND_BEAM, KIND_CYL = 0, 1, 2
+KIND_POINT, KIND_BEAM, KIND_CYL, KIND_CONE = 0, 1, 2, 3
 
 
 def log_energies(n, e0=40.0, e1=2000.0):
