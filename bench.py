@@ -417,14 +417,32 @@ def _rates(ctx, gadep, run, k_ms):
 
 
 def bench_c3(a, torch, gadep, C):
+    """64 bottle jobs on the 256-facet crystal: one detector scene and 64
+    overlays (two-level geometry), batched in one launch against one launch
+    per job; autotuned block size, park threshold and claim."""
     jobs = C.c3_jobs(64)
     ws = [C.c3_job_workload(j) for j in jobs]
     ctx = gadep.Context(0)
-    for k, w in enumerate(ws):
-        gadep.load_workload(ctx, w, scene=k)
+    w0 = ws[0]
+    for m, tab in w0.tables.items():
+        ctx.set_xs(m, w0.grid, *tab)
+    base = C.bare_crystal(64).build()
+    mat, rho, grp, act = C.Workload("base", base, w0.materials, w0.tables, w0.grid, w0.source,
+                                    [], 0, 0).region_arrays()
+    torch.cuda.synchronize()
+    f0 = torch.cuda.mem_get_info()[0]
+    ctx.load_scene(0, base.xyz, base.tri, base.tri_region,
+                   [(int(mat[r]), float(rho[r]), int(grp[r]), gadep.ACTIVE if act[r] else 0)
+                    for r in range(len(mat))])
+    for k, j in enumerate(jobs):
+        ov = C.bottle_overlay(j["r"], j["h"], 2.0, j["matrix"], j["density"], group=1)
+        ctx.load_overlay(1 + k, 0, 0, ov.xyz, ov.tri, ov.tri_region, C.overlay_regions(ov, w0.materials))
+    torch.cuda.synchronize()
+    geometry_mb = (f0 - torch.cuda.mem_get_info()[0]) / 1e6
     spec = [dict(source=w.source, energies=w.energies, n_histories=max(1, j["n_total"] // len(w.energies)),
-                 scene=k, stream=k) for k, (j, w) in enumerate(zip(jobs, ws))]
+                 scene=1 + k, stream=k) for k, (j, w) in enumerate(zip(jobs, ws))]
     total = sum(s["n_histories"] * len(s["energies"]) for s in spec)
+    tuned = ctx.autotune(spec, 20_000_000)
     dt, k_ms = _timed(ctx, torch, lambda: ctx.run_batch(spec, 1003), a.steps, a.warmup)
     singles = 0.0
     for s1 in spec:
@@ -435,9 +453,11 @@ def bench_c3(a, torch, gadep, C):
         torch.cuda.synchronize()
         singles += time.perf_counter() - t0
     return _line("histories/s, 64 bottle jobs x 20 energies in one launch", total / dt, "histories/s",
-                 a, dt, "c3_64_bottle_jobs_on_256_facet_crystal_20_energies",
+                 a, dt, "c3_64_bottle_overlays_on_256_facet_crystal_20_energies",
                  {"histories_per_step": total, "kernel_ms": k_ms, "sum_of_single_job_launches_s": singles,
                   "batched_over_single_speedup": singles / dt,
+                  "autotuned_block_period_claim": list(tuned),
+                  "geometry_device_mb_detector_plus_64_overlays": geometry_mb,
                   "rates": _rates(ctx, gadep, lambda: ctx.run_batch(spec, 1003), k_ms)})
 
 

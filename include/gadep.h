@@ -135,6 +135,29 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz_mm
                               const int32_t* tri_region, int64_t n_tri,
                               const gadep_region* regions, int32_t n_regions);
 
+/* Two-level geometry for batches of calibration jobs (Sec. 1, Sec. 3.2: many
+ * sample containers and matrices in front of one detector): loads a per-job
+ * overlay -- closed shells such as a sample container and its matrix -- into
+ * scene slot `scene`, on top of the detector in slot `base_scene`.  The
+ * overlay's mesh (xyz, tri, tri_region as for gadep_load_mesh, facets tagged
+ * 1..n_regions-1) lies inside region `host_region` of the detector and
+ * crosses none of its shells; its regions[0] is ignored (it is the host
+ * region).  The combined scene numbers the detector's regions 0..nb-1 and
+ * overlay region k >= 1 as nb + k - 1 (job overrides, volume-source regions
+ * and tallies use these numbers), and its facets as the detector's followed
+ * by the overlay's.  The detector's BVHs and facet records are stored once
+ * for all its overlays; the overlay's are added to the same device arrays,
+ * and a photon in a region bounded by both meshes searches both BVHs and
+ * keeps the nearest hit.  Validation (GADEP_OPT_VALIDATE) checks the two
+ * meshes together: closed, oriented, apart, and each outermost overlay shell
+ * directly inside host_region (else GADEP_E_TOPOLOGY).  Reloading the
+ * detector's slot invalidates its overlays.  Errors: GADEP_E_ARG,
+ * GADEP_E_STATE (no detector in base_scene), _MESH_*, _TOPOLOGY, _HIP, _OOM. */
+gadep_status gadep_load_overlay(gadep_ctx* ctx, int32_t scene, int32_t base_scene,
+                                int32_t host_region, const float* xyz_mm, int64_t n_vertices,
+                                const int32_t* tri_vertices, const int32_t* tri_region,
+                                int64_t n_tri, const gadep_region* regions, int32_t n_regions);
+
 /* ----------------------------------------------------------------------------
  * cross sections (Sec. 2.4.1) */
 
@@ -279,7 +302,11 @@ gadep_status gadep_run_batch(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jo
  * Times short pilot launches of `jobs` (scaled down to about pilot_histories
  * in total) over block sizes, park thresholds (GADEP_OPT_PERIOD) and claim
  * sizes, keeps the fastest in the context and returns it (any output pointer
- * may be NULL).  Tallies never depend on these settings. */
+ * may be NULL).  The result is cached in the process, keyed by the GPU's
+ * architecture, the kernel (GADEP_OPT_POOL) and the class of the job mix
+ * (log2 of the largest scene's facet count, of the number of jobs and of
+ * units, the source kinds): a later call with the same key returns it
+ * without timing.  Tallies never depend on these settings. */
 gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs,
                             int64_t pilot_histories, int32_t* block, int32_t* period,
                             int32_t* claim);

@@ -262,10 +262,10 @@ __device__ __forceinline__ void load_tri(const TriRec* tris, int i, float4& a, f
 template <class LeafFn>
 __device__ __forceinline__ uint32_t traverse(const BvhNode* __restrict__ nodes, const Ray& r,
                                              float& tmax, int* stack, int stride, int cap,
-                                             LeafFn&& visit_leaf) {
+                                             LeafFn&& visit_leaf, int root = 0) {
   uint32_t visits = 0;
   int sp = 0;
-  int node = 0;
+  int node = root;
   for (;;) {
     while (node >= 0) {
       ++visits;

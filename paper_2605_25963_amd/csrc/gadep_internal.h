@@ -77,6 +77,11 @@ struct SceneRec {
   const int32_t* slots;   // facet of each leaf slot, for every BVH
   const float* planes;  // 4 floats per plane
   const int32_t* roots;  // root node of each region's transport BVH (kDone: none)
+  // Two-level scenes (a per-job overlay on a shared detector): a second BVH
+  // root per region, searched after the first with the nearest hit kept
+  // (null: none), and the root of the overlay's plain BVH (-1: none).
+  const int32_t* roots2;
+  int32_t root_all2;
   int32_t n_regions;
   int32_t depth;        // deepest of the BVHs
   int32_t n_planes;     // 0: no exit planes

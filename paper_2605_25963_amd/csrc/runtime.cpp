@@ -6,7 +6,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -64,13 +67,30 @@ struct Scene {
   void* d_planes = nullptr;
   void* d_roots = nullptr;
   void* d_slots = nullptr;
+  // A detector scene keeps its mesh on the host and the element counts of its
+  // device arrays, which the overlays loaded on it extend (its BVHs and facet
+  // records are stored once for all of them).
+  std::vector<float> h_xyz;
+  std::vector<int32_t> h_tri, h_reg, h_roots;
+  int64_t arena_nodes = 0, arena_slots = 0, arena_tris = 0;
+  // An overlay (a per-job mesh, e.g. a sample container, on a detector scene):
+  // the detector's slot, its own second root per combined region and the root
+  // of its plain BVH; its node, slot and facet records live in the detector's
+  // arrays.
+  int32_t base = -1;
+  void* d_roots2 = nullptr;
+  int32_t root_all2 = -1;
 };
 
-void fill_scene_rec(const Scene& sc, SceneRec& sr) {
-  sr.nodes = static_cast<const BvhNode*>(sc.d_nodes);
-  sr.tris = static_cast<const TriRec*>(sc.d_tris);
-  sr.slots = static_cast<const int32_t*>(sc.d_slots);
-  sr.planes = static_cast<const float*>(sc.d_planes);
+void fill_scene_rec(const std::vector<std::unique_ptr<Scene>>& scenes, const Scene& sc,
+                    SceneRec& sr) {
+  const Scene& arr = sc.base >= 0 ? *scenes[sc.base] : sc;
+  sr.nodes = static_cast<const BvhNode*>(arr.d_nodes);
+  sr.tris = static_cast<const TriRec*>(arr.d_tris);
+  sr.slots = static_cast<const int32_t*>(arr.d_slots);
+  sr.planes = static_cast<const float*>(arr.d_planes);
+  sr.roots2 = static_cast<const int32_t*>(sc.d_roots2);
+  sr.root_all2 = sc.root_all2;
   sr.n_regions = sc.n_regions;
   sr.depth = sc.depth;
   sr.roots = static_cast<const int32_t*>(sc.d_roots);
@@ -525,7 +545,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   std::vector<SceneRec> st(ctx->scenes.size());
   for (size_t i = 0; i < ctx->scenes.size(); ++i) {
     if (!ctx->scenes[i] || !ctx->scenes[i]->loaded) continue;
-    fill_scene_rec(*ctx->scenes[i], st[i]);
+    fill_scene_rec(ctx->scenes, *ctx->scenes[i], st[i]);
   }
   if ((s = upload(ctx, ctx->scene_tab, st.data(), st.size() * sizeof(SceneRec), "scene table"))) return s;
   if ((s = upload(ctx, ctx->units, P.units.data(), P.units.size() * sizeof(UnitRec), "unit table"))) return s;
@@ -788,6 +808,7 @@ void gadep_destroy(gadep_ctx* ctx) {
       if (sc->d_planes) (void)hipFree(sc->d_planes);
       if (sc->d_roots) (void)hipFree(sc->d_roots);
       if (sc->d_slots) (void)hipFree(sc->d_slots);
+      if (sc->d_roots2) (void)hipFree(sc->d_roots2);
     }
   for (DevBuf* b : {&ctx->xs, &ctx->units, &ctx->chunk_begin, &ctx->scene_tab, &ctx->sources,
                     &ctx->lines, &ctx->regions, &ctx->tally, &ctx->spectra, &ctx->cursor})
@@ -902,8 +923,14 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   if (sc.d_planes) (void)hipFree(sc.d_planes);
   if (sc.d_roots) (void)hipFree(sc.d_roots);
   if (sc.d_slots) (void)hipFree(sc.d_slots);
-  sc.d_nodes = sc.d_tris = sc.d_planes = sc.d_roots = sc.d_slots = nullptr;
+  if (sc.d_roots2) (void)hipFree(sc.d_roots2);
+  sc.d_nodes = sc.d_tris = sc.d_planes = sc.d_roots = sc.d_slots = sc.d_roots2 = nullptr;
   sc.loaded = false;
+  sc.base = -1;
+  sc.root_all2 = -1;
+  // overlays loaded on this slot referred to the arrays just freed
+  for (auto& o : ctx->scenes)
+    if (o && o->base == scene) o->loaded = false;
   // the transport BVHs follow the plain one, their indices shifted to match
   std::vector<BvhNode> nodes = pm.nodes;
   const int32_t n_plain = static_cast<int32_t>(pm.nodes.size());
@@ -979,7 +1006,204 @@ gadep_status gadep_load_scene(gadep_ctx* ctx, int32_t scene, const float* xyz, i
   sc.n_tri = nt;
   sc.n_nodes = static_cast<int64_t>(pm.nodes.size());
   sc.convex_exit = pm.convex_exit;
+  sc.h_xyz.assign(xyz, xyz + 3 * nv);
+  sc.h_tri.assign(tri, tri + 3 * nt);
+  sc.h_reg.assign(tri_region, tri_region + nt);
+  sc.h_roots = roots;
+  sc.arena_nodes = static_cast<int64_t>(nodes.size());
+  sc.arena_slots = static_cast<int64_t>(slots.size());
+  sc.arena_tris = nt;
   sc.loaded = true;
+  if (ctx->graph) {
+    (void)hipGraphExecDestroy(ctx->graph);
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+  }
+  return GADEP_OK;
+}
+
+gadep_status gadep_load_overlay(gadep_ctx* ctx, int32_t scene, int32_t base_scene,
+                                int32_t host_region, const float* xyz, int64_t nv,
+                                const int32_t* tri, const int32_t* tri_region, int64_t nt,
+                                const gadep_region* regions, int32_t n_regions) {
+  if (!ctx) return GADEP_E_ARG;
+  if (scene < 0 || scene >= GADEP_MAX_SCENES || base_scene < 0 || base_scene >= GADEP_MAX_SCENES ||
+      scene == base_scene)
+    return set_err(ctx, GADEP_E_ARG, "overlay: scene slots out of range or equal");
+  if (base_scene >= static_cast<int32_t>(ctx->scenes.size()) || !ctx->scenes[base_scene] ||
+      !ctx->scenes[base_scene]->loaded || ctx->scenes[base_scene]->base >= 0)
+    return set_err(ctx, GADEP_E_STATE, "overlay: the base scene is not a loaded detector scene");
+  if (!xyz || !tri || !tri_region || !regions || nv <= 0 || nt <= 0 || n_regions < 2)
+    return set_err(ctx, GADEP_E_ARG, "overlay: empty mesh or region table");
+  Scene& B = *ctx->scenes[base_scene];
+  const int32_t nb = B.n_regions;
+  const int32_t n_comb = nb + n_regions - 1;
+  if (host_region < 0 || host_region >= nb)
+    return set_err(ctx, GADEP_E_ARG, "overlay: host region out of range");
+  if (n_comb > kMaxRegions)
+    return set_err(ctx, GADEP_E_ARG, "overlay: more than 64 regions with the base scene's");
+  for (int32_t r = 1; r < n_regions; ++r) {
+    const gadep_region& R = regions[r];
+    if (R.material < 0 || !(R.density_g_cm3 >= 0) || !std::isfinite(R.density_g_cm3) ||
+        R.scale_group < -1 || R.scale_group >= GADEP_MAX_GROUPS)
+      return set_err(ctx, GADEP_E_ARG, "overlay region " + std::to_string(r) + ": bad material, density or group");
+  }
+  for (int64_t f = 0; f < nt; ++f)
+    if (tri_region[f] < 1 || tri_region[f] >= n_regions)
+      return set_err(ctx, GADEP_E_ARG, "overlay: facet region out of range (1..n_regions-1)");
+  // overlay region k >= 1 is region nb + k - 1 of the combined scene; its
+  // region 0 (outside every overlay shell) is the base's host region
+  auto comb = [&](int32_t k) { return k == 0 ? host_region : nb + k - 1; };
+  PreparedMesh po;
+  std::string err;
+  int rc = prepare_mesh(xyz, nv, tri, tri_region, nt, n_regions, ctx->min_gap_nm * 1e-6, false, 0,
+                        ctx->split_pct * 0.01, po, err);
+  if (rc != GADEP_OK) return set_err(ctx, static_cast<gadep_status>(rc), "overlay: " + err);
+  if (ctx->validate) {
+    // the detector and the overlay together: closed, oriented, apart from each
+    // other, and each outermost overlay shell directly inside the host region
+    const int64_t nvb = static_cast<int64_t>(B.h_xyz.size() / 3), ntb = B.n_tri;
+    std::vector<float> cx(B.h_xyz);
+    cx.insert(cx.end(), xyz, xyz + 3 * nv);
+    std::vector<int32_t> ct(B.h_tri), cr(B.h_reg);
+    for (int64_t i = 0; i < 3 * nt; ++i) ct.push_back(tri[i] + static_cast<int32_t>(nvb));
+    for (int64_t f = 0; f < nt; ++f) cr.push_back(comb(tri_region[f]));
+    PreparedMesh pc;
+    rc = prepare_mesh(cx.data(), nvb + nv, ct.data(), cr.data(), ntb + nt, n_comb,
+                      ctx->min_gap_nm * 1e-6, true, 0, 0.0, pc, err);
+    if (rc != GADEP_OK) return set_err(ctx, static_cast<gadep_status>(rc), "overlay on the detector: " + err);
+    for (int64_t f = 0; f < nt; ++f)
+      if (pc.outside[ntb + f] != comb(po.outside[f]))
+        return set_err(ctx, GADEP_E_TOPOLOGY, "overlay: its shells do not lie in region " +
+                                                  std::to_string(host_region) + " of the base scene");
+  }
+  // the overlay's records, placed after the detector's in its arrays
+  const int64_t NO = B.arena_nodes, SO = B.arena_slots, TO = B.arena_tris;
+  const int32_t n_plain = static_cast<int32_t>(po.nodes.size());
+  if (SO + nt + static_cast<int64_t>(po.trans_tris.size()) >= (int64_t(1) << 28) ||
+      NO + n_plain + static_cast<int64_t>(po.trans_nodes.size()) >= (int64_t(1) << 30))
+    return set_err(ctx, GADEP_E_ARG, "overlay: the detector's arrays are full");
+  std::vector<BvhNode> nodes;
+  nodes.reserve(po.nodes.size() + po.trans_nodes.size());
+  for (BvhNode nd : po.nodes) {
+    for (int c = 0; c < 2; ++c) {
+      if (nd.child[c] >= 0) {
+        nd.child[c] += static_cast<int32_t>(NO);
+      } else {
+        const int32_t x = ~nd.child[c];
+        nd.child[c] = leaf_code((x >> 3) + SO, x & 7);
+      }
+    }
+    nodes.push_back(nd);
+  }
+  for (BvhNode nd : po.trans_nodes) {
+    for (int c = 0; c < 2; ++c) {
+      if (nd.child[c] >= 0) {
+        nd.child[c] += static_cast<int32_t>(NO) + n_plain;
+      } else {
+        const int32_t x = ~nd.child[c];
+        nd.child[c] = leaf_code((x >> 3) + SO + nt, x & 7);
+      }
+    }
+    nodes.push_back(nd);
+  }
+  std::vector<TriRec> tris(static_cast<size_t>(nt));
+  for (TriRec r : po.tris) {
+    const int32_t in = static_cast<int32_t>(r.regions & 0xFFFFu), out = static_cast<int32_t>(r.regions >> 16);
+    r.regions = static_cast<uint32_t>(comb(in)) | (static_cast<uint32_t>(comb(out)) << 16);
+    const int32_t f = r.orig;
+    r.orig = static_cast<int32_t>(B.n_tri) + f;  // the facet's number in the combined scene
+    tris[f] = r;
+  }
+  std::vector<int32_t> slots;
+  slots.reserve(nt + po.trans_tris.size());
+  for (int32_t f : po.order) slots.push_back(static_cast<int32_t>(TO) + f);
+  for (const TriRec& r : po.trans_tris) slots.push_back(static_cast<int32_t>(TO) + r.orig);
+  std::vector<int32_t> roots(B.h_roots), roots2(static_cast<size_t>(n_comb), kDone);
+  for (int32_t k = 1; k < n_regions; ++k)
+    roots.push_back(po.trans_root[k] >= 0 ? po.trans_root[k] + static_cast<int32_t>(NO) + n_plain : kDone);
+  if (po.trans_root[0] >= 0) roots2[host_region] = po.trans_root[0] + static_cast<int32_t>(NO) + n_plain;
+
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "sync");
+  // grow the detector's arrays by the overlay's records
+  auto grow = [&](void*& d, int64_t old_count, size_t elem, const void* add, int64_t add_count,
+                  const char* what) -> gadep_status {
+    void* n = nullptr;
+    HIP_TRY(hipMalloc(&n, (old_count + add_count) * elem), what);
+    if (old_count) {
+      hipError_t e = hipMemcpy(n, d, old_count * elem, hipMemcpyDeviceToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(n);
+        return hip_err(ctx, e, what);
+      }
+    }
+    hipError_t e = hipMemcpy(static_cast<char*>(n) + old_count * elem, add, add_count * elem,
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(n);
+      return hip_err(ctx, e, what);
+    }
+    (void)hipFree(d);
+    d = n;
+    return GADEP_OK;
+  };
+  gadep_status st;
+  if ((st = grow(B.d_nodes, NO, sizeof(BvhNode), nodes.data(), static_cast<int64_t>(nodes.size()), "overlay nodes")))
+    return st;
+  B.arena_nodes = NO + static_cast<int64_t>(nodes.size());
+  if ((st = grow(B.d_tris, TO, sizeof(TriRec), tris.data(), nt, "overlay facets"))) return st;
+  B.arena_tris = TO + nt;
+  if ((st = grow(B.d_slots, SO, sizeof(int32_t), slots.data(), static_cast<int64_t>(slots.size()), "overlay slots")))
+    return st;
+  B.arena_slots = SO + static_cast<int64_t>(slots.size());
+
+  if (static_cast<int32_t>(ctx->scenes.size()) <= scene) ctx->scenes.resize(scene + 1);
+  if (!ctx->scenes[scene]) ctx->scenes[scene].reset(new Scene());
+  Scene& O = *ctx->scenes[scene];
+  if (O.d_nodes) (void)hipFree(O.d_nodes);
+  if (O.d_tris) (void)hipFree(O.d_tris);
+  if (O.d_planes) (void)hipFree(O.d_planes);
+  if (O.d_slots) (void)hipFree(O.d_slots);
+  if (O.d_roots) (void)hipFree(O.d_roots);
+  if (O.d_roots2) (void)hipFree(O.d_roots2);
+  O = Scene();
+  for (auto& o : ctx->scenes)
+    if (o && o->base == scene) o->loaded = false;
+  HIP_TRY(hipMalloc(&O.d_roots, roots.size() * sizeof(int32_t)), "overlay roots");
+  HIP_TRY(hipMemcpy(O.d_roots, roots.data(), roots.size() * sizeof(int32_t), hipMemcpyHostToDevice), "overlay roots");
+  HIP_TRY(hipMalloc(&O.d_roots2, roots2.size() * sizeof(int32_t)), "overlay roots");
+  HIP_TRY(hipMemcpy(O.d_roots2, roots2.data(), roots2.size() * sizeof(int32_t), hipMemcpyHostToDevice), "overlay roots");
+  O.base = base_scene;
+  O.root_all2 = static_cast<int32_t>(NO);
+  O.regions = B.regions;
+  for (int32_t k = 1; k < n_regions; ++k) O.regions.push_back(regions[k]);
+  O.n_regions = n_comb;
+  O.depth = std::max(B.depth, std::max(po.depth, po.trans_depth));
+  O.n_tri = B.n_tri + nt;
+  O.n_nodes = static_cast<int64_t>(nodes.size());
+  // an overlay in the world takes the world's single convex neighbour away
+  const bool keep_exit = host_region != 0;
+  O.convex_exit = keep_exit && B.convex_exit;
+  O.n_planes = keep_exit ? B.n_planes : 0;
+  O.outer_root = keep_exit ? B.outer_root : kDone;
+  O.outer_region = B.outer_region;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < 3 * nt; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min<double>(lo[a], xyz[3 * static_cast<int64_t>(tri[i]) + a]);
+      hi[a] = std::max<double>(hi[a], xyz[3 * static_cast<int64_t>(tri[i]) + a]);
+    }
+  for (int a = 0; a < 3; ++a) {
+    O.outer_lo[a] = B.outer_lo[a];
+    O.outer_hi[a] = B.outer_hi[a];
+    const bool tb = B.trans_lo[0] <= B.trans_hi[0];
+    O.trans_lo[a] = tb ? std::min<float>(B.trans_lo[a], static_cast<float>(lo[a])) : static_cast<float>(lo[a]);
+    O.trans_hi[a] = tb ? std::max<float>(B.trans_hi[a], static_cast<float>(hi[a])) : static_cast<float>(hi[a]);
+    O.inner_lo[a] = std::min(B.inner_lo[a], lo[a]);
+    O.inner_hi[a] = std::max(B.inner_hi[a], hi[a]);
+  }
+  O.loaded = true;
   if (ctx->graph) {
     (void)hipGraphExecDestroy(ctx->graph);
     ctx->graph = nullptr;
@@ -1162,7 +1386,7 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
     chunks += (n + chunk - 1) / chunk;
   }
   H.chunk_begin[n_energies] = chunks;
-  fill_scene_rec(sc, H.scene);
+  fill_scene_rec(ctx->scenes, sc, H.scene);
 
   HIP_TRY(hipSetDevice(ctx->device), "set device");
   char* base = static_cast<char*>(ctx->scratch);
@@ -1266,11 +1490,70 @@ gadep_status gadep_run_batch(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jo
   return execute(ctx, P, seed, out, grads, grads_var, GADEP_MAX_GROUPS);
 }
 
+// Settings the autotuner found, per (GPU architecture, kernel, class of the
+// job mix): a later call with the same key takes them without timing again.
+// The class is what the timing depends on: mesh size (log2 of the largest
+// scene's facets), number of jobs and units (log2), source kinds, gradients.
+struct TuneKey {
+  std::string arch;
+  int64_t pool, mesh_class, jobs_class, units_class, kinds, grad;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, pool, mesh_class, jobs_class, units_class, kinds, grad) <
+           std::tie(o.arch, o.pool, o.mesh_class, o.jobs_class, o.units_class, o.kinds, o.grad);
+  }
+};
+struct TuneVal {
+  int64_t block, period, claim;
+};
+std::mutex g_tune_mutex;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
+int64_t log2_class(int64_t x) {
+  int64_t c = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++c;
+  }
+  return c;
+}
+
 gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_jobs, int64_t pilot,
                             int32_t* block_out, int32_t* period_out, int32_t* claim_out) {
   if (!ctx) return GADEP_E_ARG;
   if (pilot < 1) return set_err(ctx, GADEP_E_ARG, "pilot_histories must be >= 1");
+  if (!jobs || n_jobs <= 0) return set_err(ctx, GADEP_E_ARG, "no jobs");
   HIP_TRY(hipSetDevice(ctx->device), "set device");
+  TuneKey key;
+  {
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "device properties");
+    key.arch = prop.gcnArchName;
+    int64_t facets = 0, units = 0, kinds = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+      const int32_t sc = jobs[j].scene;
+      if (sc >= 0 && sc < static_cast<int32_t>(ctx->scenes.size()) && ctx->scenes[sc])
+        facets = std::max(facets, ctx->scenes[sc]->n_tri);
+      units += std::max(1, jobs[j].n_energies);
+      kinds |= int64_t(1) << std::min(7, std::max(0, jobs[j].src.kind));
+    }
+    key.pool = ctx->pool;
+    key.mesh_class = log2_class(facets);
+    key.jobs_class = log2_class(n_jobs);
+    key.units_class = log2_class(units);
+    key.kinds = kinds;
+    key.grad = 0;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      if (!ctx->pool) ctx->block = it->second.block;
+      ctx->period = it->second.period;
+      ctx->claim = it->second.claim;
+      if (block_out) *block_out = static_cast<int32_t>(ctx->pool ? 64 : it->second.block);
+      if (period_out) *period_out = static_cast<int32_t>(it->second.period);
+      if (claim_out) *claim_out = static_cast<int32_t>(it->second.claim);
+      return GADEP_OK;
+    }
+  }
   std::vector<gadep_job> pj(jobs, jobs + std::max(0, n_jobs));
   int64_t total = 0;
   for (auto& j : pj) total += j.n_histories * std::max(1, j.n_energies);
@@ -1329,6 +1612,10 @@ gadep_status gadep_autotune(gadep_ctx* ctx, const gadep_job* jobs, int32_t n_job
   ctx->claim = best_claim;
   ctx->period = best_period;
   ctx->graphs = saved_graphs;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[key] = TuneVal{best_block, best_period, best_claim};
+  }
   if (block_out) *block_out = static_cast<int32_t>(best_block);
   if (period_out) *period_out = static_cast<int32_t>(ctx->period);
   if (claim_out) *claim_out = static_cast<int32_t>(best_claim);
@@ -1372,7 +1659,7 @@ static gadep_status scene_rec(gadep_ctx* ctx, int32_t scene, SceneRec& sr) {
   if (scene < 0 || scene >= static_cast<int32_t>(ctx->scenes.size()) || !ctx->scenes[scene] ||
       !ctx->scenes[scene]->loaded)
     return set_err(ctx, GADEP_E_STATE, "scene not loaded");
-  fill_scene_rec(*ctx->scenes[scene], sr);
+  fill_scene_rec(ctx->scenes, *ctx->scenes[scene], sr);
   return GADEP_OK;
 }
 

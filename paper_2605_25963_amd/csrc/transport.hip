@@ -42,7 +42,7 @@ __device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, fl
                                             float oz, float dx, float dy, float dz, float tmax,
                                             int exclude, int cur, int* stack, int stride,
                                             HitOut& h, bool& glitch, uint32_t& nvis,
-                                            uint32_t& ntri) {
+                                            uint32_t& ntri, int root = 0) {
   float best = tmax;
   int best_slot = -1;
   int best_reg = 0;
@@ -73,7 +73,7 @@ __device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, fl
       best_reg = enter ? inside : outside;
     }
     return tcur;
-  });
+  }, root);
   if (COUNT) nvis += v;
   glitch = rejected < best;
   if (best_slot < 0) return false;
@@ -99,7 +99,7 @@ __constant__ float kProbe[4][3] = {
 
 template <bool COUNT>
 __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, int* stack,
-                             int stride, uint32_t& nvis, uint32_t& ntri) {
+                             int stride, uint32_t& nvis, uint32_t& ntri, int root = 0) {
   const TriRec* __restrict__ tris = sc.tris;
   for (int k = 0; k < 4; ++k) {
     const float qx = kProbe[k][0], qy = kProbe[k][1], qz = kProbe[k][2];
@@ -121,7 +121,7 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
         parity ^= 1ull << (__float_as_uint(c.y) & 63u);
       }
       return tcur;
-    });
+    }, root);
     if (COUNT) nvis += v;
     if (degenerate) continue;
     if (parity == 0) return 0;
@@ -145,11 +145,25 @@ __device__ int locate_parity(const SceneRec& sc, float px, float py, float pz, i
         tcur = t;
       }
       return tcur;
-    });
+    }, root);
     if (COUNT) nvis += v;
     return best_reg;
   }
   return -1;
+}
+
+// Region of a point in a scene that may have two levels: inside an overlay
+// shell (by the overlay's own parity), else by the base scene's parity.  The
+// overlay's shells lie in one region of the base and cross none of its
+// shells, so the two counts never mix.
+template <bool COUNT>
+__device__ int locate_two_level(const SceneRec& sc, float px, float py, float pz, int* stack,
+                                int stride, uint32_t& nvis, uint32_t& ntri) {
+  if (sc.root_all2 >= 0) {
+    const int r = locate_parity<COUNT>(sc, px, py, pz, stack, stride, nvis, ntri, sc.root_all2);
+    if (r != 0) return r;
+  }
+  return locate_parity<COUNT>(sc, px, py, pz, stack, stride, nvis, ntri, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,6 +281,8 @@ transport_kernel(TransportParams P) {
   int node = kDone, sp = 0, tri_next = 0, tri_end = 0, best_id = -1, best_reg = 0;
   // a leaf met while facets of an earlier one were still pending (kDone: none)
   int leaf2 = kDone;
+  // a second BVH root still to search (two-level scenes; kDone: none)
+  int node2 = kDone;
   // per-lane accumulators of the per-history (frequent) quantities
   unsigned long long acc_hist = 0, acc_eunc = 0, acc_esrc = 0;
   uint32_t ev[kEv_N];
@@ -876,6 +892,11 @@ transport_kernel(TransportParams P) {
         tbest = INFINITY;
         trej = INFINITY;
         node = gload(S.roots, Src.region);
+        node2 = S.roots2 ? gload(S.roots2, Src.region) : kDone;
+        if (node == kDone) {
+          node = node2;
+          node2 = kDone;
+        }
         sp = 0;
         tri_next = tri_end = 0;
         leaf2 = kDone;
@@ -915,12 +936,18 @@ transport_kernel(TransportParams P) {
             best_reg = 0;
           }
           node = S.outer_root;
+          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
           if (!(S.trans_lo[0] <= S.trans_hi[0]) ||
               slab(ray, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0], S.trans_hi[1],
                    S.trans_hi[2], tbest) == INFINITY)
-            node = kDone;  // no inner shell ahead within the flight
+            node = node2 = kDone;  // no inner shell ahead within the flight
         } else {
           node = gload(S.roots, region);
+          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
+        }
+        if (node == kDone) {
+          node = node2;
+          node2 = kDone;
         }
         phase = node == kDone ? kParked : kTrav;
       }
@@ -1023,7 +1050,15 @@ transport_kernel(TransportParams P) {
           }
         }
       }
-      if (tri_next >= tri_end && node == kDone && leaf2 == kDone) phase = kParked;
+      if (tri_next >= tri_end && node == kDone && leaf2 == kDone) {
+        if (node2 != kDone) {
+          // the second level: same ray, nearest hit so far kept
+          node = node2;
+          node2 = kDone;
+        } else {
+          phase = kParked;
+        }
+      }
     }
     if (COUNT) {
       const bool any_node = __ballot(did_node) != 0, any_tri = __ballot(did_tri) != 0;
@@ -1065,8 +1100,8 @@ __global__ void locate_units_kernel(UnitRec* units, int n_units, const SceneRec*
   if (s.kind == kCyl) {
     U.src_region = s.region;
   } else {
-    U.src_region = locate_parity<false>(scenes[U.scene], s.pos[0], s.pos[1], s.pos[2],
-                                        lstack + threadIdx.x, blockDim.x, a, b);
+    U.src_region = locate_two_level<false>(scenes[U.scene], s.pos[0], s.pos[1], s.pos[2],
+                                           lstack + threadIdx.x, blockDim.x, a, b);
   }
   (void)stack_depth;
 }
@@ -1096,10 +1131,22 @@ __global__ void raycast_kernel(SceneRec sc, const float* o, const float* d, cons
   bool glitch;
   uint32_t a = 0, b = 0;
   const int cur = region ? region[i] : -1;
-  if (closest_hit<false>(sc, r, ox, oy, oz, dx, dy, dz, INFINITY, -1, cur, lstack + threadIdx.x,
-                         blockDim.x, h, glitch, a, b)) {
+  bool hit = closest_hit<false>(sc, r, ox, oy, oz, dx, dy, dz, INFINITY, -1, cur,
+                                lstack + threadIdx.x, blockDim.x, h, glitch, a, b);
+  if (sc.root_all2 >= 0) {
+    HitOut h2;
+    if (closest_hit<false>(sc, r, ox, oy, oz, dx, dy, dz, hit ? h.t : INFINITY, -1, cur,
+                           lstack + threadIdx.x, blockDim.x, h2, glitch, a, b, sc.root_all2)) {
+      h = h2;
+      hit = true;
+    }
+  }
+  if (hit) {
     t[i] = h.t;
-    tri[i] = gload(sc.slots, h.slot);
+    // the facet's number in the (combined) scene, from its record
+    float4 fa, fb, fc;
+    load_tri(sc.tris, gload(sc.slots, h.slot), fa, fb, fc);
+    tri[i] = __float_as_int(fc.z);
     region_after[i] = h.region_after;
   } else {
     t[i] = INFINITY;
@@ -1113,8 +1160,8 @@ __global__ void locate_kernel(SceneRec sc, const float* p, int64_t n, int32_t* r
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   uint32_t a = 0, b = 0;
-  region[i] = locate_parity<false>(sc, p[3 * i], p[3 * i + 1], p[3 * i + 2], lstack + threadIdx.x,
-                                   blockDim.x, a, b);
+  region[i] = locate_two_level<false>(sc, p[3 * i], p[3 * i + 1], p[3 * i + 2],
+                                      lstack + threadIdx.x, blockDim.x, a, b);
 }
 
 // Gaussian broadening: one thread per output channel gathers from the input

@@ -39,7 +39,7 @@ enum PoolField : int {
   kF_Px = 0, kF_Py, kF_Pz, kF_Dx, kF_Dy, kF_Dz, kF_E, kF_Tau, kF_EdAct, kF_EdTot,
   kF_Mu, kF_Mp, kF_Mc, kF_Tbest, kF_Trej, kF_BestId, kF_BestReg, kF_Misc, kF_Last, kF_Steps,
   kF_HLo, kF_HHi, kF_Draw, kF_Left, kF_B0, kF_B1, kF_B2, kF_Node, kF_Sp, kF_Tri, kF_Leaf2,
-  kF_Att, kF_N
+  kF_Node2, kF_Att, kF_N
 };
 // kF_Misc: region + 1 (bits 0-7), clean, interacted, touched, esc_any (bits 8-11)
 
@@ -140,6 +140,8 @@ pool_kernel(TransportParams P) {
   float tbest = 0, trej = INFINITY;
   int node = kDone, sp = 0, tri_next = 0, tri_end = 0, best_id = -1, best_reg = 0;
   int leaf2 = kDone;
+  // a second BVH root still to search (two-level scenes; kDone: none)
+  int node2 = kDone;
   int tslot = -1;  // slot whose ray this lane traverses
   int pslot = -1;  // slot whose ray this lane paused for a housekeeping round
   unsigned long long acc_hist = 0, acc_eunc = 0, acc_esrc = 0;
@@ -171,6 +173,7 @@ pool_kernel(TransportParams P) {
     tri_next = static_cast<int>(t >> 3);
     tri_end = tri_next + static_cast<int>(t & 7u);
     leaf2 = static_cast<int>(fld(kF_Leaf2, s));
+    node2 = static_cast<int>(fld(kF_Node2, s));
     ray = make_ray(px, py, pz, dx, dy, dz);
   };
   // a finished or paused traversal's state into slot s
@@ -184,6 +187,7 @@ pool_kernel(TransportParams P) {
       fld(kF_Sp, s) = static_cast<uint32_t>(sp);
       fld(kF_Tri, s) = (static_cast<uint32_t>(tri_next) << 3) | static_cast<uint32_t>(tri_end - tri_next);
       fld(kF_Leaf2, s) = static_cast<uint32_t>(leaf2);
+      fld(kF_Node2, s) = static_cast<uint32_t>(node2);
     }
   };
   // the whole photon of slot s into this lane's registers, and back
@@ -258,6 +262,7 @@ pool_kernel(TransportParams P) {
     fld(kF_Sp, s) = 0u;
     fld(kF_Tri, s) = 0u;
     fld(kF_Leaf2, s) = static_cast<uint32_t>(kDone);
+    fld(kF_Node2, s) = static_cast<uint32_t>(node2);
   };
   // append the slots of the lanes with `pred` to a ring
   auto push = [&](uint8_t* ring, int head, int& n, bool pred, int s) {
@@ -514,6 +519,11 @@ pool_kernel(TransportParams P) {
             }
           }
         }
+      }
+      // the second level of a two-level scene: same ray, nearest hit kept
+      if (tslot >= 0 && tri_next >= tri_end && node == kDone && leaf2 == kDone && node2 != kDone) {
+        node = node2;
+        node2 = kDone;
       }
       // finished rays: their results to the slot, the slot to the done ring
       const bool fin = tslot >= 0 && tri_next >= tri_end && node == kDone && leaf2 == kDone;
@@ -1023,6 +1033,11 @@ pool_kernel(TransportParams P) {
         tbest = INFINITY;
         trej = INFINITY;
         node = gload(S.roots, Src.region);
+        node2 = S.roots2 ? gload(S.roots2, Src.region) : kDone;
+        if (node == kDone) {
+          node = node2;
+          node2 = kDone;
+        }
         sp = 0;
         tri_next = tri_end = 0;
         leaf2 = kDone;
@@ -1062,12 +1077,18 @@ pool_kernel(TransportParams P) {
             best_reg = 0;
           }
           node = S.outer_root;
+          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
           if (!(S.trans_lo[0] <= S.trans_hi[0]) ||
               slab(ray, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0], S.trans_hi[1],
                    S.trans_hi[2], tbest) == INFINITY)
-            node = kDone;  // no inner shell ahead within the flight
+            node = node2 = kDone;  // no inner shell ahead within the flight
         } else {
           node = gload(S.roots, region);
+          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
+        }
+        if (node == kDone) {
+          node = node2;
+          node2 = kDone;
         }
         phase = node == kDone ? kParked : kTrav;
       }

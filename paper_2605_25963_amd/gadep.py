@@ -105,7 +105,7 @@ EXPORTS = [
     "gadep_run_grad", "gadep_run_batch", "gadep_autotune", "gadep_get_counters",
     "gadep_broaden_dev", "gadep_raycast", "gadep_locate", "gadep_mesh_prepare",
     "gadep_get_last_launch_ms", "gadep_detmesh", "gadep_write_vrml", "gadep_philox",
-    "gadep_run_noalloc", "gadep_get_last_clock_mhz",
+    "gadep_run_noalloc", "gadep_get_last_clock_mhz", "gadep_load_overlay",
 ]
 
 _lib = None
@@ -141,6 +141,8 @@ def lib():
         "gadep_get_option": (i32, [p, i32, C.POINTER(i64)]),
         "gadep_load_mesh": (i32, [p, f32p, i64, i32p, i32p, i64, C.POINTER(Region), i32]),
         "gadep_load_scene": (i32, [p, i32, f32p, i64, i32p, i32p, i64, C.POINTER(Region), i32]),
+        "gadep_load_overlay": (i32, [p, i32, i32, i32, f32p, i64, i32p, i32p, i64,
+                                     C.POINTER(Region), i32]),
         "gadep_set_xs": (i32, [p, i32, C.c_double, C.c_double, i32, f32p, f32p, f32p, f32p]),
         "gadep_set_scales": (i32, [p, f32p, i32]),
         "gadep_run": (i32, [p, C.POINTER(Source), dp, i32, i64, u64, i64, C.POINTER(Tally)]),
@@ -295,6 +297,19 @@ class Context:
                                            _ptr(tri, C.c_int32), _ptr(reg, C.c_int32), len(tri),
                                            rs, len(regions)))
         self._scene_regions[int(scene)] = len(regions)
+
+    def load_overlay(self, scene, base_scene, host_region, xyz, tri, tri_region, regions):
+        """gadep_load_overlay: per-job shells on the detector in base_scene; regions[0]
+        (the host) is ignored, overlay region k is region n_base + k - 1 of the scene."""
+        xyz, tri, reg = _f32(xyz, (-1, 3)), _i32(tri).reshape(-1, 3), _i32(tri_region)
+        rs = (Region * len(regions))()
+        for i, r in enumerate(regions):
+            rs[i].material, rs[i].density_g_cm3, rs[i].scale_group, rs[i].flags = \
+                int(r[0]), float(r[1]), int(r[2]), int(r[3])
+        self._check(lib().gadep_load_overlay(self.h, int(scene), int(base_scene), int(host_region),
+                                             _ptr(xyz, C.c_float), len(xyz), _ptr(tri, C.c_int32),
+                                             _ptr(reg, C.c_int32), len(tri), rs, len(regions)))
+        self._scene_regions[int(scene)] = self._scene_regions.get(int(base_scene), 0) + len(regions) - 1
 
     def load_mesh(self, xyz, tri, tri_region, regions):
         self.load_scene(0, xyz, tri, tri_region, regions)
@@ -558,6 +573,7 @@ gadep_set_option = Context.set_option
 gadep_get_option = Context.get_option
 gadep_load_mesh = Context.load_mesh
 gadep_load_scene = Context.load_scene
+gadep_load_overlay = Context.load_overlay
 gadep_set_xs = Context.set_xs
 gadep_set_scales = Context.set_scales
 gadep_run = Context.run

@@ -243,6 +243,11 @@ def test_autotune_and_graph_replay_keep_tallies(G, ctx):
     block, period, claim = ctx.autotune(job, 400_000)
     assert block in (128, 256) and period in (16, 24, 32) and claim in (16, 64)
     assert ctx.get_option(G.OPT_BLOCK) == block
+    # the same job mix again: taken from the cache, no timing
+    import time
+    t0 = time.perf_counter()
+    assert ctx.autotune(job, 400_000) == (block, period, claim)
+    assert time.perf_counter() - t0 < 0.05
     tuned = ctx.run_batch(job, 71)
     replays = [ctx.run_batch(job, 71) for _ in range(3)]
     ctx.set_option(G.OPT_GRAPHS, 0)

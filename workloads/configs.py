@@ -126,6 +126,21 @@ def add_bottle(b, r, h, z_base, matrix, density, n_seg=64, wall=1.5, group=-1):
                  mg.cylinder(r, z_base + wall, z_base + wall + h, n_seg), group=group)
 
 
+def bottle_overlay(r, h, z_base, matrix, density, n_seg=64, wall=1.5, group=-1):
+    """A PP bottle and its matrix alone, as an overlay mesh (regions: the host,
+    container, matrix) for a detector scene; the same shells add_bottle puts
+    into a full scene."""
+    b = mg.SceneBuilder("vacuum", 0.0)
+    add_bottle(b, r, h, z_base, matrix, density, n_seg=n_seg, wall=wall, group=group)
+    return b.build()
+
+
+def overlay_regions(scene, materials):
+    """Region tuples (material id, density, group, ACTIVE flag) of an overlay scene."""
+    return [(materials.index(r["material"]), float(r["density"]), int(r["group"]),
+             1 if r["active"] else 0) for r in scene.regions]
+
+
 # ----------------------------------------------------------------------------
 # the five calibration workloads
 
