@@ -32,7 +32,7 @@ class Tally(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "n_histories", "n_absorbed", "n_fep", "n_uncollided", "n_escape", "n_lost", "n_killed",
         "n_source_fail", "n_balance_fail", "n_segments", "n_crossings", "n_photo", "n_compton",
-        "n_coherent", "n_pair", "spectrum_overflow")] + [
+        "n_coherent", "n_pair", "n_electrons", "spectrum_overflow")] + [
         ("edep_active", C.c_double), ("edep_total", C.c_double), ("e_escape", C.c_double),
         ("sum_score", C.c_double * MAX_GROUPS), ("sum_fep_score", C.c_double * MAX_GROUPS),
         ("sum_fep_score2", C.c_double * MAX_GROUPS)]
@@ -80,6 +80,11 @@ def lib():
                               C.POINTER(C.c_uint64), C.c_int32, C.c_int32, C.POINTER(Tally)]
         L.orc_broaden.argtypes = [dp, C.c_int32, C.c_double, C.c_double, C.c_double, dp]
         L.orc_rotate.argtypes = [dp, C.c_double, C.c_double, dp]
+        L.orc_set_electrons.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_csda_range.restype = C.c_double
+        L.orc_csda_range.argtypes = [C.c_double]
+        L.orc_csda_energy.restype = C.c_double
+        L.orc_csda_energy.argtypes = [C.c_double]
         L.orc_emission.restype = C.c_int32
         L.orc_emission.argtypes = [C.c_void_p, C.POINTER(Source), C.c_uint64, C.c_uint32, C.c_int64,
                                    dp, dp, C.POINTER(C.c_int32)]
@@ -193,6 +198,10 @@ class Scene:
     def locate(self, p):
         p = np.ascontiguousarray(p, dtype=np.float64)
         return lib().orc_locate(self.h, _dp(p))
+
+    def set_electrons(self, on):
+        """Secondary electrons as straight CSDA tracks (1) or local deposits (0)."""
+        lib().orc_set_electrons(self.h, 1 if on else 0)
 
     def closest_hit(self, o, d, exclude=-1):
         o = np.ascontiguousarray(o, dtype=np.float64)

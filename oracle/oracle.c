@@ -120,6 +120,7 @@ struct orc_scene {
   int grid_set;
   double lnE0, dlnE;
   int32_t nE;
+  int electrons; /* 1: secondary electrons run straight CSDA tracks (see electron_track) */
 };
 
 static const double* V(const orc_scene* s, int64_t t) { return s->v + 9 * t; }
@@ -573,6 +574,113 @@ void orc_rotate(const double d[3], double ct, double phi, double out[3]) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* secondary electrons (a synthetic reading of the electron transport the
+ * paper couples to its photons, Sec. 2.4.1): each electron set in motion by
+ * a photoelectric absorption, a Compton scattering or a pair production runs
+ * a straight track in the continuous-slowing-down approximation, with the
+ * mass range of Katz and Penfold (1952), and leaves in every region it
+ * crosses the energy it loses there.  Electrons below ELEC_TMIN deposit at
+ * once.  Ranges use the regions' nominal densities (not the density scales),
+ * so the score-function derivative keeps its form. */
+
+#define ELEC_TMIN 10.0 /* keV: the lower end of the range relation's validity */
+
+/* Katz-Penfold mass range [g/cm^2] of an electron of kinetic energy T [keV] */
+static double csda_range(double T) {
+  const double t = T * 1e-3;
+  if (t > 2.5) return 0.530 * t - 0.106;
+  if (!(t > 0.0)) return 0.0;
+  return 0.412 * pow(t, 1.265 - 0.0954 * log(t));
+}
+
+double orc_csda_range(double T_keV) { return csda_range(T_keV); }
+
+/* kinetic energy [keV] whose range is R [g/cm^2]: bisection (the range grows
+ * monotonically with the energy) */
+static double csda_energy(double R) {
+  if (!(R > 0.0)) return 0.0;
+  double lo = 0.0, hi = 4000.0;
+  for (int i = 0; i < 100; ++i) {
+    const double m = 0.5 * (lo + hi);
+    if (csda_range(m) < R)
+      lo = m;
+    else
+      hi = m;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double orc_csda_energy(double R) { return csda_energy(R); }
+
+typedef struct {
+  double act, tot, esc; /* energy left in ACTIVE regions, in all regions, carried out */
+  int lost;
+} etrack;
+
+/* An electron of kinetic energy T from p along the unit direction e, in
+ * `region`: straight, region by region (the region past each crossing by the
+ * parity rule, as for photons); in a region of density rho it can run
+ * 10 R / rho mm on its remaining range R; it stops where that range is spent,
+ * or leaves the world through void. */
+static etrack electron_track(const orc_scene* s, const double* p0, const double* e, double T,
+                             int32_t region) {
+  etrack out = {0.0, 0.0, 0.0, 0};
+  double p[3] = {p0[0], p0[1], p0[2]};
+  double R = csda_range(T), Tcur = T;
+  int64_t last = -1;
+  for (int steps = 0; steps < 100000; ++steps) {
+    const double rho = s->rho[region];
+    const double smax = rho > 0.0 ? 10.0 * R / rho : INFINITY;
+    double th;
+    int64_t tri;
+    const int hit = orc_closest_hit(s, p, e, last, &th, &tri);
+    if (hit && th < smax) {
+      const double Rn = fmax(0.0, R - rho * th / 10.0);
+      const double Tn = csda_energy(Rn);
+      const double dep = Tcur - Tn;
+      out.tot += dep;
+      if (s->act[region]) out.act += dep;
+      Tcur = Tn;
+      R = Rn;
+      for (int a = 0; a < 3; ++a) p[a] += th * e[a];
+      const double* fv = V(s, tri);
+      double e1[3], e2[3], fn[3];
+      sub3(fv + 3, fv, e1);
+      sub3(fv + 6, fv, e2);
+      cross3(e1, e2, fn);
+      const double fl = norm3(fn);
+      const double side = dot3(e, fn) >= 0.0 ? STEP_NORMAL / fl : -STEP_NORMAL / fl;
+      double q[3];
+      for (int a = 0; a < 3; ++a) q[a] = p[a] + STEP_PAST * e[a] + side * fn[a];
+      region = orc_locate(s, q);
+      last = tri;
+      if (region < 0) {
+        out.lost = 1;
+        return out;
+      }
+      continue;
+    }
+    if (rho > 0.0) { /* the range ends inside this region */
+      out.tot += Tcur;
+      if (s->act[region]) out.act += Tcur;
+      return out;
+    }
+    /* void and no facet ahead: out of the world (or lost inside a void shell) */
+    out.esc = Tcur;
+    out.lost = region != 0;
+    return out;
+  }
+  out.lost = 1;
+  return out;
+}
+
+int32_t orc_set_electrons(orc_scene* s, int32_t on) {
+  if (!s) return -1;
+  s->electrons = on ? 1 : 0;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* transport */
 
 typedef struct {
@@ -688,6 +796,29 @@ static void one_history(worker* w, int64_t h) {
       clean = 0;                 \
   } while (0)
 
+/* kinetic energy x given to an electron at p along direction ed in region
+ * reg: a CSDA track, or a local deposit below ELEC_TMIN or without electrons */
+#define ELECTRON(x, ed, reg)                                             \
+  do {                                                                   \
+    if (s->electrons && (x) >= ELEC_TMIN) {                              \
+      const etrack et = electron_track(s, p, (ed), (x), (reg));          \
+      edep_tot += et.tot;                                                \
+      edep_act += et.act;                                                \
+      if (et.tot > et.act || et.esc > 0.0) clean = 0;                    \
+      if (et.esc > 0.0) {                                                \
+        e_esc += et.esc;                                                 \
+        T->e_escape += et.esc;                                           \
+      }                                                                  \
+      if (et.lost) {                                                     \
+        T->n_lost++;                                                     \
+        broken = 1;                                                      \
+      }                                                                  \
+      T->n_electrons++;                                                  \
+    } else {                                                             \
+      DEPOSIT((x), (reg));                                               \
+    }                                                                    \
+  } while (0)
+
 /* the current photon is done (absorbed or escaped): go on with the waiting
  * annihilation photon, if there is one */
 #define NEXT_PHOTON()                    \
@@ -760,7 +891,15 @@ static void one_history(worker* w, int64_t h) {
       double x = rng_uniform(&g) * mu;
       if (x < mu4[0]) {
         T->n_photo++;
-        DEPOSIT(E, region);
+        if (s->electrons && E >= ELEC_TMIN) {
+          /* the photoelectron leaves isotropically (synthetic reading) */
+          double ed[3];
+          isotropic(&g, ed);
+          ELECTRON(E, ed, region);
+        } else {
+          DEPOSIT(E, region);
+        }
+        if (broken) break;
         NEXT_PHOTON();
         absorbed = !escaped;
         break;
@@ -771,7 +910,19 @@ static void one_history(worker* w, int64_t h) {
         double ct = 1.0 - (1.0 / eps - 1.0) / k;
         double ph = 2.0 * PI * rng_uniform(&g);
         double Ep = eps * E;
-        DEPOSIT(E - Ep, region);
+        if (s->electrons && E - Ep >= ELEC_TMIN) {
+          /* the recoil electron: in the scattering plane, on the other side,
+           * at cot(theta_e) = (1 + k) tan(theta / 2) from the incoming photon */
+          const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+          const double a = (1.0 + k) * st, b = 1.0 + ct;
+          const double cte = a / sqrt(a * a + b * b);
+          double ed[3] = {d[0], d[1], d[2]};
+          rotate(ed, cte, ph + PI);
+          ELECTRON(E - Ep, ed, region);
+          if (broken) break;
+        } else {
+          DEPOSIT(E - Ep, region);
+        }
         rotate(d, ct, ph);
         E = Ep;
         if (E < Ecut) {
@@ -790,7 +941,9 @@ static void one_history(worker* w, int64_t h) {
          * E - 2 m_e c^2 is deposited here and the positron annihilates at
          * rest into two 511 keV photons flying apart along a random axis */
         T->n_pair++;
-        DEPOSIT(E - 2.0 * MEC2, region);
+        /* the pair's kinetic energy as one track along the photon (reading) */
+        ELECTRON(E - 2.0 * MEC2, d, region);
+        if (broken) break;
         double a[3];
         isotropic(&g, a);
         memcpy(p2, p, sizeof p2);
@@ -821,6 +974,7 @@ static void one_history(worker* w, int64_t h) {
     break;
   }
 #undef DEPOSIT
+#undef ELECTRON
 #undef NEXT_PHOTON
 
   if (escaped && !broken) T->n_escape++;
@@ -933,6 +1087,7 @@ int32_t orc_run(const orc_scene* s, const orc_source* src, double E0, int64_t n,
     out->n_compton += t->n_compton;
     out->n_coherent += t->n_coherent;
     out->n_pair += t->n_pair;
+    out->n_electrons += t->n_electrons;
     out->spectrum_overflow += t->spectrum_overflow;
     out->edep_active += t->edep_active;
     out->edep_total += t->edep_total;

@@ -54,6 +54,18 @@ int32_t orc_set_xs(orc_scene* s, int32_t material, double lnE0, double dlnE, int
                    const double* photo, const double* compton, const double* coherent,
                    const double* pair);
 
+/* Secondary electrons (synthetic reading of Sec. 2.4.1's electron transport):
+ * on = 1 makes every electron of at least 10 keV set in motion by a photo-
+ * electric absorption (isotropic), a Compton scattering (recoil direction
+ * from two-body kinematics) or a pair production (the pair's kinetic energy
+ * as one track along the photon) run a straight continuous-slowing-down track
+ * with the Katz-Penfold (1952) mass range, leaving in each region the energy
+ * it loses there and carrying the rest out of the world through void; 0
+ * (default) deposits their energy at the interaction point. */
+int32_t orc_set_electrons(orc_scene* s, int32_t on);
+double orc_csda_range(double T_keV);   /* g/cm^2 */
+double orc_csda_energy(double R);      /* keV */
+
 /* Ray-parity localization (Sec. 2.4.2).  Returns region id, or -1 if every
  * probe direction was degenerate. */
 int32_t orc_locate(const orc_scene* s, const double p[3]);
@@ -90,7 +102,7 @@ typedef struct {
 typedef struct {
   uint64_t n_histories, n_absorbed, n_fep, n_uncollided, n_escape, n_lost, n_killed,
       n_source_fail, n_balance_fail;
-  uint64_t n_segments, n_crossings, n_photo, n_compton, n_coherent, n_pair;
+  uint64_t n_segments, n_crossings, n_photo, n_compton, n_coherent, n_pair, n_electrons;
   uint64_t spectrum_overflow;
   double edep_active, edep_total, e_escape;
   double sum_score[ORC_MAX_GROUPS];

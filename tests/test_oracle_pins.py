@@ -732,3 +732,72 @@ def test_single_scatter_thin_slab_spectrum(orc):
     assert hit - obs.sum() <= 0.01 * hit
     assert stats.chisquare(obs, obs.sum() * w / w.sum()).pvalue > 1e-3
     assert t.n_balance_fail == 0
+
+
+# --------------------------------------------------------------------------
+# secondary electrons: straight CSDA tracks (Katz-Penfold mass range)
+
+def _electron_slab_fepe(mu, d, R):
+    """FEPE of a normal pencil beam on a photo-only ACTIVE slab of thickness d
+    whose photoelectrons leave isotropically from the absorption depth z and
+    run a straight range R: one escapes through a face at distance h with
+    probability (1 - h/R)/2 for h < R (the directions within arccos(h/R) of
+    the face's normal), and then takes part of the energy out of the world."""
+    from scipy import integrate
+
+    def f(h):
+        return max(0.0, 1.0 - h / R) / 2.0
+
+    val, _ = integrate.quad(lambda z: mu * math.exp(-mu * z) * (1.0 - f(z) - f(d - z)), 0.0, d,
+                            points=[R, d - R], limit=200)
+    return val
+
+
+@pytest.mark.parametrize("E", [400.0, 1000.0])
+def test_photoelectron_escape_from_a_slab(orc, E):
+    # density 5 g/cm3, photo partial 1 cm2/g: mu = 0.5 / mm; slab 2 mm
+    rho, d = 5.0, 2.0
+    scene, mats, tabs, grid = C.slab(d, 1.0, density=rho)
+    s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+    s.set_region(0, 0, 0.0, -1, False)
+    s.set_region(1, 1, rho, -1, True)
+    for m, t in tabs.items():
+        s.set_xs(m, grid, *t)
+    s.set_electrons(True)
+    R = 10.0 * orc.lib().orc_csda_range(E) / rho  # mm
+    assert 0.1 < R < d / 2
+    src = C.Source(C.KIND_BEAM, pos=(0.3, -0.2, 10.0), direction=(0.0, 0.0, -1.0))
+    n = 600_000
+    r = s.run(src, E, n, 77)
+    expect = _electron_slab_fepe(0.5, d, R)
+    p = r.fepe()
+    sig = math.sqrt(expect * (1 - expect) / n)
+    assert abs(p - expect) <= 3 * sig, (E, p, expect, sig)
+    # without the electron tracks every absorbed photon is a full-energy event
+    no_elec = 1.0 - math.exp(-0.5 * d)
+    assert p < no_elec - 10 * sig
+    t = r.tally
+    assert t.n_balance_fail == 0 and t.n_lost == 0 and t.n_electrons == t.n_photo
+    assert t.edep_total + t.e_escape == pytest.approx(n * E, rel=1e-9)
+
+
+def test_csda_range_inverse_and_threshold(orc):
+    L = orc.lib()
+    for T in (12.0, 100.0, 661.7, 2499.0, 2501.0, 3000.0):
+        assert L.orc_csda_energy(L.orc_csda_range(T)) == pytest.approx(T, rel=1e-9)
+    rs = [L.orc_csda_range(T) for T in np.linspace(10.0, 3000.0, 400)]
+    assert all(b > a for a, b in zip(rs, rs[1:]))
+    # below 10 keV (the range relation's lower end) electrons deposit in place:
+    # results equal those without electrons
+    scene, mats, tabs, grid = C.slab(2.0, 1.0, density=5.0)
+    out = []
+    for on in (False, True):
+        s = orc.Scene(scene.xyz, scene.tri, scene.tri_region, scene.n_regions)
+        s.set_region(0, 0, 0.0, -1, False)
+        s.set_region(1, 1, 5.0, -1, True)
+        for m, t in tabs.items():
+            s.set_xs(m, grid, *t)
+        s.set_electrons(on)
+        src = C.Source(C.KIND_BEAM, pos=(0.0, 0.0, 10.0), direction=(0.0, 0.0, -1.0))
+        out.append(s.run(src, 8.0, 20_000, 5).tally)
+    assert out[0].n_fep == out[1].n_fep and out[1].n_electrons == 0
