@@ -95,7 +95,7 @@ typedef enum {
                                  leave through the planes without nearing the inner
                                  shells, and transports the rest in full.  Tallies
                                  are identical either way                             */
-  GADEP_OPT_POOL = 13         /* 1 = pooled transport kernel: each wavefront keeps 96
+  GADEP_OPT_POOL = 13,        /* 1 = pooled transport kernel: each wavefront keeps 96
                                  photons in LDS for its 64 lanes, steps rays with full
                                  lanes while set-up rays last, and runs outcomes, new
                                  histories and set-up 64 photons at a time
@@ -104,6 +104,20 @@ typedef enum {
                                  0 = per-lane kernel (0; the faster one on MI355X: the
                                  pooled kernel's LDS and registers allow 2 wavefronts
                                  per SIMD against 3).  Tallies are the same either way */
+  GADEP_OPT_ELECTRONS = 14    /* 1 = secondary electrons run straight tracks (a
+                                 synthetic reading of the electron transport of
+                                 Sec. 2.4.1; 0 = their energy is deposited where they
+                                 start, the default): every electron of at least 10
+                                 keV set in motion by a photoelectric absorption
+                                 (isotropic), a Compton scattering (two-body recoil
+                                 direction) or a pair production (the pair's kinetic
+                                 energy, along the photon) runs a continuous-slowing-
+                                 down track with the Katz-Penfold (1952) mass range
+                                 at the regions' nominal densities; each region it
+                                 crosses keeps the energy it loses there, and one
+                                 that reaches the void world carries the rest out
+                                 (the history is then not full-energy).  Per-lane
+                                 kernel only (GADEP_E_ARG with GADEP_OPT_POOL = 1) */
 } gadep_option;
 gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t value);
 gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* value);
@@ -330,6 +344,7 @@ typedef struct {
    * the attenuation nor the exit planes are evaluated (no segment is counted) */
   uint64_t box_tests;
   uint64_t pair;        /* pair-production events */
+  uint64_t electrons;   /* electron tracks (GADEP_OPT_ELECTRONS) */
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 

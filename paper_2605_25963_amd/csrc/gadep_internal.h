@@ -148,6 +148,7 @@ enum EventSlot : int {
   // screened histories settled by one box test (no attenuation, no exit planes)
   kEv_BoxTests,
   kEv_Pair,  // pair-production events
+  kEv_Electrons,  // electron tracks
   kEv_N
 };
 static_assert(kT_Ev + kEv_N <= kT_FepScore2Lo, "tally slots");

@@ -173,6 +173,7 @@ struct gadep_ctx {
   int64_t split_pct = 100;
   int64_t screen = 1;
   int64_t pool = 0;
+  int64_t electrons = 0;
 
   DevBuf units, chunk_begin, scene_tab, sources, lines, regions, tally, spectra, cursor;
   void* h_tally = nullptr;  // pinned
@@ -589,12 +590,14 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   K.pair = 0;
   for (const Material& m : ctx->mats)
     if (m.set && m.pair) K.pair = 1;
+  if (ctx->electrons && ctx->pool)
+    return set_err(ctx, GADEP_E_ARG, "electron tracks run with the per-lane kernel (GADEP_OPT_POOL = 0)");
 
   bool vol = false;
   for (const SourceRec& sr : P.sources) vol = vol || sr.kind == kCyl;
   const int variant =
       (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0) | (vol ? 8 : 0) |
-      (K.pair ? 16 : 0);
+      (K.pair ? 16 : 0) | (ctx->electrons ? 32 : 0);
   const int block = ctx->pool ? 64 : static_cast<int>(ctx->block);
   int grid = 0;
   HIP_TRY(pick_grid(ctx, variant, P.depth, K.pair, &grid), "occupancy");
@@ -726,6 +729,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     cnt.cycles_traversal += ev[kEv_CycTrav];
     cnt.box_tests += ev[kEv_BoxTests];
     cnt.pair += ev[kEv_Pair];
+    cnt.electrons += ev[kEv_Electrons];
   }
   if (ctx->counters) {
     ctx->last_counters = cnt;
@@ -871,6 +875,9 @@ gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t v) {
     case GADEP_OPT_POOL:
       ctx->pool = v ? 1 : 0;
       return GADEP_OK;
+    case GADEP_OPT_ELECTRONS:
+      ctx->electrons = v ? 1 : 0;
+      return GADEP_OK;
     default:
       return set_err(ctx, GADEP_E_ARG, "unknown option");
   }
@@ -892,6 +899,7 @@ gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* v) 
     case GADEP_OPT_SPLIT_PCT: *v = ctx->split_pct; return GADEP_OK;
     case GADEP_OPT_SCREEN: *v = ctx->screen; return GADEP_OK;
     case GADEP_OPT_POOL: *v = ctx->pool; return GADEP_OK;
+    case GADEP_OPT_ELECTRONS: *v = ctx->electrons; return GADEP_OK;
     default: return GADEP_E_ARG;
   }
 }
@@ -1428,7 +1436,10 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
   K.pair = 0;
   for (const Material& m : ctx->mats)
     if (m.set && m.pair) K.pair = 1;
-  const int variant = (spectrum ? 2 : 0) | (src->kind == GADEP_SRC_CYL ? 8 : 0) | (K.pair ? 16 : 0);
+  if (ctx->electrons && ctx->pool)
+    return set_err(ctx, GADEP_E_ARG, "electron tracks run with the per-lane kernel (GADEP_OPT_POOL = 0)");
+  const int variant = (spectrum ? 2 : 0) | (src->kind == GADEP_SRC_CYL ? 8 : 0) | (K.pair ? 16 : 0) |
+                      (ctx->electrons ? 32 : 0);
   int grid = 0;
   HIP_TRY(pick_grid(ctx, variant, K.stack_depth, K.pair, &grid), "occupancy");
   if (grid < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");

@@ -24,66 +24,6 @@
 namespace gadep {
 
 // ---------------------------------------------------------------------------
-// closest hit with the region-consistency filter
-
-struct HitOut {
-  float t;
-  int slot;
-  int region_after;
-};
-
-// Closest facet with 0 < t <= tmax, skipping slot `exclude`.  A candidate is
-// accepted only if it is consistent with the current region: entering
-// requires outside == cur, leaving requires inside == cur (cur < 0: accept
-// all).  Returns true on a hit; `glitch` is set when a rejected candidate lay
-// nearer than the accepted one.
-template <bool COUNT>
-__device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, float ox, float oy,
-                                            float oz, float dx, float dy, float dz, float tmax,
-                                            int exclude, int cur, int* stack, int stride,
-                                            HitOut& h, bool& glitch, uint32_t& nvis,
-                                            uint32_t& ntri, int root = 0) {
-  float best = tmax;
-  int best_slot = -1;
-  int best_reg = 0;
-  float rejected = INFINITY;
-  const TriRec* __restrict__ tris = sc.tris;
-  float tm = tmax;
-  const uint32_t v = traverse(sc.nodes, r, tm, stack, stride, sc.depth, [&](int first, int count,
-                                                                             float tcur) {
-    for (int k = 0; k < count; ++k) {
-      const int slot = first + k;
-      if (COUNT) ntri++;
-      if (slot == exclude) continue;
-      float4 a, b, c;
-      load_tri(tris, gload(sc.slots, slot), a, b, c);
-      float t;
-      bool enter;
-      if (wt_test(r, ox, oy, oz, dx, dy, dz, a, b, c, tcur, t, enter) == kWtMiss) continue;
-      const uint32_t regs = __float_as_uint(c.y);
-      const int inside = static_cast<int>(regs & 0xFFFFu);
-      const int outside = static_cast<int>(regs >> 16);
-      if (cur >= 0 && (enter ? outside : inside) != cur) {
-        rejected = fminf(rejected, t);
-        continue;
-      }
-      tcur = t;
-      best = t;
-      best_slot = slot;
-      best_reg = enter ? inside : outside;
-    }
-    return tcur;
-  }, root);
-  if (COUNT) nvis += v;
-  glitch = rejected < best;
-  if (best_slot < 0) return false;
-  h.t = best;
-  h.slot = best_slot;
-  h.region_after = best_reg;
-  return true;
-}
-
-// ---------------------------------------------------------------------------
 // ray-parity localization (Sec. 2.4.2): count crossings per closed geometry
 // along a probe ray; odd => inside; the odd geometry crossed first contains
 // the point; none odd => world.  Two traversals: the parity mask, then the
@@ -181,8 +121,9 @@ __device__ int locate_two_level(const SceneRec& sc, float px, float py, float pz
 // GRAD: score-function tallies; SPEC: pulse-height spectra; COUNT: event
 // counters; VOL: some unit has a volume source (emission points are
 // localised by probe traversals); PAIR: some material has a pair-production
-// partial (pair events, waiting annihilation photons).
-template <bool GRAD, bool SPEC, bool COUNT, bool VOL, bool PAIR>
+// partial (pair events, waiting annihilation photons); ELEC: secondary
+// electrons run CSDA tracks.
+template <bool GRAD, bool SPEC, bool COUNT, bool VOL, bool PAIR, bool ELEC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 transport_kernel(TransportParams P) {
   extern __shared__ unsigned long long smem[];
@@ -381,6 +322,28 @@ transport_kernel(TransportParams P) {
     }
   };
 
+  // kinetic energy T given to an electron where the photon is, moving along
+  // (ex, ey, ez): a CSDA track when electrons are on (returns true if it
+  // ended lost), else deposited in place
+  auto electron = [&](float T, float ex, float ey, float ez, bool active) -> bool {
+    if (ELEC && T >= kElecMin) {
+      if (COUNT) ev[kEv_Electrons]++;
+      const ElecOut eo = electron_track(P.scenes + U.scene, P.regions + U.region_off, px, py, pz,
+                                        ex, ey, ez, T, region, stack, stride);
+      edep_tot += eo.tot;
+      edep_act += eo.act;
+      if (eo.tot > eo.act || eo.esc > 0.0f) clean = false;
+      if (eo.esc > 0.0f) atomicAdd(&wt[kT_EEsc], fx_kev(eo.esc));
+      return eo.lost != 0;
+    }
+    edep_tot += T;
+    if (active)
+      edep_act += T;
+    else
+      clean = false;
+    return false;
+  };
+
   // a point of a volume source, uniform in its cylindrical annulus
   auto sample_point = [&]() {
     const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
@@ -498,12 +461,18 @@ transport_kernel(TransportParams P) {
           const float x = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]) * mu;
           if (x < mp) {
             if (COUNT) ev[kEv_Photo]++;
-            edep_tot += E;
-            if (active)
-              edep_act += E;
-            else
-              clean = false;
-            end_history(true, false, false, false);
+            bool lost_e = false;
+            if (ELEC && E >= kElecMin) {
+              // the photoelectron leaves isotropically (synthetic reading)
+              const float ce = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
+              const float se = hw_sqrt(fmaxf(0.0f, 1.0f - ce * ce));
+              const float ue = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+              lost_e = electron(E, se * __builtin_amdgcn_cosf(ue), se * __builtin_amdgcn_sinf(ue), ce,
+                                active);
+            } else {
+              electron(E, 0.0f, 0.0f, 1.0f, active);
+            }
+            end_history(!lost_e, false, lost_e, false);
           } else {
             bool absorbed = false;
             if (x < mp + mc) {
@@ -536,14 +505,25 @@ transport_kernel(TransportParams P) {
               }
               const float Ep = eps * E;
               const float dep = E - Ep;
-              edep_tot += dep;
-              if (active)
-                edep_act += dep;
-              else
-                clean = false;
-              turn(dx, dy, dz, 1.0f - t, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
+              const float uph = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+              bool lost_e = false;
+              if (ELEC && dep >= kElecMin) {
+                // the recoil electron: in the scattering plane, on the other
+                // side, at cot(theta_e) = (1 + k) tan(theta / 2)
+                const float ctg = 1.0f - t;
+                const float a = (1.0f + k) * hw_sqrt(fmaxf(0.0f, 1.0f - ctg * ctg)), b = 1.0f + ctg;
+                float ex = dx, ey = dy, ez = dz;
+                turn(ex, ey, ez, a * rsqrtf(fmaf(a, a, b * b)), uph + 0.5f);
+                lost_e = electron(dep, ex, ey, ez, active);
+              } else {
+                electron(dep, 0.0f, 0.0f, 1.0f, active);
+              }
+              turn(dx, dy, dz, 1.0f - t, uph);
               E = Ep;
-              if (E < P.e_cut) {
+              if (lost_e) {
+                end_history(false, false, true, false);
+                absorbed = true;  // the history is over
+              } else if (E < P.e_cut) {
                 edep_tot += E;
                 if (active)
                   edep_act += E;
@@ -571,26 +551,27 @@ transport_kernel(TransportParams P) {
               // This lane follows the first; the second waits in LDS.
               if (COUNT) ev[kEv_Pair]++;
               const float kin = E - 2.0f * kMec2;
-              edep_tot += kin;
-              if (active)
-                edep_act += kin;
-              else
-                clean = false;
-              const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
-              const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
-              const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
-              dx = st * __builtin_amdgcn_cosf(uphi);
-              dy = st * __builtin_amdgcn_sinf(uphi);
-              dz = ct;
-              wait[0] = __float_as_int(px);
-              wait[stride] = __float_as_int(py);
-              wait[2 * stride] = __float_as_int(pz);
-              wait[3 * stride] = __float_as_int(-dx);
-              wait[4 * stride] = __float_as_int(-dy);
-              wait[5 * stride] = __float_as_int(-dz);
-              wait[6 * stride] = region;
-              E = kMec2;
-              ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+              // the pair's kinetic energy as one track along the photon (reading)
+              if (electron(kin, dx, dy, dz, active)) {
+                end_history(false, false, true, false);
+                absorbed = true;  // the history is over
+              } else {
+                const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
+                const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
+                const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+                dx = st * __builtin_amdgcn_cosf(uphi);
+                dy = st * __builtin_amdgcn_sinf(uphi);
+                dz = ct;
+                wait[0] = __float_as_int(px);
+                wait[stride] = __float_as_int(py);
+                wait[2 * stride] = __float_as_int(pz);
+                wait[3 * stride] = __float_as_int(-dx);
+                wait[4 * stride] = __float_as_int(-dy);
+                wait[5 * stride] = __float_as_int(-dz);
+                wait[6 * stride] = region;
+                E = kMec2;
+                ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+              }
             }
             if (!absorbed) tau = -hw_log(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
           }
@@ -1224,7 +1205,8 @@ using TK = void (*)(TransportParams);
 
 template <int V>
 constexpr TK variant_kernel() {
-  return transport_kernel<(V & 1) != 0, (V & 2) != 0, (V & 4) != 0, (V & 8) != 0, (V & 16) != 0>;
+  return transport_kernel<(V & 1) != 0, (V & 2) != 0, (V & 4) != 0, (V & 8) != 0, (V & 16) != 0,
+                          (V & 32) != 0>;
 }
 
 template <int... V>
@@ -1233,8 +1215,8 @@ static TK pick_from(int variant, std::integer_sequence<int, V...>) {
   return table[variant];
 }
 
-// variant bits: 1 GRAD, 2 SPEC, 4 COUNT, 8 VOL, 16 PAIR
-static TK pick(int variant) { return pick_from(variant & 31, std::make_integer_sequence<int, 32>{}); }
+// variant bits: 1 GRAD, 2 SPEC, 4 COUNT, 8 VOL, 16 PAIR, 32 ELEC
+static TK pick(int variant) { return pick_from(variant & 63, std::make_integer_sequence<int, 64>{}); }
 
 // LDS: per-wavefront tallies, the traversal stacks, and (GRAD) the scores
 size_t transport_smem(int block, int depth, bool grad, bool pair) {

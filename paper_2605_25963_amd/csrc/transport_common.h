@@ -106,6 +106,165 @@ __device__ __forceinline__ unsigned long long fx(double v, double scale) {
   return static_cast<unsigned long long>(__double2ll_rn(v * scale));
 }
 
+// ---------------------------------------------------------------------------
+// closest hit with the region-consistency filter
+
+struct HitOut {
+  float t;
+  int slot;
+  int region_after;
+};
+
+// Closest facet with 0 < t <= tmax, skipping slot `exclude`.  A candidate is
+// accepted only if it is consistent with the current region: entering
+// requires outside == cur, leaving requires inside == cur (cur < 0: accept
+// all).  Returns true on a hit; `glitch` is set when a rejected candidate lay
+// nearer than the accepted one.
+template <bool COUNT>
+__device__ __forceinline__ bool closest_hit(const SceneRec& sc, const Ray& r, float ox, float oy,
+                                            float oz, float dx, float dy, float dz, float tmax,
+                                            int exclude, int cur, int* stack, int stride,
+                                            HitOut& h, bool& glitch, uint32_t& nvis,
+                                            uint32_t& ntri, int root = 0) {
+  float best = tmax;
+  int best_slot = -1;
+  int best_reg = 0;
+  float rejected = INFINITY;
+  const TriRec* __restrict__ tris = sc.tris;
+  float tm = tmax;
+  const uint32_t v = traverse(sc.nodes, r, tm, stack, stride, sc.depth, [&](int first, int count,
+                                                                             float tcur) {
+    for (int k = 0; k < count; ++k) {
+      const int slot = first + k;
+      if (COUNT) ntri++;
+      if (slot == exclude) continue;
+      float4 a, b, c;
+      load_tri(tris, gload(sc.slots, slot), a, b, c);
+      float t;
+      bool enter;
+      if (wt_test(r, ox, oy, oz, dx, dy, dz, a, b, c, tcur, t, enter) == kWtMiss) continue;
+      const uint32_t regs = __float_as_uint(c.y);
+      const int inside = static_cast<int>(regs & 0xFFFFu);
+      const int outside = static_cast<int>(regs >> 16);
+      if (cur >= 0 && (enter ? outside : inside) != cur) {
+        rejected = fminf(rejected, t);
+        continue;
+      }
+      tcur = t;
+      best = t;
+      best_slot = slot;
+      best_reg = enter ? inside : outside;
+    }
+    return tcur;
+  }, root);
+  if (COUNT) nvis += v;
+  glitch = rejected < best;
+  if (best_slot < 0) return false;
+  h.t = best;
+  h.slot = best_slot;
+  h.region_after = best_reg;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// secondary electrons (the straight-track reading of the electron transport
+// of Sec. 2.4.1): each electron of at least kElecMin set in motion by a
+// photoelectric absorption, a Compton scattering or a pair production runs a
+// straight continuous-slowing-down track with the Katz-Penfold (1952) mass
+// range, and every region it crosses keeps the energy it loses there.
+
+constexpr float kElecMin = 10.0f;  // keV: lower end of the range relation
+
+// mass range [g/cm^2] of an electron of kinetic energy T [keV]
+__device__ __forceinline__ float csda_range(float T) {
+  const float t = T * 1e-3f;
+  if (t > 2.5f) return 0.530f * t - 0.106f;
+  if (!(t > 0.0f)) return 0.0f;
+  const float lt = __logf(t);
+  return 0.412f * __expf((1.265f - 0.0954f * lt) * lt);
+}
+
+// kinetic energy [keV] with mass range R: bisection (the range grows with T)
+__device__ __forceinline__ float csda_energy(float R) {
+  if (!(R > 0.0f)) return 0.0f;
+  float lo = 0.0f, hi = 4000.0f;
+  for (int i = 0; i < 32; ++i) {
+    const float m = 0.5f * (lo + hi);
+    if (csda_range(m) < R)
+      lo = m;
+    else
+      hi = m;
+  }
+  return 0.5f * (lo + hi);
+}
+
+struct ElecOut {
+  float act, tot, esc;  // energy left in ACTIVE regions, in all regions, carried out of the world
+  int lost;             // ended in a void region that is not the world
+};
+
+// The track of an electron of kinetic energy T from p along the unit
+// direction e in `region`: nearest facets on the plain BVHs (of an overlay
+// too) with the region-consistency filter; in a region of nominal density
+// rho it runs 10 R / rho mm on its remaining range R.  Out of line: it is
+// rare, and its traversal loop would otherwise swell the transport kernel.
+// `stack` is the calling lane's LDS column (entries stack[k * stride]), free
+// while the lane does the per-segment work.
+__device__ __noinline__ ElecOut electron_track(const SceneRec* __restrict__ scene,
+                                               const RegionRec* __restrict__ regions, float px,
+                                               float py, float pz, float ex, float ey, float ez,
+                                               float T, int region, int* stack, int stride) {
+  const SceneRec S = *scene;
+  ElecOut out{0.0f, 0.0f, 0.0f, 0};
+  float R = csda_range(T), Tcur = T;
+  int excl = -1;
+  uint32_t nv = 0, nt = 0;
+  for (int it = 0; it < 4096; ++it) {
+    const RegionRec rr = gload(regions, region);
+    const float rho10 = rr.mult * rr.inv_scale;  // 0.1 x nominal density: g/cm^2 per mm
+    const bool active = (rr.bits >> 8) & 1;
+    const float smax = rho10 > 0.0f ? R / rho10 : INFINITY;
+    const Ray r = make_ray(px, py, pz, ex, ey, ez);
+    HitOut h;
+    bool glitch;
+    bool hit = closest_hit<false>(S, r, px, py, pz, ex, ey, ez, smax, excl, region, stack, stride,
+                                  h, glitch, nv, nt);
+    if (S.root_all2 >= 0) {
+      HitOut h2;
+      if (closest_hit<false>(S, r, px, py, pz, ex, ey, ez, hit ? h.t : smax, excl, region, stack,
+                             stride, h2, glitch, nv, nt, S.root_all2)) {
+        h = h2;
+        hit = true;
+      }
+    }
+    if (hit) {
+      const float Rn = fmaxf(0.0f, R - rho10 * h.t);
+      const float Tn = csda_energy(Rn);
+      const float dep = Tcur - Tn;
+      out.tot += dep;
+      if (active) out.act += dep;
+      Tcur = Tn;
+      R = Rn;
+      px = fmaf(h.t, ex, px);
+      py = fmaf(h.t, ey, py);
+      pz = fmaf(h.t, ez, pz);
+      region = h.region_after;
+      excl = h.slot;
+      continue;
+    }
+    if (rho10 > 0.0f) {  // the range ends in this region
+      out.tot += Tcur;
+      if (active) out.act += Tcur;
+      return out;
+    }
+    out.esc = Tcur;  // void and no facet ahead
+    out.lost = region != 0;
+    return out;
+  }
+  out.lost = 1;
+  return out;
+}
+
 // Per-photon phases.  kSample: draw a volume-source point; kLaunch: the
 // emission point is settled, draw the direction and first flight; kResume: the
 // photon is done but a pair event left a second one waiting.

@@ -58,6 +58,9 @@ size_t pool_smem(int depth, bool grad, bool pair) {
 template <bool GRAD, bool SPEC, bool COUNT, bool VOL, bool PAIR>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
 pool_kernel(TransportParams P) {
+  // electron tracks need the lane's LDS stack column, which may hold a paused
+  // ray here: the runtime runs them with the per-lane kernel only
+  constexpr bool ELEC = false;
   extern __shared__ unsigned long long smem[];
   const int lane = static_cast<int>(__lane_id());
   const uint64_t lanes_below = (1ull << lane) - 1ull;
@@ -363,6 +366,18 @@ pool_kernel(TransportParams P) {
     }
   };
 
+  // kinetic energy T given to an electron where the photon is: deposited in
+  // place (the runtime runs electron tracks with the per-lane kernel only: a
+  // lane's LDS stack may hold a paused ray here)
+  auto electron = [&](float T, float, float, float, bool active) -> bool {
+    edep_tot += T;
+    if (active)
+      edep_act += T;
+    else
+      clean = false;
+    return false;
+  };
+
   // a point of a volume source, uniform in its cylindrical annulus
   auto sample_point = [&]() {
     const float r2lo = Src.r_in * Src.r_in, r2hi = Src.r_out * Src.r_out;
@@ -639,12 +654,18 @@ pool_kernel(TransportParams P) {
           const float x = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]) * mu;
           if (x < mp) {
             if (COUNT) ev[kEv_Photo]++;
-            edep_tot += E;
-            if (active)
-              edep_act += E;
-            else
-              clean = false;
-            end_history(true, false, false, false);
+            bool lost_e = false;
+            if (ELEC && E >= kElecMin) {
+              // the photoelectron leaves isotropically (synthetic reading)
+              const float ce = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
+              const float se = hw_sqrt(fmaxf(0.0f, 1.0f - ce * ce));
+              const float ue = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+              lost_e = electron(E, se * __builtin_amdgcn_cosf(ue), se * __builtin_amdgcn_sinf(ue), ce,
+                                active);
+            } else {
+              electron(E, 0.0f, 0.0f, 1.0f, active);
+            }
+            end_history(!lost_e, false, lost_e, false);
           } else {
             bool absorbed = false;
             if (x < mp + mc) {
@@ -677,14 +698,25 @@ pool_kernel(TransportParams P) {
               }
               const float Ep = eps * E;
               const float dep = E - Ep;
-              edep_tot += dep;
-              if (active)
-                edep_act += dep;
-              else
-                clean = false;
-              turn(dx, dy, dz, 1.0f - t, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
+              const float uph = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+              bool lost_e = false;
+              if (ELEC && dep >= kElecMin) {
+                // the recoil electron: in the scattering plane, on the other
+                // side, at cot(theta_e) = (1 + k) tan(theta / 2)
+                const float ctg = 1.0f - t;
+                const float a = (1.0f + k) * hw_sqrt(fmaxf(0.0f, 1.0f - ctg * ctg)), b = 1.0f + ctg;
+                float ex = dx, ey = dy, ez = dz;
+                turn(ex, ey, ez, a * rsqrtf(fmaf(a, a, b * b)), uph + 0.5f);
+                lost_e = electron(dep, ex, ey, ez, active);
+              } else {
+                electron(dep, 0.0f, 0.0f, 1.0f, active);
+              }
+              turn(dx, dy, dz, 1.0f - t, uph);
               E = Ep;
-              if (E < P.e_cut) {
+              if (lost_e) {
+                end_history(false, false, true, false);
+                absorbed = true;  // the history is over
+              } else if (E < P.e_cut) {
                 edep_tot += E;
                 if (active)
                   edep_act += E;
@@ -712,26 +744,27 @@ pool_kernel(TransportParams P) {
               // This lane follows the first; the second waits in LDS.
               if (COUNT) ev[kEv_Pair]++;
               const float kin = E - 2.0f * kMec2;
-              edep_tot += kin;
-              if (active)
-                edep_act += kin;
-              else
-                clean = false;
-              const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
-              const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
-              const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
-              dx = st * __builtin_amdgcn_cosf(uphi);
-              dy = st * __builtin_amdgcn_sinf(uphi);
-              dz = ct;
-              wait[0] = __float_as_int(px);
-              wait[stride] = __float_as_int(py);
-              wait[2 * stride] = __float_as_int(pz);
-              wait[3 * stride] = __float_as_int(-dx);
-              wait[4 * stride] = __float_as_int(-dy);
-              wait[5 * stride] = __float_as_int(-dz);
-              wait[6 * stride] = region;
-              E = kMec2;
-              ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+              // the pair's kinetic energy as one track along the photon (reading)
+              if (electron(kin, dx, dy, dz, active)) {
+                end_history(false, false, true, false);
+                absorbed = true;  // the history is over
+              } else {
+                const float ct = fmaf(2.0f, rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), -1.0f);
+                const float st = hw_sqrt(fmaxf(0.0f, 1.0f - ct * ct));
+                const float uphi = rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]);
+                dx = st * __builtin_amdgcn_cosf(uphi);
+                dy = st * __builtin_amdgcn_sinf(uphi);
+                dz = ct;
+                wait[0] = __float_as_int(px);
+                wait[stride] = __float_as_int(py);
+                wait[2 * stride] = __float_as_int(pz);
+                wait[3 * stride] = __float_as_int(-dx);
+                wait[4 * stride] = __float_as_int(-dy);
+                wait[5 * stride] = __float_as_int(-dz);
+                wait[6 * stride] = region;
+                E = kMec2;
+                ix = xs_index(E, P.ln_e0, P.inv_dlne, P.n_e);
+              }
             }
             if (!absorbed) tau = -hw_log(rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]));
           }
