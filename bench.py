@@ -59,8 +59,11 @@ PEAK_LANE_OPS = 256 * 4 * 16 * PEAK_SCLK_MHZ * 1e6
 # runs scaled by a copy probe (profiles/transport_hpge20k_counters.md), valid only
 # for the kernel sources they were taken with (SHA-256 of the files below).
 KERNEL_SOURCES = ["paper_2605_25963_amd/csrc/transport.hip",
+                  "paper_2605_25963_amd/csrc/transport_common.h",
                   "paper_2605_25963_amd/csrc/device_common.h",
-                  "paper_2605_25963_amd/csrc/gadep_internal.h"]
+                  "paper_2605_25963_amd/csrc/gadep_internal.h",
+                  "paper_2605_25963_amd/csrc/runtime.cpp",
+                  "paper_2605_25963_amd/csrc/mesh_prep.cpp"]
 MEASURED_TRAFFIC = {"sources_sha256": "13ae446c4287d4b51986105f3b8fd2c01b842f8209a656d46b33ce1d336a6e41",
                     "bytes_per_launch": 9.00e7}
 

@@ -75,7 +75,8 @@ typedef enum {
                                  traversal wait until this many (1..64) have, then the
                                  wavefront runs physics, scoring and new histories for
                                  all of them together; 0 = default (24)                */
-  GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim (16)       */
+  GADEP_OPT_CLAIM = 4,        /* histories per lane taken by one work claim, the least
+                                 one when claims shrink (16)                          */
   GADEP_OPT_VALIDATE = 5,     /* 1 = validate meshes at load (default); 0 skips the
                                  closed/orientation/overlap checks (fault-injection
                                  tests only: results are undefined on a bad mesh)      */
@@ -86,7 +87,7 @@ typedef enum {
   GADEP_OPT_EXIT_PLANES = 10, /* 1 = leave a convex outermost shell through its planes
                                  when the world is void (1); 0 = through its facets   */
   GADEP_OPT_SPLIT_PCT = 11,   /* extra facet slots the transport BVH may add by spatial
-                                 splits, % of its facets (100); 0 = no spatial splits;
+                                 splits, % of its facets (400); 0 = no spatial splits;
                                  applies to meshes loaded afterwards                  */
   GADEP_OPT_SCREEN = 12,      /* 1 = first-flight screening (1): with exit planes and a
                                  point or beam source in the outermost shell's region,
@@ -104,7 +105,7 @@ typedef enum {
                                  0 = per-lane kernel (0; the faster one on MI355X: the
                                  pooled kernel's LDS and registers allow 2 wavefronts
                                  per SIMD against 3).  Tallies are the same either way */
-  GADEP_OPT_ELECTRONS = 14    /* 1 = secondary electrons run straight tracks (a
+  GADEP_OPT_ELECTRONS = 14,   /* 1 = secondary electrons run straight tracks (a
                                  synthetic reading of the electron transport of
                                  Sec. 2.4.1; 0 = their energy is deposited where they
                                  start, the default): every electron of at least 10
@@ -118,6 +119,15 @@ typedef enum {
                                  that reaches the void world carries the rest out
                                  (the history is then not full-energy).  Per-lane
                                  kernel only (GADEP_E_ARG with GADEP_OPT_POOL = 1) */
+  GADEP_OPT_GUIDE = 15        /* shrinking work claims (16): claims on an energy come
+                                 in batches, one claim per wavefront of the energy's
+                                 share of the grid, and each claim of a batch takes
+                                 1/(this value x that count) of the histories the
+                                 earlier batches left, down to 64 x GADEP_OPT_CLAIM
+                                 (factoring: large claims first, small ones at the
+                                 end); 0 = every claim takes 64 x GADEP_OPT_CLAIM.
+                                 Histories keep their counter-keyed random numbers,
+                                 so tallies do not depend on it (0..16) */
 } gadep_option;
 gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t value);
 gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* value);
@@ -345,6 +355,10 @@ typedef struct {
   uint64_t box_tests;
   uint64_t pair;        /* pair-production events */
   uint64_t electrons;   /* electron tracks (GADEP_OPT_ELECTRONS) */
+  /* wavefronts launched, and the sum of their lifetimes in shader-clock
+   * cycles: over wavefronts x launch duration x shader clock, the share of
+   * the launch the grid was busy (the rest is the tail of the work claims) */
+  uint64_t wavefronts, wave_cycles;
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 

@@ -164,7 +164,8 @@ struct TransportParams {
   const UnitRec* units;
   const int64_t* chunk_begin;  // [n_units + 1], prefix sums of chunks per unit
   int32_t n_units;
-  int32_t chunk;               // histories per chunk
+  int32_t chunk;               // histories per claim (the least, when claims shrink)
+  int64_t total_h;             // histories of all units
   const SceneRec* scenes;
   const SourceRec* sources;
   const float* lines;          // float2 pairs
@@ -178,14 +179,16 @@ struct TransportParams {
   unsigned long long* spectra; // [n_units][n_channels] or null
   int32_t n_channels;
   float inv_channel_kev;
-  unsigned long long* cursor;  // [n_units] chunk cursors
+  unsigned long long* cursor;  // [n_units] claims made per unit
   uint32_t seed_lo, seed_hi;
   int32_t max_steps;
   int32_t stack_depth;
   int32_t period;
   int32_t screen;              // 1: first-flight screening where it applies
   int32_t pair;                // 1: some material has a pair-production partial
+  int32_t guide;               // > 0: claims shrink by factoring (1/guide of the rest per batch)
 };
+static_assert(sizeof(TransportParams) % 8 == 0, "no tail padding in the graph key");
 
 // ---------------------------------------------------------------------------
 // host preparation (mesh_prep.cpp)

@@ -170,9 +170,10 @@ struct gadep_ctx {
   int64_t counters = 0;
   int64_t grid = 0;
   int64_t exit_planes = 1;
-  int64_t split_pct = 100;
+  int64_t split_pct = 400;
   int64_t screen = 1;
   int64_t pool = 0;
+  int64_t guide = 16;
   int64_t electrons = 0;
 
   DevBuf units, chunk_begin, scene_tab, sources, lines, regions, tally, spectra, cursor;
@@ -567,6 +568,9 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   K.chunk_begin = static_cast<const int64_t*>(ctx->chunk_begin.p);
   K.n_units = nu;
   K.chunk = static_cast<int32_t>(64 * ctx->claim);
+  K.total_h = 0;
+  for (const UnitRec& u : P.units) K.total_h += u.n;
+  K.guide = static_cast<int32_t>(ctx->guide);
   K.scenes = static_cast<const SceneRec*>(ctx->scene_tab.p);
   K.sources = static_cast<const SourceRec*>(ctx->sources.p);
   K.lines = static_cast<const float*>(ctx->lines.p);
@@ -593,10 +597,13 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   if (ctx->electrons && ctx->pool)
     return set_err(ctx, GADEP_E_ARG, "electron tracks run with the per-lane kernel (GADEP_OPT_POOL = 0)");
 
-  bool vol = false;
-  for (const SourceRec& sr : P.sources) vol = vol || sr.kind == kCyl;
+  // the general kernel variant: volume or cone sources, or a unit whose scene
+  // has overlays
+  bool gen = false;
+  for (const SourceRec& sr : P.sources) gen = gen || sr.kind == kCyl || sr.kind == kCone;
+  for (const UnitRec& u : P.units) gen = gen || st[u.scene].roots2 != nullptr;
   const int variant =
-      (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0) | (vol ? 8 : 0) |
+      (P.grad ? 1 : 0) | (P.spectrum ? 2 : 0) | (ctx->counters ? 4 : 0) | (gen ? 8 : 0) |
       (K.pair ? 16 : 0) | (ctx->electrons ? 32 : 0);
   const int block = ctx->pool ? 64 : static_cast<int>(ctx->block);
   int grid = 0;
@@ -686,8 +693,10 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
   const unsigned long long* T = static_cast<const unsigned long long*>(ctx->h_tally);
   note_clock(ctx, T, nu);
   gadep_counters cnt{};
+  cnt.wavefronts = static_cast<uint64_t>(grid) * (block / 64);
   for (int32_t u = 0; u < nu; ++u) {
     const unsigned long long* Tu = T + static_cast<int64_t>(u) * kT_Slots;
+    cnt.wave_cycles += Tu[kT_ClkCore];
     if (out) {
       gadep_tally& t = out[u];
       to_tally(Tu, t);
@@ -878,6 +887,10 @@ gadep_status gadep_set_option(gadep_ctx* ctx, int32_t option, int64_t v) {
     case GADEP_OPT_ELECTRONS:
       ctx->electrons = v ? 1 : 0;
       return GADEP_OK;
+    case GADEP_OPT_GUIDE:
+      if (v < 0 || v > 16) return set_err(ctx, GADEP_E_ARG, "guide must be in [0, 16]");
+      ctx->guide = v;
+      return GADEP_OK;
     default:
       return set_err(ctx, GADEP_E_ARG, "unknown option");
   }
@@ -899,6 +912,7 @@ gadep_status gadep_get_option(const gadep_ctx* ctx, int32_t option, int64_t* v) 
     case GADEP_OPT_SPLIT_PCT: *v = ctx->split_pct; return GADEP_OK;
     case GADEP_OPT_SCREEN: *v = ctx->screen; return GADEP_OK;
     case GADEP_OPT_POOL: *v = ctx->pool; return GADEP_OK;
+    case GADEP_OPT_GUIDE: *v = ctx->guide; return GADEP_OK;
     case GADEP_OPT_ELECTRONS: *v = ctx->electrons; return GADEP_OK;
     default: return GADEP_E_ARG;
   }
@@ -1413,6 +1427,8 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
   K.chunk_begin = reinterpret_cast<const int64_t*>(base + kNaChunks);
   K.n_units = n_energies;
   K.chunk = static_cast<int32_t>(chunk);
+  K.total_h = n * static_cast<int64_t>(n_energies);
+  K.guide = static_cast<int32_t>(ctx->guide);
   K.scenes = reinterpret_cast<const SceneRec*>(base + kNaScene);
   K.sources = reinterpret_cast<const SourceRec*>(base + kNaSource);
   K.lines = reinterpret_cast<const float*>(base + kNaLines);
@@ -1438,8 +1454,8 @@ gadep_status gadep_run_noalloc(gadep_ctx* ctx, const gadep_source* src, const do
     if (m.set && m.pair) K.pair = 1;
   if (ctx->electrons && ctx->pool)
     return set_err(ctx, GADEP_E_ARG, "electron tracks run with the per-lane kernel (GADEP_OPT_POOL = 0)");
-  const int variant = (spectrum ? 2 : 0) | (src->kind == GADEP_SRC_CYL ? 8 : 0) | (K.pair ? 16 : 0) |
-                      (ctx->electrons ? 32 : 0);
+  const bool gen = src->kind == GADEP_SRC_CYL || src->kind == GADEP_SRC_CONE || H.scene.roots2 != nullptr;
+  const int variant = (spectrum ? 2 : 0) | (gen ? 8 : 0) | (K.pair ? 16 : 0) | (ctx->electrons ? 32 : 0);
   int grid = 0;
   HIP_TRY(pick_grid(ctx, variant, K.stack_depth, K.pair, &grid), "occupancy");
   if (grid < 1) return set_err(ctx, GADEP_E_ARG, "block size does not fit (LDS or registers)");

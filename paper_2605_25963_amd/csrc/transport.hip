@@ -7,9 +7,10 @@
 //   boundary (region from the facet's inside/outside pair) or interact
 //   (photoelectric, Klein-Nishina Compton, Thomson coherent) -> score.
 // Work is claimed per wavefront in chunks of consecutive histories of one
-// unit; a lane whose history ends immediately starts the next history of the
-// chunk, and a wavefront only drains (waits for its live lanes) when its next
-// chunk belongs to another unit.  Tallies are integer (fixed point for sums),
+// unit (large chunks first, smaller ones toward the end of the unit); a lane
+// whose history ends immediately starts the next history of the chunk, and a
+// wavefront only drains (waits for its live lanes) when its next chunk
+// belongs to another unit.  Tallies are integer (fixed point for sums),
 // accumulated per wavefront in LDS and flushed with one global atomic per
 // slot, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -119,11 +120,13 @@ __device__ int locate_two_level(const SceneRec& sc, float px, float py, float pz
 
 
 // GRAD: score-function tallies; SPEC: pulse-height spectra; COUNT: event
-// counters; VOL: some unit has a volume source (emission points are
-// localised by probe traversals); PAIR: some material has a pair-production
-// partial (pair events, waiting annihilation photons); ELEC: secondary
-// electrons run CSDA tracks.
-template <bool GRAD, bool SPEC, bool COUNT, bool VOL, bool PAIR, bool ELEC>
+// counters; GEN: the general sources and scenes -- some unit has a volume
+// source (emission points are localised by probe traversals) or a cone
+// source, or a scene with overlays (a second BVH root per region); without it
+// the kernel handles point and beam sources in one-level scenes; PAIR: some
+// material has a pair-production partial (pair events, waiting annihilation
+// photons); ELEC: secondary electrons run CSDA tracks.
+template <bool GRAD, bool SPEC, bool COUNT, bool GEN, bool PAIR, bool ELEC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 transport_kernel(TransportParams P) {
   extern __shared__ unsigned long long smem[];
@@ -162,6 +165,7 @@ transport_kernel(TransportParams P) {
   // to the next unit only when that one is used up, so it rarely has to
   // drain (let its open histories finish) for a change of unit.
   int claim_unit = 0;
+  const int64_t n_w = static_cast<int64_t>(gridDim.x) * nwaves;
   {
     // Workgroups are dealt to the chip's kXcds dies in turn (block b runs on
     // die b % kXcds), and each die has its own L2: number the blocks die by
@@ -171,7 +175,6 @@ transport_kernel(TransportParams P) {
     int64_t blk = blockIdx.x;
     if (gridDim.x % kXcds == 0)
       blk = static_cast<int64_t>(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
-    const int64_t n_w = static_cast<int64_t>(gridDim.x) * nwaves;
     const int64_t gw = blk * nwaves + wave;
     const int64_t x = (gw * total_chunks + total_chunks / 2) / n_w;
     int lo = 0, hi = P.n_units - 1;  // unit u: chunk_begin[u] <= x < chunk_begin[u+1]
@@ -189,6 +192,7 @@ transport_kernel(TransportParams P) {
   int pend = -1;            // claimed chunk waiting for a drain
   int64_t pend_h0 = 0, pend_h1 = 0;
   bool exhausted = false;
+  ClaimBatch claim_batch;
   UnitRec U{};
   SceneRec S{};
   int sp_cap = 0;  // stack capacity of this scene's BVHs, times the stride
@@ -361,7 +365,7 @@ transport_kernel(TransportParams P) {
       dx = Src.dir[0];
       dy = Src.dir[1];
       dz = Src.dir[2];
-    } else if (Src.kind == kCone && Src.cone_cos > -1.0f) {
+    } else if (GEN && Src.kind == kCone && Src.cone_cos > -1.0f) {
       // uniform in the cone about the axis: cos theta uniform in [cone_cos, 1]
       const float ct = fmaf(-rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), 1.0f - Src.cone_cos, 1.0f);
       dx = Src.dir[0];
@@ -402,7 +406,7 @@ transport_kernel(TransportParams P) {
           clk = now;
         }
       };
-      if (VOL && phase == kParked && attempts > 0) {
+      if (GEN && phase == kParked && attempts > 0) {
         // ---- a volume-source point was localised: the region on the near
         // side of the first facet along the probe ray (the world if none)
         const int here = best_id != -1 ? (best_reg >> 8) : 0;
@@ -610,15 +614,12 @@ transport_kernel(TransportParams P) {
           if (next_h >= end_h && pend < 0 && !exhausted) {
             // next chunk of the claim unit, else of the units after it in turn
             for (int t = 0; t < P.n_units; ++t) {
-              unsigned long long c = 0;
-              if (lane == 0) c = atomicAdd(P.cursor + claim_unit, 1ull);
-              c = uniform_u64(__shfl(c, 0, kWave));
-              const int64_t n_chunks = P.chunk_begin[claim_unit + 1] - P.chunk_begin[claim_unit];
-              if (static_cast<int64_t>(c) < n_chunks) {
+              int64_t h1 = 0;
+              const int64_t h0 = claim_histories(P, claim_unit, n_w, lane, claim_batch, h1);
+              if (h0 < h1) {
                 pend = claim_unit;
-                pend_h0 = static_cast<int64_t>(c) * P.chunk;
-                const int64_t nu = P.units[claim_unit].n;
-                pend_h1 = pend_h0 + P.chunk < nu ? pend_h0 + P.chunk : nu;
+                pend_h0 = h0;
+                pend_h1 = h1;
                 break;
               }
               claim_unit = claim_unit + 1 == P.n_units ? 0 : claim_unit + 1;
@@ -713,7 +714,7 @@ transport_kernel(TransportParams P) {
               u2 = u3;
             }
             float qx = Src.dir[0], qy = Src.dir[1], qz = Src.dir[2];
-            if (Src.kind == kCone && Src.cone_cos > -1.0f) {
+            if (GEN && Src.kind == kCone && Src.cone_cos > -1.0f) {
               // the same draws as begin_flight's cone branch
               turn(qx, qy, qz, fmaf(-u0, 1.0f - Src.cone_cos, 1.0f), u1);
               u0 = u2;
@@ -827,7 +828,7 @@ transport_kernel(TransportParams P) {
           } else {
             E = U.energy;
           }
-          if (VOL && Src.kind == kCyl) {
+          if (GEN && Src.kind == kCyl) {
             // rejection sampling: each point is localised by a probe traversal
             attempts = 0;
             phase = kSample;
@@ -847,7 +848,7 @@ transport_kernel(TransportParams P) {
       }
 
       lap(kEv_CycRefill);
-      if (VOL && phase == kSample) {
+      if (GEN && phase == kSample) {
         // next try of a volume-source point
         ++attempts;
         sample_point();
@@ -857,7 +858,7 @@ transport_kernel(TransportParams P) {
       lap(kEv_CycLaunch);
 
       // ---- set up the next segment: attenuation, flight limit, ray
-      if (VOL && phase == kSetup && attempts > 0) {
+      if (GEN && phase == kSetup && attempts > 0) {
         // probe ray of a volume-source point.  The point lies in the source
         // region exactly when the nearest facet along the ray that bounds
         // that region is met from its inside, so only the region's own BVH
@@ -873,7 +874,7 @@ transport_kernel(TransportParams P) {
         tbest = INFINITY;
         trej = INFINITY;
         node = gload(S.roots, Src.region);
-        node2 = S.roots2 ? gload(S.roots2, Src.region) : kDone;
+        node2 = GEN && S.roots2 ? gload(S.roots2, Src.region) : kDone;
         if (node == kDone) {
           node = node2;
           node2 = kDone;
@@ -917,14 +918,14 @@ transport_kernel(TransportParams P) {
             best_reg = 0;
           }
           node = S.outer_root;
-          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
+          node2 = GEN && S.roots2 ? gload(S.roots2, region) : kDone;
           if (!(S.trans_lo[0] <= S.trans_hi[0]) ||
               slab(ray, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0], S.trans_hi[1],
                    S.trans_hi[2], tbest) == INFINITY)
             node = node2 = kDone;  // no inner shell ahead within the flight
         } else {
           node = gload(S.roots, region);
-          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
+          node2 = GEN && S.roots2 ? gload(S.roots2, region) : kDone;
         }
         if (node == kDone) {
           node = node2;
@@ -1032,7 +1033,7 @@ transport_kernel(TransportParams P) {
         }
       }
       if (tri_next >= tri_end && node == kDone && leaf2 == kDone) {
-        if (node2 != kDone) {
+        if (GEN && node2 != kDone) {
           // the second level: same ray, nearest hit so far kept
           node = node2;
           node2 = kDone;
@@ -1215,7 +1216,7 @@ static TK pick_from(int variant, std::integer_sequence<int, V...>) {
   return table[variant];
 }
 
-// variant bits: 1 GRAD, 2 SPEC, 4 COUNT, 8 VOL, 16 PAIR, 32 ELEC
+// variant bits: 1 GRAD, 2 SPEC, 4 COUNT, 8 GEN, 16 PAIR, 32 ELEC
 static TK pick(int variant) { return pick_from(variant & 63, std::make_integer_sequence<int, 64>{}); }
 
 // LDS: per-wavefront tallies, the traversal stacks, and (GRAD) the scores

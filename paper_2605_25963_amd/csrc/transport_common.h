@@ -96,6 +96,63 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) 
   return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// Work claims.  cursor[u] counts the claims made on unit u; claim c of a unit
+// is a fixed range of its histories.  With `guide` = 0 every claim holds
+// `chunk` histories.  Otherwise claims come in batches of B (the number of
+// wavefronts the unit's share of the grid holds), and every claim of a batch
+// takes 1/(guide x B) of the histories the earlier batches left, rounded down
+// to whole wavefronts of histories, until that falls to `chunk` or below;
+// from then on claims hold `chunk` (factoring, Hummel, Schonberg & Flynn
+// 1992).  Claims start large and shrink toward the end of the unit: few
+// device-scope atomics (each one a write past the L2) and a short tail.  The
+// ranges depend on c alone, so the schedule cannot change which histories
+// run.
+//
+// A wavefront keeps the batch its last claim fell in (claims on a unit only
+// grow), so that finding the batch of the next claim takes a step or two.
+struct ClaimBatch {
+  int unit = -1;
+  int64_t k0 = 0;  // first claim of the batch
+  int64_t h = 0;   // its first history
+  int64_t R = 0;   // histories the earlier batches left
+  int64_t s = 0;   // histories per claim of the batch (<= chunk: fixed from here on)
+};
+
+// Returns the first history of the claim on every lane (at or beyond the
+// unit's size once the unit is used up) and its end in h1.
+__device__ __forceinline__ int64_t claim_histories(const TransportParams& P, int u, int64_t n_w,
+                                                   int lane, ClaimBatch& cb, int64_t& h1) {
+  const int64_t nu = P.units[u].n;
+  unsigned long long c = 0;
+  if (lane == 0) c = atomicAdd(P.cursor + u, 1ull);
+  const int64_t k = static_cast<int64_t>(uniform_u64(__shfl(c, 0, kWave)));
+  const int64_t chunk = P.chunk;
+  int64_t h = k * chunk, size = chunk;
+  if (P.guide > 0) {
+    int64_t B = P.total_h > 0 ? n_w * nu / P.total_h : 1;
+    if (B < 1) B = 1;
+    const int64_t D = static_cast<int64_t>(P.guide) * B;
+    if (cb.unit != u) {
+      cb.unit = u;
+      cb.k0 = 0;
+      cb.h = 0;
+      cb.R = nu;
+      cb.s = (nu / D) & ~static_cast<int64_t>(kWave - 1);
+    }
+    while (cb.s > chunk && k - cb.k0 >= B) {
+      cb.h += B * cb.s;
+      cb.R -= B * cb.s;
+      cb.k0 += B;
+      cb.s = (cb.R / D) & ~static_cast<int64_t>(kWave - 1);
+    }
+    if (cb.s > chunk) size = cb.s;
+    h = cb.h + (k - cb.k0) * size;
+  }
+  const int64_t e = h + size;
+  h1 = e < nu ? e : nu;
+  return h;
+}
+
 // Energies in keV (0 <= E < 65536) in units of 2^-16 keV: E * 2^16 is exact in
 // FP32, so rounding it to an integer in FP32 gives the same value as FP64.
 __device__ __forceinline__ unsigned long long fx_kev(float e) {

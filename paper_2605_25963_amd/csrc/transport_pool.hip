@@ -53,9 +53,9 @@ size_t pool_smem(int depth, bool grad, bool pair) {
 }
 
 // GRAD: score-function tallies; SPEC: pulse-height spectra; COUNT: event
-// counters; VOL: some unit has a volume source; PAIR: some material has a
-// pair-production partial.
-template <bool GRAD, bool SPEC, bool COUNT, bool VOL, bool PAIR>
+// counters; GEN: some unit has a volume or cone source, or a scene with
+// overlays; PAIR: some material has a pair-production partial.
+template <bool GRAD, bool SPEC, bool COUNT, bool GEN, bool PAIR>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
 pool_kernel(TransportParams P) {
   // electron tracks need the lane's LDS stack column, which may hold a paused
@@ -96,11 +96,11 @@ pool_kernel(TransportParams P) {
 
   // wave-uniform claim state (as in the per-lane kernel)
   int claim_unit = 0;
+  const int64_t n_w = static_cast<int64_t>(gridDim.x);
   {
     int64_t blk = blockIdx.x;
     if (gridDim.x % kXcds == 0)
       blk = static_cast<int64_t>(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
-    const int64_t n_w = static_cast<int64_t>(gridDim.x);
     const int64_t x = (blk * total_chunks + total_chunks / 2) / n_w;
     int lo = 0, hi = P.n_units - 1;
     while (lo < hi) {
@@ -117,6 +117,7 @@ pool_kernel(TransportParams P) {
   int pend = -1;
   int64_t pend_h0 = 0, pend_h1 = 0;
   bool exhausted = false;
+  ClaimBatch claim_batch;
   UnitRec U{};
   SceneRec S{};
   int sp_cap = 0;
@@ -176,7 +177,7 @@ pool_kernel(TransportParams P) {
     tri_next = static_cast<int>(t >> 3);
     tri_end = tri_next + static_cast<int>(t & 7u);
     leaf2 = static_cast<int>(fld(kF_Leaf2, s));
-    node2 = static_cast<int>(fld(kF_Node2, s));
+    node2 = GEN ? static_cast<int>(fld(kF_Node2, s)) : kDone;
     ray = make_ray(px, py, pz, dx, dy, dz);
   };
   // a finished or paused traversal's state into slot s
@@ -190,7 +191,7 @@ pool_kernel(TransportParams P) {
       fld(kF_Sp, s) = static_cast<uint32_t>(sp);
       fld(kF_Tri, s) = (static_cast<uint32_t>(tri_next) << 3) | static_cast<uint32_t>(tri_end - tri_next);
       fld(kF_Leaf2, s) = static_cast<uint32_t>(leaf2);
-      fld(kF_Node2, s) = static_cast<uint32_t>(node2);
+      if (GEN) fld(kF_Node2, s) = static_cast<uint32_t>(node2);
     }
   };
   // the whole photon of slot s into this lane's registers, and back
@@ -265,7 +266,7 @@ pool_kernel(TransportParams P) {
     fld(kF_Sp, s) = 0u;
     fld(kF_Tri, s) = 0u;
     fld(kF_Leaf2, s) = static_cast<uint32_t>(kDone);
-    fld(kF_Node2, s) = static_cast<uint32_t>(node2);
+    if (GEN) fld(kF_Node2, s) = static_cast<uint32_t>(node2);
   };
   // append the slots of the lanes with `pred` to a ring
   auto push = [&](uint8_t* ring, int head, int& n, bool pred, int s) {
@@ -395,7 +396,7 @@ pool_kernel(TransportParams P) {
       dx = Src.dir[0];
       dy = Src.dir[1];
       dz = Src.dir[2];
-    } else if (Src.kind == kCone && Src.cone_cos > -1.0f) {
+    } else if (GEN && Src.kind == kCone && Src.cone_cos > -1.0f) {
       // uniform in the cone about the axis: cos theta uniform in [cone_cos, 1]
       const float ct = fmaf(-rng_u<COUNT>(g, U.stream, k0, k1, ev[kEv_Rng]), 1.0f - Src.cone_cos, 1.0f);
       dx = Src.dir[0];
@@ -536,7 +537,7 @@ pool_kernel(TransportParams P) {
         }
       }
       // the second level of a two-level scene: same ray, nearest hit kept
-      if (tslot >= 0 && tri_next >= tri_end && node == kDone && leaf2 == kDone && node2 != kDone) {
+      if (GEN && tslot >= 0 && tri_next >= tri_end && node == kDone && leaf2 == kDone && node2 != kDone) {
         node = node2;
         node2 = kDone;
       }
@@ -595,7 +596,7 @@ pool_kernel(TransportParams P) {
           clk = now;
         }
       };
-      if (VOL && phase == kParked && attempts > 0) {
+      if (GEN && phase == kParked && attempts > 0) {
         // ---- a volume-source point was localised: the region on the near
         // side of the first facet along the probe ray (the world if none)
         const int here = best_id != -1 ? (best_reg >> 8) : 0;
@@ -803,15 +804,12 @@ pool_kernel(TransportParams P) {
           if (next_h >= end_h && pend < 0 && !exhausted) {
             // next chunk of the claim unit, else of the units after it in turn
             for (int t = 0; t < P.n_units; ++t) {
-              unsigned long long c = 0;
-              if (lane == 0) c = atomicAdd(P.cursor + claim_unit, 1ull);
-              c = uniform_u64(__shfl(c, 0, kWave));
-              const int64_t n_chunks = P.chunk_begin[claim_unit + 1] - P.chunk_begin[claim_unit];
-              if (static_cast<int64_t>(c) < n_chunks) {
+              int64_t h1 = 0;
+              const int64_t h0 = claim_histories(P, claim_unit, n_w, lane, claim_batch, h1);
+              if (h0 < h1) {
                 pend = claim_unit;
-                pend_h0 = static_cast<int64_t>(c) * P.chunk;
-                const int64_t nu = P.units[claim_unit].n;
-                pend_h1 = pend_h0 + P.chunk < nu ? pend_h0 + P.chunk : nu;
+                pend_h0 = h0;
+                pend_h1 = h1;
                 break;
               }
               claim_unit = claim_unit + 1 == P.n_units ? 0 : claim_unit + 1;
@@ -906,7 +904,7 @@ pool_kernel(TransportParams P) {
               u2 = u3;
             }
             float qx = Src.dir[0], qy = Src.dir[1], qz = Src.dir[2];
-            if (Src.kind == kCone && Src.cone_cos > -1.0f) {
+            if (GEN && Src.kind == kCone && Src.cone_cos > -1.0f) {
               // the same draws as begin_flight's cone branch
               turn(qx, qy, qz, fmaf(-u0, 1.0f - Src.cone_cos, 1.0f), u1);
               u0 = u2;
@@ -1020,7 +1018,7 @@ pool_kernel(TransportParams P) {
           } else {
             E = U.energy;
           }
-          if (VOL && Src.kind == kCyl) {
+          if (GEN && Src.kind == kCyl) {
             // rejection sampling: each point is localised by a probe traversal
             attempts = 0;
             phase = kSample;
@@ -1040,7 +1038,7 @@ pool_kernel(TransportParams P) {
       }
 
       lap(kEv_CycRefill);
-      if (VOL && phase == kSample) {
+      if (GEN && phase == kSample) {
         // next try of a volume-source point
         ++attempts;
         sample_point();
@@ -1050,7 +1048,7 @@ pool_kernel(TransportParams P) {
       lap(kEv_CycLaunch);
 
       // ---- set up the next segment: attenuation, flight limit, ray
-      if (VOL && phase == kSetup && attempts > 0) {
+      if (GEN && phase == kSetup && attempts > 0) {
         // probe ray of a volume-source point.  The point lies in the source
         // region exactly when the nearest facet along the ray that bounds
         // that region is met from its inside, so only the region's own BVH
@@ -1066,7 +1064,7 @@ pool_kernel(TransportParams P) {
         tbest = INFINITY;
         trej = INFINITY;
         node = gload(S.roots, Src.region);
-        node2 = S.roots2 ? gload(S.roots2, Src.region) : kDone;
+        node2 = GEN && S.roots2 ? gload(S.roots2, Src.region) : kDone;
         if (node == kDone) {
           node = node2;
           node2 = kDone;
@@ -1110,14 +1108,14 @@ pool_kernel(TransportParams P) {
             best_reg = 0;
           }
           node = S.outer_root;
-          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
+          node2 = GEN && S.roots2 ? gload(S.roots2, region) : kDone;
           if (!(S.trans_lo[0] <= S.trans_hi[0]) ||
               slab(ray, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0], S.trans_hi[1],
                    S.trans_hi[2], tbest) == INFINITY)
             node = node2 = kDone;  // no inner shell ahead within the flight
         } else {
           node = gload(S.roots, region);
-          node2 = S.roots2 ? gload(S.roots2, region) : kDone;
+          node2 = GEN && S.roots2 ? gload(S.roots2, region) : kDone;
         }
         if (node == kDone) {
           node = node2;

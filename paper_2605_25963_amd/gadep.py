@@ -24,7 +24,7 @@ SRC_POINT, SRC_BEAM, SRC_CYL, SRC_CONE = 0, 1, 2, 3
 
 OPT_MAX_STEPS, OPT_BLOCK, OPT_PERIOD, OPT_CLAIM, OPT_VALIDATE, OPT_MIN_GAP_NM, OPT_GRAPHS, \
     OPT_COUNTERS, OPT_GRID, OPT_EXIT_PLANES, OPT_SPLIT_PCT, OPT_SCREEN, OPT_POOL, \
-    OPT_ELECTRONS = range(1, 15)
+    OPT_ELECTRONS, OPT_GUIDE = range(1, 16)
 
 STATUS = {
     0: "GADEP_OK", -1: "GADEP_E_ARG", -2: "GADEP_E_MESH_OPEN", -3: "GADEP_E_MESH_ORIENT",
@@ -76,7 +76,8 @@ class Counters(C.Structure):
         "segments", "crossings", "node_visits", "tri_tests", "photo", "compton", "coherent",
         "rng_calls", "locates", "emissions", "plane_tests", "iterations", "iterations_node",
         "iterations_facet", "passes", "cycles_outcome", "cycles_refill", "cycles_launch",
-        "cycles_setup", "cycles_traversal", "box_tests", "pair", "electrons")]
+        "cycles_setup", "cycles_traversal", "box_tests", "pair", "electrons", "wavefronts",
+        "wave_cycles")]
 
 
 class Detector(C.Structure):
