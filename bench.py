@@ -64,8 +64,8 @@ KERNEL_SOURCES = ["paper_2605_25963_amd/csrc/transport.hip",
                   "paper_2605_25963_amd/csrc/gadep_internal.h",
                   "paper_2605_25963_amd/csrc/runtime.cpp",
                   "paper_2605_25963_amd/csrc/mesh_prep.cpp"]
-MEASURED_TRAFFIC = {"sources_sha256": "13ae446c4287d4b51986105f3b8fd2c01b842f8209a656d46b33ce1d336a6e41",
-                    "bytes_per_launch": 9.00e7}
+MEASURED_TRAFFIC = {"sources_sha256": "d1bc86f85688a439ed97cefdc753a6818567ec7a9d4e6084901b0db38086af61",
+                    "bytes_per_launch": 6.368e+07}
 
 
 def measured_traffic():
@@ -93,6 +93,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=60.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--guide", type=int, default=None,
+                    help="ablation: GADEP_OPT_GUIDE for the metric workload (0 = fixed claims)")
+    ap.add_argument("--claim", type=int, default=None, help="ablation: GADEP_OPT_CLAIM")
+    ap.add_argument("--split-pct", type=int, default=None,
+                    help="ablation: GADEP_OPT_SPLIT_PCT (transport BVH split budget, %%)")
     ap.add_argument("--quick", action="store_true",
                     help="profiling run: 1e7 histories per energy, no grad, no CPU baseline")
     ap.add_argument("--copy-probe", action="store_true",
@@ -186,6 +191,9 @@ def main():
     distance = 250.0 if a.workload == "c2" else 100.0
     stream = torch.cuda.current_stream()
     ctx = gadep.Context(0, stream if stream.cuda_stream else None)
+    for opt, v in ((gadep.OPT_GUIDE, a.guide), (gadep.OPT_CLAIM, a.claim), (gadep.OPT_SPLIT_PCT, a.split_pct)):
+        if v is not None:
+            ctx.set_option(opt, v)
     m = measure(a, torch, gadep, C, ctx, distance, a.steps, a.warmup, full=True)
     near = None
     if a.workload == "c2" and not a.quick:
@@ -216,7 +224,9 @@ def main():
         "config": {"workload": f"hpge_coaxial_20236_facets_point_{distance:.0f}mm_12_energies",
                    "n_facets": int(len(w.scene.tri)), "energies_keV": [round(e, 3) for e in w.energies],
                    "histories_per_energy": [int(x) for x in m["n_e"]], "histories_per_step": m["total"],
-                   "max_fepe_rse": float(m["rse"].max())},
+                   "max_fepe_rse": float(m["rse"].max()),
+                   **({"ablation": {"guide": a.guide, "claim": a.claim, "split_pct": a.split_pct}}
+                      if (a.guide, a.claim, a.split_pct) != (None, None, None) else {})},
         "fwd_grad_over_fwd": m["fwd_grad_ratio"],
         "batched_grad_vs_single_job": m["batched_vs_single"],
         "fepe": [float(x) for x in m["fepe"]],
@@ -351,6 +361,7 @@ def measure(a, torch, gadep, C, ctx, distance, steps, warmup, full):
     ctx.set_option(gadep.OPT_COUNTERS, 1)
     step()
     ev = ctx.get_counters()
+    count_ms, count_sclk = ctx.get_last_launch_ms(), ctx.get_last_clock_mhz()
     ctx.set_option(gadep.OPT_COUNTERS, 0)
     ops = sum(OPS_PER_EVENT[k] * ev[k] for k in OPS_PER_EVENT)
     # lanes busy per wavefront step: node visits per iteration with a node
@@ -362,15 +373,20 @@ def measure(a, torch, gadep, C, ctx, distance, steps, warmup, full):
     cyc = {k[7:]: ev[k] for k in ev if k.startswith("cycles_")}
     cyc_total = max(sum(cyc.values()), 1)
     lanes["time_share"] = {k: v / cyc_total for k, v in cyc.items()}
+    # share of the counting launch the grid was busy: summed wavefront
+    # lifetimes over wavefronts x launch duration (the rest is the tail)
+    lanes["grid_busy"] = ev["wave_cycles"] / max(ev["wavefronts"] * count_ms * 1e-3 * count_sclk * 1e6, 1.0)
     k_ms = float(np.mean(kernel_ms))
     achieved = ops / (k_ms * 1e-3)
     peak = PEAK_LANE_OPS * (sclk / PEAK_SCLK_MHZ if sclk else 1.0)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
             "unit": "T lane-op/s", "frac": achieved / peak,
-            "traffic": measured_traffic() if distance == 250.0 else None,
+            "traffic": (measured_traffic() if distance == 250.0 and
+                        (a.guide, a.claim, a.split_pct) == (None, None, None) else None),
             "kernel_ms": k_ms, "measured_sclk_mhz": sclk,
             "peak_at_2400_mhz": PEAK_LANE_OPS / 1e12, "ops_per_history": ops / total,
-            "events_per_history": {k: ev[k] / total for k in ev if not k.startswith("cycles_")},
+            "events_per_history": {k: ev[k] / total for k in ev
+                                   if not k.startswith("cycles_") and k not in ("wavefronts", "wave_cycles")},
             "active_lanes": lanes}
     s = k_ms * 1e-3
     rates = {"node_visits_per_s": ev["node_visits"] / s, "facet_tests_per_s": ev["tri_tests"] / s,
