@@ -471,13 +471,65 @@ def bench_c3(a, torch, gadep, C):
         ctx.run_batch([s1], 1003)
         torch.cuda.synchronize()
         singles += time.perf_counter() - t0
+    rates = _rates(ctx, gadep, lambda: ctx.run_batch(spec, 1003), k_ms)
+    ctx.close()
     return _line("histories/s, 64 bottle jobs x 20 energies in one launch", total / dt, "histories/s",
                  a, dt, "c3_64_bottle_overlays_on_256_facet_crystal_20_energies",
                  {"histories_per_step": total, "kernel_ms": k_ms, "sum_of_single_job_launches_s": singles,
                   "batched_over_single_speedup": singles / dt,
                   "autotuned_block_period_claim": list(tuned),
                   "geometry_device_mb_detector_plus_64_overlays": geometry_mb,
-                  "rates": _rates(ctx, gadep, lambda: ctx.run_batch(spec, 1003), k_ms)})
+                  "rates": rates,
+                  "hpge20k_64_overlays": _c3_on_detector(a, torch, gadep, C, jobs)})
+
+
+def _c3_on_detector(a, torch, gadep, C, jobs):
+    """The same 64 bottle jobs (a tenth of their histories) as overlays above the
+    end-cap of the 20236-facet detector: one copy of the detector BVH, one
+    batched launch against one launch per job."""
+    det = C.c2_hpge(n_histories=1).scene
+    mats = ["vacuum", "air", "Al", "Ge", "Cu", "PP", "water", "soil"]
+    tables, grid = C._tables_for(mats, coherent=False)
+    ctx = gadep.Context(0)
+    for m, tab in tables.items():
+        ctx.set_xs(m, grid, *tab)
+    host = det.region_id("air")
+    regions = [(mats.index(r["material"]), float(r["density"]), int(r["group"]),
+                gadep.ACTIVE if r["active"] else 0) for r in det.regions]
+    torch.cuda.synchronize()
+    f0 = torch.cuda.mem_get_info()[0]
+    ctx.load_scene(0, det.xyz, det.tri, det.tri_region, regions)
+    torch.cuda.synchronize()
+    f1 = torch.cuda.mem_get_info()[0]
+    z0 = 5.5 + 2.0  # 2 mm above the end-cap
+    energies = C.log_energies(20)
+    spec = []
+    for k, j in enumerate(jobs):
+        ov = C.bottle_overlay(j["r"], j["h"], z0, j["matrix"], j["density"], group=len(C.HPGE_GROUPS))
+        ctx.load_overlay(1 + k, 0, host, ov.xyz, ov.tri, ov.tri_region, C.overlay_regions(ov, mats))
+        src = C.Source(C.KIND_CYL, pos=(0.0, 0.0, z0 + 1.5), r_in=0.0, r_out=j["r"], h=j["h"],
+                       region=det.n_regions + 1)
+        spec.append(dict(source=src, energies=energies, n_histories=max(1, j["n_total"] // 10 // len(energies)),
+                         scene=1 + k, stream=k))
+    torch.cuda.synchronize()
+    f2 = torch.cuda.mem_get_info()[0]
+    total = sum(s["n_histories"] * len(s["energies"]) for s in spec)
+    tuned = ctx.autotune(spec, 20_000_000)
+    dt, k_ms = _timed(ctx, torch, lambda: ctx.run_batch(spec, 1007), a.steps, a.warmup)
+    singles = 0.0
+    for s1 in spec:
+        ctx.run_batch([s1], 1007)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run_batch([s1], 1007)
+        torch.cuda.synchronize()
+        singles += time.perf_counter() - t0
+    ctx.close()
+    return {"value": total / dt, "unit": "histories/s", "histories_per_step": total, "ms_per_step": dt * 1e3,
+            "kernel_ms": k_ms, "sum_of_single_job_launches_s": singles,
+            "batched_over_single_speedup": singles / dt, "autotuned_block_period_claim": list(tuned),
+            "geometry_device_mb_detector": (f0 - f1) / 1e6,
+            "geometry_device_mb_64_overlays": (f1 - f2) / 1e6}
 
 
 def bench_c4(a, torch, gadep, C):
