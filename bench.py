@@ -190,10 +190,7 @@ def main():
         return
     distance = 250.0 if a.workload == "c2" else 100.0
     stream = torch.cuda.current_stream()
-    ctx = gadep.Context(0, stream if stream.cuda_stream else None)
-    for opt, v in ((gadep.OPT_GUIDE, a.guide), (gadep.OPT_CLAIM, a.claim), (gadep.OPT_SPLIT_PCT, a.split_pct)):
-        if v is not None:
-            ctx.set_option(opt, v)
+    ctx = _ablate(gadep.Context(0, stream if stream.cuda_stream else None), a, gadep)
     m = measure(a, torch, gadep, C, ctx, distance, a.steps, a.warmup, full=True)
     near = None
     if a.workload == "c2" and not a.quick:
@@ -399,6 +396,14 @@ def measure(a, torch, gadep, C, ctx, distance, steps, warmup, full):
 # ---------------------------------------------------------------------------
 # secondary workloads (one JSON line each; not the metric)
 
+def _ablate(ctx, a, gadep):
+    """The ablation options of the command line, set on a new context."""
+    for opt, v in ((gadep.OPT_GUIDE, a.guide), (gadep.OPT_CLAIM, a.claim), (gadep.OPT_SPLIT_PCT, a.split_pct)):
+        if v is not None:
+            ctx.set_option(opt, v)
+    return ctx
+
+
 def _timed(ctx, torch, fn, steps, warmup):
     for i in range(warmup):
         fn()
@@ -441,7 +446,7 @@ def bench_c3(a, torch, gadep, C):
     per job; autotuned block size, park threshold and claim."""
     jobs = C.c3_jobs(64)
     ws = [C.c3_job_workload(j) for j in jobs]
-    ctx = gadep.Context(0)
+    ctx = _ablate(gadep.Context(0), a, gadep)
     w0 = ws[0]
     for m, tab in w0.tables.items():
         ctx.set_xs(m, w0.grid, *tab)
@@ -490,7 +495,7 @@ def _c3_on_detector(a, torch, gadep, C, jobs):
     det = C.c2_hpge(n_histories=1).scene
     mats = ["vacuum", "air", "Al", "Ge", "Cu", "PP", "water", "soil"]
     tables, grid = C._tables_for(mats, coherent=False)
-    ctx = gadep.Context(0)
+    ctx = _ablate(gadep.Context(0), a, gadep)
     for m, tab in tables.items():
         ctx.set_xs(m, grid, *tab)
     host = det.region_id("air")
@@ -534,7 +539,7 @@ def _c3_on_detector(a, torch, gadep, C, jobs):
 
 def bench_c4(a, torch, gadep, C):
     w = C.c4_grad()
-    ctx = gadep.Context(0)
+    ctx = _ablate(gadep.Context(0), a, gadep)
     gadep.load_workload(ctx, w)
     ng = len(w.groups)
     J = [dict(source=w.source, energies=w.energies, n_histories=w.n_histories, stream=0)]
@@ -553,7 +558,7 @@ def bench_c5(a, torch, gadep, C):
     t0 = time.perf_counter()
     w = C.c5_stress()
     t_gen = time.perf_counter() - t0
-    ctx = gadep.Context(0)
+    ctx = _ablate(gadep.Context(0), a, gadep)
     print(f"bench: {len(w.scene.tri)} facets generated", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     gadep.load_workload(ctx, w)
@@ -593,7 +598,7 @@ def bench_c5(a, torch, gadep, C):
 
 
 def bench_build(a, torch, gadep, C):
-    ctx = gadep.Context(0)
+    ctx = _ablate(gadep.Context(0), a, gadep)
     out = {}
     for name, make in (("c1_256", lambda: C.c1_bare()), ("c2_20236", lambda: C.c2_hpge(n_histories=1)),
                        ("c5_962572", lambda: C.c5_stress(n_histories=1))):
