@@ -80,3 +80,33 @@ def test_noalloc_rejects_sizes_beyond_the_scratch(G):
         a = ctx.run_noalloc(w.source, [661.7], 20_000, seed=3)
         b = ctx.run(w.source, [661.7], 20_000, seed=3)
         same(a, b)
+
+
+def test_noalloc_cone_electrons_and_pairs(G):
+    """The other kernel variants through the no-allocation entry: a cone
+    source (general variant, with its weight), electron tracks, and pair
+    production, each equal to gadep_run bit for bit."""
+    w = C.c2_hpge(n_histories=1, distance=100.0)
+    with G.Context(0) as ctx:
+        G.load_workload(ctx, w)
+        cone = C.Source(C.KIND_CONE, pos=w.source.pos)
+        print("noalloc: cone source", flush=True)
+        a = ctx.run_noalloc(cone, [661.7, 1332.5], 200_000, seed=21, spectrum=(4096, 0.5))
+        b = ctx.run(cone, [661.7, 1332.5], 200_000, seed=21, spectrum=(4096, 0.5))
+        same(a, b)
+        assert np.array_equal(a.weights(), b.weights()) and np.all(a.weights() < 1.0)
+        print("noalloc: electron tracks", flush=True)
+        ctx.set_option(G.OPT_ELECTRONS, 1)
+        try:
+            a = ctx.run_noalloc(w.source, [661.7, 2000.0], 200_000, seed=22)
+            b = ctx.run(w.source, [661.7, 2000.0], 200_000, seed=22)
+        finally:
+            ctx.set_option(G.OPT_ELECTRONS, 0)
+        same(a, b)
+        print("noalloc: pair production", flush=True)
+        w.tables, w.grid = C._tables_for(w.materials, coherent=False, pair=True)
+        G.load_workload(ctx, w)
+        a = ctx.run_noalloc(w.source, [2000.0], 200_000, seed=23)
+        b = ctx.run(w.source, [2000.0], 200_000, seed=23)
+        same(a, b)
+        assert a.tallies[0].n_fep > 0
