@@ -49,6 +49,7 @@ OPS_PER_EVENT = {
     "locates": 40,       # probe-ray set-up (its traversal is in node_visits/tri_tests)
     "plane_tests": 13,   # exit plane: two 3-term dot products, reciprocal, product, min
     "box_tests": 30,     # screened history: ray set-up (3 rcp, 3 products) + one slab test
+    "cone_tests": 5,     # screened history: direction against the cone around the inner box
     "pair": 40,          # pair event: deposit, annihilation axis (sqrt, sin, cos), LDS store
 }
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz one-lane-op slots per second

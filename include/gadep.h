@@ -276,7 +276,7 @@ gadep_status gadep_run(gadep_ctx* ctx, const gadep_source* src, const double* en
  * cursors, tally rows and spectra live in one fixed 4 MiB device array per GPU
  * (kept until the process ends); the mesh and cross sections must already be
  * on the device (gadep_load_mesh, gadep_set_xs).  Limits: n_energies <= 256,
- * n_lines <= 256, n_energies * n_channels <= 503328 spectrum words; larger
+ * n_lines <= 256, n_energies * n_channels <= 501280 spectrum words; larger
  * inputs return GADEP_E_ARG.  Like gadep_run it returns when the tallies are
  * in `out`.  Every call on one GPU shares that GPU's array, from any
  * context: calls that overlap in time on one GPU race and must not be made. */
@@ -359,6 +359,9 @@ typedef struct {
    * cycles: over wavefronts x launch duration x shader clock, the share of
    * the launch the grid was busy (the rest is the tail of the work claims) */
   uint64_t wavefronts, wave_cycles;
+  /* screened histories settled by their direction alone (it misses the sphere
+   * around the inner shells' box), without the box test */
+  uint64_t cone_tests;
 } gadep_counters;
 gadep_status gadep_get_counters(const gadep_ctx* ctx, gadep_counters* out);
 

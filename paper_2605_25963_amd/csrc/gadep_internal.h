@@ -133,9 +133,9 @@ enum TallySlot : int {
   // shader clock the launch ran at
   kT_ClkCore, kT_ClkRef,
   kT_Score = 16, kT_FepScore = 24, kT_FepScore2 = 32,
-  kT_Ev = 40,  // event counters, up to 24 slots
-  kT_FepScore2Lo = 64,  // fractions of the FEP score^2 sums (see kScore2Fix)
-  kT_Slots = 72
+  kT_Ev = 40,  // event counters, up to 32 slots
+  kT_FepScore2Lo = 72,  // fractions of the FEP score^2 sums (see kScore2Fix)
+  kT_Slots = 80
 };
 enum EventSlot : int {
   kEv_Segments = 0, kEv_Crossings, kEv_NodeVisits, kEv_TriTests, kEv_Photo, kEv_Compton,
@@ -149,6 +149,9 @@ enum EventSlot : int {
   kEv_BoxTests,
   kEv_Pair,  // pair-production events
   kEv_Electrons,  // electron tracks
+  // screened histories settled by the direction alone: it misses the sphere
+  // around the inner shells' box (no box test)
+  kEv_ConeTests,
   kEv_N
 };
 static_assert(kT_Ev + kEv_N <= kT_FepScore2Lo, "tally slots");

@@ -739,6 +739,7 @@ gadep_status execute(gadep_ctx* ctx, Plan& P, uint64_t seed, gadep_tally* out, d
     cnt.box_tests += ev[kEv_BoxTests];
     cnt.pair += ev[kEv_Pair];
     cnt.electrons += ev[kEv_Electrons];
+    cnt.cone_tests += ev[kEv_ConeTests];
   }
   if (ctx->counters) {
     ctx->last_counters = cnt;

@@ -96,6 +96,54 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) 
   return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// First-flight screening constants of a unit (point or beam source in the
+// outermost shell's region, fixed energy).  No point of the outermost shell
+// is farther from the source than the farthest corner of its box, so a first
+// flight whose optical depth reaches tau (that distance times the outer
+// region's attenuation m, with a margin far above rounding) always ends at the
+// shell.  A direction whose cosine with (ax, ay, az) is below cos misses the
+// sphere around the inner shells' box, so it misses the box as well (radius
+// and cosine widened far beyond rounding; cos = -2: no such test).
+struct ScreenUnit {
+  float tau = INFINITY, far = INFINITY, m = -1.0f;
+  float ax = 0.0f, ay = 0.0f, az = 0.0f, cos = -2.0f;
+};
+
+__device__ __forceinline__ ScreenUnit screen_unit(const SceneRec& S, const SourceRec& Src,
+                                                  const RegionRec& ro, float energy, const float4* xs,
+                                                  int n_e, float ln_e0, float inv_dlne, bool pair) {
+  ScreenUnit su;
+  float d2 = 0.0f;
+  for (int a = 0; a < 3; ++a) {
+    const float e = fmaxf(fabsf(S.outer_lo[a] - Src.pos[a]), fabsf(S.outer_hi[a] - Src.pos[a]));
+    d2 = fmaf(e, e, d2);
+  }
+  su.far = sqrtf(d2) * 1.0001f;
+  float m_p, m_c, m_h;
+  const Xs ixu = xs_index(energy, ln_e0, inv_dlne, n_e);
+  xs_mu(xs, n_e, ro, ixu, m_p, m_c, m_h);
+  su.m = m_p + m_c + m_h + xs_pair(xs, n_e, ro, ixu, energy, pair);
+  su.tau = su.m * su.far * 1.0001f;
+  if (S.trans_lo[0] <= S.trans_hi[0]) {
+    float c[3], r2 = 0.0f, dd = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+      const float h = 0.5f * (S.trans_hi[a] - S.trans_lo[a]);
+      c[a] = 0.5f * (S.trans_hi[a] + S.trans_lo[a]) - Src.pos[a];
+      r2 = fmaf(h, h, r2);
+      dd = fmaf(c[a], c[a], dd);
+    }
+    const float r = sqrtf(r2) * 1.001f + 1e-3f, d = sqrtf(dd);
+    if (d > 1.01f * r) {
+      su.ax = c[0] / d;
+      su.ay = c[1] / d;
+      su.az = c[2] / d;
+      const float sn = r / d;
+      su.cos = sqrtf(1.0f - sn * sn) - 1e-4f;
+    }
+  }
+  return su;
+}
+
 // Work claims.  cursor[u] counts the claims made on unit u; claim c of a unit
 // is a fixed range of its histories.  With `guide` = 0 every claim holds
 // `chunk` histories.  Otherwise claims come in batches of B (the number of

@@ -125,8 +125,7 @@ pool_kernel(TransportParams P) {
   bool screen = false;
   int q_head = 0, q_n = 0;
   int s_head = 0, s_n = 0;
-  float scr_tau = INFINITY, scr_far = INFINITY;
-  float scr_m = -1.0f;
+  ScreenUnit scr;  // the current unit's screening constants
 
   // photon state of a housekeeping lane, and the ray state of a traversing
   // lane (the same registers: a lane does one or the other at a time)
@@ -830,26 +829,10 @@ pool_kernel(TransportParams P) {
               const RegionRec ro = gload(P.regions, U.region_off + S.outer_region);
               screen = P.screen && (U.flags & kUnitExitPlanes) && Src.kind != kCyl &&
                        U.src_region == S.outer_region && (!GRAD || (ro.bits & 0xFF) == 0xFF);
-              scr_tau = scr_far = INFINITY;
-              scr_m = -1.0f;
-              if (screen && Src.n_lines == 0) {
-                // No point of the outermost shell is farther from the source
-                // than the farthest corner of its box, so a flight longer
-                // than that (plus a margin far above rounding) always ends
-                // at the shell: tau >= mu * far.
-                float d2 = 0.0f;
-                for (int a = 0; a < 3; ++a) {
-                  const float e = fmaxf(fabsf(S.outer_lo[a] - Src.pos[a]), fabsf(S.outer_hi[a] - Src.pos[a]));
-                  d2 = fmaf(e, e, d2);
-                }
-                scr_far = sqrtf(d2) * 1.0001f;
-                float m_p, m_c, m_h;
-                const Xs ixu = xs_index(U.energy, P.ln_e0, P.inv_dlne, P.n_e);
-                xs_mu(reinterpret_cast<const float4*>(P.xs), P.n_e, ro, ixu, m_p, m_c, m_h);
-                scr_m = m_p + m_c + m_h +
-                        xs_pair(reinterpret_cast<const float4*>(P.xs), P.n_e, ro, ixu, U.energy, PAIR);
-                scr_tau = scr_m * scr_far * 1.0001f;
-              }
+              scr = ScreenUnit();
+              if (screen && Src.n_lines == 0)
+                scr = screen_unit(S, Src, ro, U.energy, reinterpret_cast<const float4*>(P.xs), P.n_e,
+                                  P.ln_e0, P.inv_dlne, PAIR);
             }
             next_h = pend_h0;
             end_h = pend_h1;
@@ -919,15 +902,21 @@ pool_kernel(TransportParams P) {
             const float tau0 = -hw_log(u0);
             const float ox = Src.pos[0], oy = Src.pos[1], oz = Src.pos[2];
             bool escapes = false;
-            float te = scr_far;
+            float te = scr.far;
             // the flight outlasts the shell (the common case): no need for
-            // the attenuation or the exit distance, only for the box test
-            const bool settled = tau0 >= scr_tau;
+            // the attenuation or the exit distance, only for the box test --
+            // and not even that when the direction misses the sphere around
+            // the box (as in the per-lane kernel)
+            const bool settled = tau0 >= scr.tau;
+            const bool far_off = fmaf(qx, scr.ax, fmaf(qy, scr.ay, qz * scr.az)) < scr.cos;
             if (settled) {
-              escapes = true;
-            } else if (exact || scr_m < 0.0f) {
+              if (far_off || exact)
+                escapes = true;
+              else
+                defer = true;
+            } else if (exact || scr.m < 0.0f) {
               // (with a line spectrum nothing is settled early: no deferral)
-              float m = scr_m;  // the unit's, for a fixed energy
+              float m = scr.m;  // the unit's, for a fixed energy
               if (m < 0.0f) {
                 const RegionRec rr = gload(P.regions, U.region_off + S.outer_region);
                 float m_p, m_c, m_h;
@@ -948,7 +937,7 @@ pool_kernel(TransportParams P) {
             } else {
               defer = true;
             }
-            if (escapes && S.trans_lo[0] <= S.trans_hi[0]) {
+            if (escapes && !far_off && S.trans_lo[0] <= S.trans_hi[0]) {
               const Ray r0 = make_ray(ox, oy, oz, qx, qy, qz);
               escapes = slab(r0, S.trans_lo[0], S.trans_lo[1], S.trans_lo[2], S.trans_hi[0],
                              S.trans_hi[1], S.trans_hi[2], te) == INFINITY;
@@ -962,7 +951,7 @@ pool_kernel(TransportParams P) {
                 ev[kEv_Crossings]++;
                 ev[kEv_Rng]++;
                 if (settled) {
-                  ev[kEv_BoxTests]++;
+                  ev[far_off ? kEv_ConeTests : kEv_BoxTests]++;
                 } else {
                   ev[kEv_Segments]++;
                   ev[kEv_PlaneTests] += S.n_planes;

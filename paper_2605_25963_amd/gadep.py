@@ -77,7 +77,7 @@ class Counters(C.Structure):
         "rng_calls", "locates", "emissions", "plane_tests", "iterations", "iterations_node",
         "iterations_facet", "passes", "cycles_outcome", "cycles_refill", "cycles_launch",
         "cycles_setup", "cycles_traversal", "box_tests", "pair", "electrons", "wavefronts",
-        "wave_cycles")]
+        "wave_cycles", "cone_tests")]
 
 
 class Detector(C.Structure):

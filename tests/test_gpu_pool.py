@@ -17,7 +17,8 @@ FIELDS = ("n_histories", "n_absorbed", "n_fep", "n_escape", "n_uncollided", "n_l
 # event counts that belong to the histories; loop iterations, passes and
 # cycles depend on the schedule
 HISTORY_EVENTS = ("segments", "crossings", "node_visits", "tri_tests", "photo", "compton",
-                  "coherent", "rng_calls", "locates", "emissions", "plane_tests", "box_tests", "pair")
+                  "coherent", "rng_calls", "locates", "emissions", "plane_tests", "box_tests", "pair",
+                  "cone_tests")
 
 
 @pytest.fixture(scope="module")
