@@ -336,7 +336,7 @@ def test_exit_planes_agree_with_facet_exit(G, ctx, orc, where):
         assert sigma3(pg, math.sqrt(pg * (1 - pg) / n), o.fepe(), o.fepe_sigma()), (e, pg, o.fepe())
 
 
-@pytest.mark.parametrize("case", ["point", "lines", "grad", "set_aside"])
+@pytest.mark.parametrize("case", ["point", "lines", "grad", "set_aside", "off_axis", "near"])
 def test_first_flight_screening_is_exact(G, ctx, case):
     # Screening tallies the histories that leave the air box on their first
     # flight without nearing the detector, and repeats the same draws and
@@ -344,10 +344,15 @@ def test_first_flight_screening_is_exact(G, ctx, case):
     # "set_aside": low energies, where air attenuation leaves most first
     # flights too short to settle by the box test alone (they go through the
     # set-aside queue), and one-chunk claims, so that the queue is emptied at
-    # many chunk and unit boundaries.
-    w = C.c2_hpge(n_histories=1)
+    # many chunk and unit boundaries.  Most settled histories are settled by
+    # their direction alone (it misses the sphere around the detector); the
+    # rest take the box test: "off_axis" puts the source off the detector's
+    # axis, "near" inside that sphere, where every settled history takes it.
+    w = C.c2_hpge(n_histories=1, distance=20.0 if case == "near" else 250.0)
     loaded(G, ctx, w)
     src, E = w.source, [60.0, 661.7]
+    if case == "off_axis":
+        src = C.Source(C.KIND_POINT, pos=(130.0, -90.0, 160.0))
     if case == "lines":
         src = C.Source(C.KIND_POINT, pos=w.source.pos, lines_keV=[59.54, 661.66, 1332.5],
                        lines_prob=[0.36, 0.85, 1.0])
@@ -358,6 +363,7 @@ def test_first_flight_screening_is_exact(G, ctx, case):
 
     def run(on):
         ctx.set_option(G.OPT_SCREEN, on)
+        ctx.set_option(G.OPT_COUNTERS, 1)
         if case == "set_aside":
             ctx.set_option(G.OPT_CLAIM, 1)
         try:
@@ -365,12 +371,19 @@ def test_first_flight_screening_is_exact(G, ctx, case):
                 r = ctx.run_grad(src, E, n, 91, scales=[1.0] * len(w.groups))
             else:
                 r = ctx.run(src, E, n, 91, spectrum=(1024, 2.0))
+            c = ctx.get_counters()
         finally:
             ctx.set_option(G.OPT_SCREEN, 1)
+            ctx.set_option(G.OPT_COUNTERS, 0)
             ctx.set_option(G.OPT_CLAIM, 16)
-        return r
+        return r, c
 
-    off, on = run(0), run(1)
+    (off, c_off), (on, c_on) = run(0), run(1)
+    assert c_off["cone_tests"] == 0 and c_off["box_tests"] == 0
+    if case in ("point", "off_axis", "set_aside"):
+        assert c_on["cone_tests"] > 20 * c_on["box_tests"] > 0, (c_on["cone_tests"], c_on["box_tests"])
+    if case in ("lines", "near"):
+        assert c_on["cone_tests"] == 0
     for f in ["n_histories", "n_absorbed", "n_fep", "n_escape", "n_uncollided", "n_lost",
               "n_killed", "n_glitch", "edep_active_keV", "edep_total_keV", "e_escape_keV",
               "e_source_keV"]:
