@@ -140,6 +140,7 @@ def cpu_baseline(w, target_s):
             break
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "per_core": n / dt / threads,
             "sample": f"{rounds} rounds of {per_e} histories at each of the {len(w.energies)} energies "
                       f"({n} total, {dt:.1f} s), same detector and source",
             "host": host_cpu()}
@@ -206,6 +207,8 @@ def main():
         cone = measure_cone(a, torch, gadep, C, ctx, min(a.steps, 5))
     w = m["w"]
     base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
+    if base:
+        base["gpu_over_oracle"] = m["total"] / m["dt"] / base["value"]
     line = {
         "metric": "histories/s on 20k-tri HPGe mesh at <=0.5% FEPE RSE; fwd+grad/fwd cost",
         "value": m["total"] / m["dt"],
