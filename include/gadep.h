@@ -375,7 +375,8 @@ gadep_status gadep_get_last_launch_ms(const gadep_ctx* ctx, double* ms);
  * the shader-clock counter (s_memtime) and the constant-rate counter
  * (s_memrealtime) when it starts and when it ends; the ratio of the summed
  * differences times the constant counter's rate.  For scaling the ALU peak
- * of the roofline to the clock actually sustained. */
+ * of the roofline to the clock actually sustained (the kernel time of Sec.
+ * 3.3 depends on it). */
 gadep_status gadep_get_last_clock_mhz(const gadep_ctx* ctx, double* mhz);
 
 /* Pulse-height spectrum post-processing (the detector resolution the paper
