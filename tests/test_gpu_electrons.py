@@ -96,3 +96,29 @@ def test_detector_with_electrons_matches_oracle(G, orc, pair):
             assert pg < p0 - 3 * sd
         else:
             assert pg < p0 + 3 * sd
+
+
+def test_gradients_with_electron_tracks_match_oracle(G, orc):
+    # the density scales do not shorten the electron tracks (nominal
+    # densities), so the photon's score function stays the estimator of
+    # dFEPE/ds; the oracle with tracks on must agree
+    w = C.c2_hpge(n_histories=1, distance=100.0)
+    s = orc.scene_from_workload(w)
+    s.set_electrons(True)
+    ng, no = 20_000_000, 400_000
+    scales = [1.0] * len(w.groups)
+    E = [1332.5]
+    with G.Context(0) as ctx:
+        G.load_workload(ctx, w)
+        ctx.set_option(G.OPT_ELECTRONS, 1)
+        r = ctx.run_grad(w.source, E, ng, 83, scales)
+    o = s.run(w.source, E[0], no, 3183, scales=scales)
+    t = r.tallies[0]
+    pg, sg = t.n_fep / ng, math.sqrt(t.n_fep) / ng
+    assert abs(pg - o.fepe()) <= 3 * math.hypot(sg, o.fepe_sigma())
+    og, os_ = o.grad(len(scales)), o.grad_sigma(len(scales))
+    for gi, name in enumerate(w.groups):
+        gg, gs = r.grad[0, gi], math.sqrt(r.grad_var[0, gi])
+        print(f"electrons grad {name:8s}: gpu {gg:+.4e} +- {gs:.1e}  oracle {og[gi]:+.4e} +- {os_[gi]:.1e}",
+              flush=True)
+        assert abs(gg - og[gi]) <= 3 * math.hypot(gs, os_[gi]), (name, gg, og[gi])
