@@ -65,7 +65,7 @@ KERNEL_SOURCES = ["paper_2605_25963_amd/csrc/transport.hip",
                   "paper_2605_25963_amd/csrc/gadep_internal.h",
                   "paper_2605_25963_amd/csrc/runtime.cpp",
                   "paper_2605_25963_amd/csrc/mesh_prep.cpp"]
-MEASURED_TRAFFIC = {"sources_sha256": "bd0027053a8fc3b7bbbbb4bdd24456ba2a8d7a9b9451753e072e752c80a354e8",
+MEASURED_TRAFFIC = {"sources_sha256": "5326819c08314fe5d5b4bf7ba552d5e70791894386ea2ab9d3bb5dcc0c158e8f",
                     "bytes_per_launch": 6.133e+07}
 
 

@@ -757,8 +757,8 @@ transport_kernel(TransportParams P) {
               acc_esrc += fx_kev(e);
               acc_eunc += fx_kev(e);
               if (COUNT) {
+                // (leaving the world here takes no crossing step: none is counted)
                 ev[kEv_Emissions]++;
-                ev[kEv_Crossings]++;
                 ev[kEv_Rng]++;
                 if (settled) {
                   ev[far_off ? kEv_ConeTests : kEv_BoxTests]++;
