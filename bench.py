@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=60.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the one-step summaries of the C3, C4 and C5 workloads on the metric line")
     ap.add_argument("--guide", type=int, default=None,
                     help="ablation: GADEP_OPT_GUIDE for the metric workload (0 = fixed claims)")
     ap.add_argument("--claim", type=int, default=None, help="ablation: GADEP_OPT_CLAIM")
@@ -112,6 +114,7 @@ def parse():
     a = ap.parse_args()
     if a.quick:
         a.min_histories, a.pilot, a.no_grad, a.no_cpu_baseline = 1e7, 1e6, True, True
+        a.no_secondary = True
     return a
 
 
@@ -205,6 +208,22 @@ def main():
     cone = None
     if a.workload == "c2" and not a.quick:
         cone = measure_cone(a, torch, gadep, C, ctx, min(a.steps, 5))
+    secondary = None
+    if a.workload == "c2" and not a.no_secondary:
+        # one warm-up and one timed step of each secondary workload, so that
+        # the metric's own run reports them too
+        secondary = {}
+        sa = argparse.Namespace(**vars(a))
+        sa.steps, sa.warmup = 1, 1
+        skip = ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+                "dtype", "data")
+        for name in ("c3", "c4", "c5"):
+            try:
+                r = OTHER[name](sa, torch, gadep, C)
+                secondary[name] = {k: v for k, v in r.items() if k not in skip}
+            except Exception as e:  # a failure here must not cost the metric line
+                secondary[name] = {"error": repr(e)}
+            print(f"bench: secondary workload {name} done", file=sys.stderr, flush=True)
     w = m["w"]
     base = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
     if base:
@@ -235,6 +254,7 @@ def main():
         "roofline": m["roof"],
         "c2_source_100mm": near,
         "cone_emission": cone,
+        "secondary_workloads": secondary,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)
